@@ -1,0 +1,185 @@
+"""TEST INFRASTRUCTURE: the FP64 CPU oracle of the smooth-and-clip finder.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never calls it and it
+never calls the GPU library.
+
+``sc_oracle.cpp`` is the oracle proper (C++17, FP64, direct summation);
+``brute.py`` is an independent dense-matrix formulation used to pin it on tiny
+cubes. Citations are to Westmeier et al. 2021 (arXiv:2106.15789).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsc_oracle.so")
+# Tests that plant mistakes in a copy of the oracle point this at the copy.
+_LIB_OVERRIDE = os.environ.get("SC_ORACLE_LIB")
+_lib = None
+
+NOISE = {"std": 0, "mad": 1}
+RANGE = {"negative": -1, "all": 0, "positive": 1}
+ENOSTAT = -4
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with g++ -O2 -fopenmp (no fast-math: IEEE FP64)."""
+    import subprocess
+    src = os.path.join(_HERE, "sc_oracle.cpp")
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+           "-ffp-contract=off", src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if _LIB_OVERRIDE:
+            return _bind(ctypes.CDLL(_LIB_OVERRIDE))
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: run __graft_entry__.build() first")
+        return _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _bind(lib):
+    global _lib
+    i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    lib.sco_plan.argtypes = [dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sco_smooth.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, vp]
+    lib.sco_noise.argtypes = [vp, i64, i32, i32, ctypes.POINTER(dbl),
+                              ctypes.POINTER(i64)]
+    lib.sco_step.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, dbl,
+                             i32, i32, vp, ctypes.POINTER(dbl), vp,
+                             ctypes.POINTER(i64)]
+    lib.sco_run.argtypes = [vp, i64, i64, i64, vp, vp, i32, dbl, i32, i32,
+                            dbl, vp, vp, ctypes.POINTER(dbl), vp, vp]
+    for f in (lib.sco_plan, lib.sco_smooth, lib.sco_noise, lib.sco_step,
+              lib.sco_run):
+        f.restype = ctypes.c_int
+    _lib = lib
+    return _lib
+
+
+def _cube(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    if x.ndim != 3:
+        raise ValueError("cube must be 3-D [nz][ny][nx]")
+    return x
+
+
+def _mask_in(m: Optional[np.ndarray], shape) -> Optional[np.ndarray]:
+    if m is None:
+        return None
+    m = np.ascontiguousarray(m, dtype=np.uint8)
+    if m.shape != shape:
+        raise ValueError("mask shape mismatch")
+    return m
+
+
+def plan(fwhm: float) -> Tuple[int, int]:
+    """(n_iter, radius) of the boxcar cascade for a spatial FWHM (reading R1)."""
+    n, r = ctypes.c_int32(), ctypes.c_int32()
+    if _load().sco_plan(float(fwhm), ctypes.byref(n), ctypes.byref(r)) != 0:
+        raise ValueError("bad FWHM %r" % fwhm)
+    return n.value, r.value
+
+
+def smooth(cube: np.ndarray, fwhm: float, width: int,
+           mask_prev: Optional[np.ndarray] = None, repl: float = -1.0,
+           sigma0: float = float("nan")) -> np.ndarray:
+    """Smoothed cube s (FP64, NaN where the input is blanked)."""
+    x = _cube(cube)
+    m = _mask_in(mask_prev, x.shape)
+    out = np.empty(x.shape, dtype=np.float64)
+    nz, ny, nx = x.shape
+    rc = _load().sco_smooth(x.ctypes.data, nx, ny, nz,
+                            None if m is None else m.ctypes.data,
+                            float(repl), float(sigma0), float(fwhm), int(width),
+                            out.ctypes.data)
+    if rc != 0:
+        raise ValueError("sco_smooth failed (%d)" % rc)
+    return out
+
+
+def noise(values: np.ndarray, mode: str, flux_range: str) -> Tuple[float, int]:
+    """(sigma, number of selected voxels) of an FP64 array; NaN = blanked."""
+    v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+    s, m = ctypes.c_double(), ctypes.c_int64()
+    rc = _load().sco_noise(v.ctypes.data, v.size, NOISE[mode], RANGE[flux_range],
+                           ctypes.byref(s), ctypes.byref(m))
+    if rc not in (0, ENOSTAT):
+        raise ValueError("sco_noise failed (%d)" % rc)
+    return s.value, m.value
+
+
+@dataclass
+class StepResult:
+    mask: np.ndarray
+    sigma: float
+    band: np.ndarray
+    band_count: int
+    status: int
+
+
+def step(cube: np.ndarray, fwhm: float, width: int, threshold: float,
+         mode: str, flux_range: str, mask_prev: Optional[np.ndarray] = None,
+         repl: float = -1.0, sigma0: float = float("nan")) -> StepResult:
+    """One S+C iteration (teacher-forcing unit): mask_prev OR new detections."""
+    x = _cube(cube)
+    m = _mask_in(mask_prev, x.shape)
+    nz, ny, nx = x.shape
+    out = np.empty(x.shape, dtype=np.uint8)
+    band = np.zeros(x.shape, dtype=np.uint8)
+    sig, nb = ctypes.c_double(), ctypes.c_int64()
+    rc = _load().sco_step(x.ctypes.data, nx, ny, nz,
+                          None if m is None else m.ctypes.data, float(repl),
+                          float(sigma0), float(fwhm), int(width), float(threshold),
+                          NOISE[mode], RANGE[flux_range], out.ctypes.data,
+                          ctypes.byref(sig), band.ctypes.data, ctypes.byref(nb))
+    if rc not in (0, ENOSTAT):
+        raise ValueError("sco_step failed (%d)" % rc)
+    return StepResult(out, sig.value, band, nb.value, rc)
+
+
+@dataclass
+class RunResult:
+    mask: np.ndarray
+    sigma: np.ndarray
+    sigma0: float
+    band: np.ndarray
+    band_count: np.ndarray
+    status: int
+
+
+def run(cube: np.ndarray, kernels: Sequence[Tuple[float, int]], threshold: float,
+        mode: str, flux_range: str, repl: float = 2.0) -> RunResult:
+    """Whole S+C run over the kernel list, in list order."""
+    x = _cube(cube)
+    nz, ny, nx = x.shape
+    K = len(kernels)
+    f = np.array([k[0] for k in kernels], dtype=np.float64)
+    w = np.array([k[1] for k in kernels], dtype=np.int32)
+    mask = np.empty(x.shape, dtype=np.uint8)
+    band = np.empty(x.shape, dtype=np.uint8)
+    sig = np.full(K, np.nan)
+    bc = np.zeros(K, dtype=np.int64)
+    s0 = ctypes.c_double()
+    rc = _load().sco_run(x.ctypes.data, nx, ny, nz, f.ctypes.data, w.ctypes.data,
+                         K, float(threshold), NOISE[mode], RANGE[flux_range],
+                         float(repl), mask.ctypes.data, sig.ctypes.data,
+                         ctypes.byref(s0), band.ctypes.data, bc.ctypes.data)
+    if rc not in (0, ENOSTAT):
+        raise ValueError("sco_run failed (%d)" % rc)
+    return RunResult(mask, sig, s0.value, band, bc, rc)

@@ -1,0 +1,183 @@
+"""Seeded synthetic H I cubes shared by the oracle tests, GPU tests and bench.
+
+Holds no smooth-and-clip arithmetic: it only draws noise and mock galaxies
+(see ``gen.c``) and names the workload recipes. The paper's cubes (a WSRT
+cube with WHISP galaxies, ASKAP Eridanus noise with galmod mocks, the
+WALLABY Hydra field; Sects. 5-7) are not available, so these stand in for
+them with the shapes and settings of the benchmark workloads.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+        ("seed", ctypes.c_uint64), ("cube_id", ctypes.c_uint32),
+        ("field_kind", ctypes.c_int32),
+        ("sigma_lo", ctypes.c_double), ("sigma_hi", ctypes.c_double),
+        ("n_gal", ctypes.c_int64), ("nan_border", ctypes.c_int64),
+        ("peak_lo", ctypes.c_double), ("peak_hi", ctypes.c_double),
+        ("fwhm_z_lo", ctypes.c_double), ("fwhm_z_hi", ctypes.c_double),
+        ("fwhm_xy_lo", ctypes.c_double), ("fwhm_xy_hi", ctypes.c_double),
+        ("z0", ctypes.c_int64), ("z1", ctypes.c_int64),
+    ]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile gen.c into libsynth.so (gcc, OpenMP)."""
+    import subprocess
+    src = os.path.join(_HERE, "gen.c")
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", src,
+           "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(
+                f"{_LIB_PATH} is missing: run __graft_entry__.build() first")
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.synth_cube.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p]
+        lib.synth_cube.restype = ctypes.c_int
+        lib.synth_sigma_field.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p]
+        lib.synth_sigma_field.restype = ctypes.c_int
+        lib.synth_philox4x32_10.argtypes = [
+            ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32, ctypes.c_uint32,
+            ctypes.POINTER(ctypes.c_uint32)]
+        lib.synth_philox4x32_10.restype = None
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class CubeSpec:
+    """Recipe for one synthetic cube (float32, [nz][ny][nx])."""
+    nx: int
+    ny: int
+    nz: int
+    seed: int
+    cube_id: int = 0
+    radial: bool = False          # sigma grows as rho^2 from the centre
+    sigma_lo: float = 1.0
+    sigma_hi: float = 1.0
+    n_gal: int = 0
+    nan_border: int = 0
+    peak: Tuple[float, float] = (0.5, 3.0)       # x local sigma
+    fwhm_z: Tuple[float, float] = (5.0, 20.0)    # channels
+    fwhm_xy: Tuple[float, float] = (4.0, 12.0)   # pixels
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def n_vox(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def _params(self, z0: int = 0, z1: int = 0) -> _Params:
+        return _Params(
+            self.nx, self.ny, self.nz, self.seed, self.cube_id,
+            1 if self.radial else 0, self.sigma_lo, self.sigma_hi,
+            self.n_gal, self.nan_border, self.peak[0], self.peak[1],
+            self.fwhm_z[0], self.fwhm_z[1], self.fwhm_xy[0], self.fwhm_xy[1],
+            z0, z1)
+
+
+def generate(spec: CubeSpec, out: Optional[np.ndarray] = None,
+             z0: int = 0, z1: int = 0) -> np.ndarray:
+    """Generate the cube (or planes [z0, z1)) as float32 [nz][ny][nx]."""
+    lib = _load()
+    z1 = z1 or spec.nz
+    shape = (z1 - z0, spec.ny, spec.nx)
+    if out is None:
+        out = np.empty(shape, dtype=np.float32)
+    if out.shape != shape or out.dtype != np.float32 or not out.flags.c_contiguous:
+        raise ValueError("out must be a C-contiguous float32 array of shape %r" % (shape,))
+    p = spec._params(z0, z1)
+    rc = lib.synth_cube(ctypes.byref(p), out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("synth_cube failed (%d)" % rc)
+    return out
+
+
+def sigma_field(spec: CubeSpec) -> np.ndarray:
+    lib = _load()
+    out = np.empty((spec.ny, spec.nx), dtype=np.float64)
+    p = spec._params()
+    if lib.synth_sigma_field(ctypes.byref(p), out.ctypes.data) != 0:
+        raise RuntimeError("synth_sigma_field failed")
+    return out
+
+
+def philox4x32_10(ctr, key):
+    """Raw Philox4x32-10 block (for the generator's known-answer test)."""
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    o = (ctypes.c_uint32 * 4)()
+    lib.synth_philox4x32_10(c, key[0], key[1], o)
+    return [int(v) for v in o]
+
+
+# --------------------------------------------------------------------------
+# Workload recipes. Kernel lists are (spatial FWHM px, spectral width ch),
+# spatial-major, as in the paper's benchmark settings (Sect. 5).
+
+@dataclass
+class Workload:
+    name: str
+    cubes: List[CubeSpec]
+    kernels: List[Tuple[float, int]]
+    threshold: float
+    noise_mode: str            # "std" | "mad"
+    flux_range: str            # "negative" | "all" | "positive"
+    replacement: float = 2.0   # n in +-n*sigma0 (Sect. 6.2.4); < 0 disables
+    notes: str = ""
+
+
+def _pairs(spatial, spectral):
+    return [(float(f), int(w)) for f in spatial for w in spectral]
+
+
+def workload(name: str) -> Workload:
+    """Named workloads (shapes and settings of the benchmark configurations)."""
+    if name == "plain_64x64x128":
+        return Workload(
+            name, [CubeSpec(64, 64, 128, seed=1, n_gal=5)],
+            _pairs([0, 3], [0, 3, 7]), 4.0, "std", "all",
+            notes="i.i.d. sigma=1 noise, 5 blobs; flux range not stated -> all")
+    if name == "plain_1024cube":
+        return Workload(
+            name, [CubeSpec(1024, 1024, 1024, seed=2, radial=True, sigma_lo=0.8,
+                            sigma_hi=1.5, n_gal=2000, nan_border=13)],
+            _pairs([0, 3, 6], [0, 3, 7, 15]), 3.5, "mad", "negative")
+    if name == "plain_256cube":
+        # Same recipe as plain_1024cube at 1/64 of the volume (galaxy density
+        # kept); sized for the CPU oracle.
+        return Workload(
+            name, [CubeSpec(256, 256, 256, seed=2, radial=True, sigma_lo=0.8,
+                            sigma_hi=1.5, n_gal=31, nan_border=4)],
+            _pairs([0, 3, 6], [0, 3, 7, 15]), 3.5, "mad", "negative")
+    if name == "paper_360x360x1464":
+        return Workload(
+            name, [CubeSpec(360, 360, 1464, seed=7, n_gal=40)],
+            _pairs([0, 5, 10], [0, 3, 7, 15]), 3.5, "mad", "negative",
+            notes="shape and kernels of the paper's laptop speed test (Sect. 5)")
+    raise KeyError(name)
