@@ -1,0 +1,166 @@
+/*
+ * sofia_sc.h -- C ABI of the MI355X smooth-and-clip (S+C) source finder.
+ *
+ * S+C is the default source finder of SoFiA 2 (Westmeier et al. 2021,
+ * arXiv:2106.15789, Sect. 4.2): the cube is smoothed with a list of spatial x
+ * spectral kernels; after each smoothing the noise of the smoothed cube is
+ * measured and every voxel whose absolute value exceeds threshold x noise is
+ * added to one binary mask (positive and negative excursions alike, Sect. 4.2).
+ * Before each smoothing, voxels already in the mask are replaced by +-n times
+ * the noise of the input, keeping their sign (Sect. 6.2.4, default n = 2).
+ * Spatial kernels are Gaussians given by FWHM in pixels, spectral kernels are
+ * boxcars given by width in channels (Fig. 9 caption; kernel sets in Sects. 5
+ * and 6). The robust noise is 1.4826 x the median absolute value (the MAD
+ * estimator of Sect. 4.1, taken about zero).
+ *
+ * Conventions for every entry point:
+ *  - Cubes are float32 [nz][ny][nx] (x fastest, z = spectral axis slowest),
+ *    dense and contiguous. Masks are uint8 of the same shape: 1 = detected,
+ *    0 = not detected. Non-finite voxels are "blanked": they count as 0 in the
+ *    smoothing, never enter the noise and are never detected.
+ *  - Pointers named cube/mask/out are DEVICE pointers on the handle's device;
+ *    pointers named noise/sigma0/stats are HOST pointers. The caller owns all
+ *    of them; the library keeps none after the call returns.
+ *  - Work is enqueued on the given stream (NULL = the null stream); calls
+ *    return after the work has completed, since results land in host memory.
+ *  - Return 0 on success or a negative SOFIA_SC_E* code. On error every
+ *    host noise value is set to NaN, sofia_sc_last_error() describes the
+ *    cause and the handle stays usable.
+ *  - A handle is not thread-safe: use one handle per host thread.
+ */
+#ifndef SOFIA_SC_H
+#define SOFIA_SC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sofia_sc sofia_sc;
+
+/* One smoothing kernel. spatial_fwhm_px = 0 means no spatial smoothing;
+ * otherwise the Gaussian is built as a cascade of n boxcars of width 2r+1
+ * along x and then along y (see sofia_sc_plan). spectral_width_ch = 0 or 1
+ * means no spectral smoothing; other widths must be odd and >= 3. */
+typedef struct {
+    double spatial_fwhm_px;
+    int32_t spectral_width_ch;
+} sofia_sc_kernel;
+
+enum { SOFIA_SC_NOISE_STD = 0, SOFIA_SC_NOISE_MAD = 1 };
+enum { SOFIA_SC_FLUX_NEGATIVE = -1, SOFIA_SC_FLUX_ALL = 0, SOFIA_SC_FLUX_POSITIVE = 1 };
+
+enum {
+    SOFIA_SC_OK = 0,
+    SOFIA_SC_EINVAL = -1,   /* bad argument (see each entry point) */
+    SOFIA_SC_ENOMEM = -2,   /* device allocation failed */
+    SOFIA_SC_EDEVICE = -3,  /* HIP error; text via sofia_sc_last_error */
+    SOFIA_SC_ENOSTAT = -4   /* a noise had no finite voxel in its flux range:
+                               that noise is NaN and the mask is undefined */
+};
+
+/* Limits of this build. */
+#define SOFIA_SC_MAX_KERNELS 64
+#define SOFIA_SC_MAX_HALO 16        /* n * r of the spatial cascade */
+#define SOFIA_SC_MAX_WIDTH 63       /* spectral boxcar width */
+
+typedef struct {
+    uint32_t struct_size;   /* = sizeof(sofia_sc_options) */
+    double replacement;     /* n of +-n sigma_0 (Sect. 6.2.4); < 0 disables
+                               replacement; default 2.0 */
+    void *stream;           /* hipStream_t to run on; NULL = null stream */
+} sofia_sc_options;
+
+/* Fill opt with defaults (replacement 2.0, null stream). */
+void sofia_sc_default_options(sofia_sc_options *opt);
+
+/* Create a handle on a HIP device. The handle owns all device workspace
+ * (working masks, smoothed-plane buffer, histograms); workspace grows on
+ * demand and is released by sofia_sc_destroy. EINVAL for a bad ordinal. */
+int sofia_sc_create(sofia_sc **out, int device_ordinal);
+
+/* Release a handle and its workspace. NULL is a no-op. */
+void sofia_sc_destroy(sofia_sc *h);
+
+/* Whole S+C run (Sect. 4.2) over n_kernels kernels, in list order.
+ *  cube       device, float32 [nz][ny][nx], read only.
+ *  kernels    host array of n_kernels (1..SOFIA_SC_MAX_KERNELS).
+ *  threshold  t > 0: a voxel is detected when |s| > t * noise_k.
+ *  noise_mode SOFIA_SC_NOISE_STD (RMS about zero) or SOFIA_SC_NOISE_MAD.
+ *  flux_range which smoothed voxels enter the noise: NEGATIVE (s < 0),
+ *             ALL (every finite s) or POSITIVE (s > 0).
+ *  mask       device, uint8 [nz][ny][nx], fully overwritten with 0/1.
+ *  noise      host, double[n_kernels]: the noise of each smoothed cube.
+ * Uses the default options. EINVAL: NULL pointer, a dimension < 1,
+ * nx*ny*nz > 2^40, bad kernel (FWHM < 0 or non-finite, halo above
+ * SOFIA_SC_MAX_HALO, even or too large width), bad threshold or enum. */
+int sofia_sc_run(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                 int64_t nz, const sofia_sc_kernel *kernels, int32_t n_kernels,
+                 double threshold, int32_t noise_mode, int32_t flux_range,
+                 uint8_t *mask, double *noise);
+
+/* sofia_sc_run with options. sigma0 (host, may be NULL) receives the noise
+ * of the unsmoothed input that replacement uses (NaN when replacement is
+ * off). EINVAL also for opt == NULL or a struct_size mismatch. */
+int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                    int64_t nz, const sofia_sc_kernel *kernels,
+                    int32_t n_kernels, double threshold, int32_t noise_mode,
+                    int32_t flux_range, uint8_t *mask, double *noise,
+                    const sofia_sc_options *opt, double *sigma0);
+
+/* One S+C iteration with the previous state given (Sect. 4.2 and 6.2.4):
+ * smooth the cube after replacing the voxels set in mask_in by
+ * copysign(replacement * sigma0, x) (skipped when replacement < 0), measure
+ * the noise, and write mask_out = mask_in OR (|s| > t * noise).
+ *  mask_in    device, uint8 0/1 (may be NULL: no previous detections).
+ *  mask_out   device, uint8, fully overwritten; must not alias mask_in.
+ *  noise      host, double[1].
+ *  stream     hipStream_t or NULL. */
+int sofia_sc_step(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                  int64_t nz, sofia_sc_kernel kernel, double threshold,
+                  int32_t noise_mode, int32_t flux_range, double replacement,
+                  double sigma0, const uint8_t *mask_in, uint8_t *mask_out,
+                  double *noise, void *stream);
+
+/* The smoothed cube s of one kernel, as float32 (NaN at blanked voxels),
+ * with replacement applied as in sofia_sc_step. out: device, float32
+ * [nz][ny][nx]. For inspection and tests; S+C itself never stores s. */
+int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                    int64_t nz, sofia_sc_kernel kernel, double replacement,
+                    double sigma0, const uint8_t *mask_in, float *out,
+                    void *stream);
+
+/* Spatial cascade for a FWHM: n_iter boxcars of radius r per axis, chosen to
+ * match the Gaussian variance, sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2, with
+ * n_iter r (r+1) / 3 (n_iter in 3..6, r >= 1; ties go to the larger n_iter).
+ * FWHM 0 gives (0, 0). EINVAL for FWHM < 0 or non-finite. No device work. */
+int sofia_sc_plan(double spatial_fwhm_px, int32_t *n_iter, int32_t *radius);
+
+/* Per-kernel timing of the GPU launches, collected with HIP events on the
+ * launch stream while profiling is enabled. */
+typedef struct {
+    char name[40];          /* kernel family, e.g. "spatial_cascade" */
+    int64_t launches;
+    double total_ms;        /* sum of event-measured launch durations */
+    double bytes;           /* algorithmic HBM bytes summed over launches */
+    double voxels;          /* voxels processed, summed over launches */
+} sofia_sc_kernel_stat;
+
+/* enable = 1 starts collecting (and clears previous figures), 0 stops. */
+int sofia_sc_profile(sofia_sc *h, int enable);
+
+/* Copy up to cap entries into stats; *n_out gets the number of families. */
+int sofia_sc_profile_read(const sofia_sc *h, sofia_sc_kernel_stat *stats,
+                          int32_t cap, int32_t *n_out);
+
+/* Last error text of this handle ("" if none). Valid until the next call. */
+const char *sofia_sc_last_error(const sofia_sc *h);
+
+/* Static text for an error code. */
+const char *sofia_sc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOFIA_SC_H */

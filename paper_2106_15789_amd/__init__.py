@@ -1,0 +1,271 @@
+"""MI355X smooth-and-clip (S+C) source finder: Python binding of libsofia_sc.so.
+
+The work runs in the HIP kernels behind the C ABI of ``include/sofia_sc.h``;
+this module only marshals arguments (torch tensors give device memory and
+streams) and fails loudly when the library is missing. Method: SoFiA 2's S+C
+finder, Westmeier et al. 2021 (arXiv:2106.15789), Sect. 4.2 and 6.2.4.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libsofia_sc.so")
+HEADER = os.path.join(ROOT, "include", "sofia_sc.h")
+SOURCES = [os.path.join(_HERE, "csrc", "sc_kernels.hip"),
+           os.path.join(_HERE, "csrc", "sc_api.hip")]
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
+NOISE = {"std": 0, "mad": 1}
+RANGE = {"negative": -1, "all": 0, "positive": 1}
+
+# Every symbol include/sofia_sc.h declares.
+EXPORTS = [
+    "sofia_sc_default_options", "sofia_sc_create", "sofia_sc_destroy",
+    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step", "sofia_sc_smooth",
+    "sofia_sc_plan", "sofia_sc_profile", "sofia_sc_profile_read",
+    "sofia_sc_last_error", "sofia_sc_strerror",
+]
+
+
+def hipcc_command(out: str) -> List[str]:
+    return ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17",
+            "-fPIC", "-shared",
+            # packed FP32 instructions stay off (see the design notes)
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I" + os.path.join(ROOT, "include"), *SOURCES, "-o", out]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the HIP library for gfx950 (cross-compiles without a GPU)."""
+    tmp = LIB_PATH + ".tmp"
+    cmd = hipcc_command(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("spatial_fwhm_px", ctypes.c_double),
+                ("spectral_width_ch", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32),
+                ("replacement", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("voxels", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libsofia_sc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with __graft_entry__.build(); "
+            "there is no fallback implementation")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    lib.sofia_sc_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.sofia_sc_default_options.restype = None
+    lib.sofia_sc_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.sofia_sc_destroy.argtypes = [vp]
+    lib.sofia_sc_destroy.restype = None
+    lib.sofia_sc_run.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(Kernel), i32,
+                                 dbl, i32, i32, vp, ctypes.POINTER(dbl)]
+    lib.sofia_sc_run_ex.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(Kernel), i32,
+                                    dbl, i32, i32, vp, ctypes.POINTER(dbl),
+                                    ctypes.POINTER(Options), ctypes.POINTER(dbl)]
+    lib.sofia_sc_step.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, dbl,
+                                  dbl, vp, vp, ctypes.POINTER(dbl), vp]
+    lib.sofia_sc_smooth.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, dbl, vp, vp, vp]
+    lib.sofia_sc_plan.argtypes = [dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sofia_sc_profile.argtypes = [vp, ctypes.c_int]
+    lib.sofia_sc_profile_read.argtypes = [vp, ctypes.POINTER(KernelStat), i32,
+                                          ctypes.POINTER(i32)]
+    lib.sofia_sc_last_error.argtypes = [vp]
+    lib.sofia_sc_last_error.restype = ctypes.c_char_p
+    lib.sofia_sc_strerror.argtypes = [ctypes.c_int]
+    lib.sofia_sc_strerror.restype = ctypes.c_char_p
+    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step",
+                 "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_profile",
+                 "sofia_sc_profile_read"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class ScError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def plan(fwhm: float) -> Tuple[int, int]:
+    """(n_iter, radius) of the spatial boxcar cascade for a FWHM."""
+    n, r = ctypes.c_int32(), ctypes.c_int32()
+    rc = load().sofia_sc_plan(float(fwhm), ctypes.byref(n), ctypes.byref(r))
+    if rc != OK:
+        raise ScError(rc, "bad spatial FWHM")
+    return n.value, r.value
+
+
+def _kernels(kernels: Sequence[Tuple[float, int]]):
+    arr = (Kernel * len(kernels))()
+    for i, (f, w) in enumerate(kernels):
+        arr[i].spatial_fwhm_px = float(f)
+        arr[i].spectral_width_ch = int(w)
+    return arr
+
+
+def _check_cube(cube):
+    import torch
+    if not (isinstance(cube, torch.Tensor) and cube.is_cuda and cube.dtype == torch.float32
+            and cube.dim() == 3 and cube.is_contiguous()):
+        raise ValueError("cube must be a contiguous 3-D float32 CUDA tensor [nz][ny][nx]")
+    nz, ny, nx = cube.shape
+    return nx, ny, nz
+
+
+def _check_like(t, cube, dtype, what):
+    """A caller-supplied mask/output must match the cube's shape and device."""
+    import torch
+    if t is None:
+        return
+    if not (isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_contiguous()
+            and t.shape == cube.shape and t.device == cube.device):
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor shaped like the cube")
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+class SofiaSC:
+    """A library handle bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.h = ctypes.c_void_p()
+        rc = self.lib.sofia_sc_create(ctypes.byref(self.h), int(device))
+        if rc != OK:
+            raise ScError(rc, "sofia_sc_create failed: " +
+                          self.lib.sofia_sc_strerror(rc).decode())
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.sofia_sc_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, rc: int, what: str):
+        msg = self.lib.sofia_sc_last_error(self.h).decode()
+        raise ScError(rc, f"{what}: {msg or self.lib.sofia_sc_strerror(rc).decode()}")
+
+    def run(self, cube, kernels, threshold: float, noise_mode: str = "mad",
+            flux_range: str = "negative", replacement: float = 2.0, mask=None,
+            stream=None, allow_nostat: bool = False):
+        """Whole S+C run. Returns (mask uint8 tensor, noise[K] ndarray, sigma0)."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        _check_like(mask, cube, torch.uint8, "mask")
+        if mask is None:
+            mask = torch.empty(cube.shape, dtype=torch.uint8, device=cube.device)
+        K = len(kernels)
+        noise = (ctypes.c_double * K)()
+        s0 = ctypes.c_double()
+        opt = Options()
+        self.lib.sofia_sc_default_options(ctypes.byref(opt))
+        opt.replacement = float(replacement)
+        opt.stream = _stream_ptr(stream)
+        rc = self.lib.sofia_sc_run_ex(self.h, cube.data_ptr(), nx, ny, nz,
+                                      _kernels(kernels), K, float(threshold),
+                                      NOISE[noise_mode], RANGE[flux_range],
+                                      mask.data_ptr(), noise, ctypes.byref(opt),
+                                      ctypes.byref(s0))
+        if rc != OK and not (allow_nostat and rc == ENOSTAT):
+            self._raise(rc, "sofia_sc_run_ex")
+        return mask, np.array(noise[:], dtype=np.float64), s0.value
+
+    def step(self, cube, kernel, threshold: float, noise_mode: str, flux_range: str,
+             replacement: float = 2.0, sigma0: float = float("nan"), mask_in=None,
+             mask_out=None, stream=None, allow_nostat: bool = False):
+        """One S+C iteration from a given state. Returns (mask_out, noise)."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        _check_like(mask_in, cube, torch.uint8, "mask_in")
+        _check_like(mask_out, cube, torch.uint8, "mask_out")
+        if mask_out is None:
+            mask_out = torch.empty(cube.shape, dtype=torch.uint8, device=cube.device)
+        noise = ctypes.c_double()
+        k = Kernel(float(kernel[0]), int(kernel[1]))
+        rc = self.lib.sofia_sc_step(self.h, cube.data_ptr(), nx, ny, nz, k,
+                                    float(threshold), NOISE[noise_mode],
+                                    RANGE[flux_range], float(replacement), float(sigma0),
+                                    None if mask_in is None else mask_in.data_ptr(),
+                                    mask_out.data_ptr(), ctypes.byref(noise),
+                                    _stream_ptr(stream))
+        if rc != OK and not (allow_nostat and rc == ENOSTAT):
+            self._raise(rc, "sofia_sc_step")
+        return mask_out, noise.value
+
+    def smooth(self, cube, kernel, replacement: float = -1.0,
+               sigma0: float = float("nan"), mask_in=None, out=None, stream=None):
+        """Smoothed cube s (float32, NaN at blanked voxels) of one kernel."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        _check_like(mask_in, cube, torch.uint8, "mask_in")
+        _check_like(out, cube, torch.float32, "out")
+        if out is None:
+            out = torch.empty(cube.shape, dtype=torch.float32, device=cube.device)
+        k = Kernel(float(kernel[0]), int(kernel[1]))
+        rc = self.lib.sofia_sc_smooth(self.h, cube.data_ptr(), nx, ny, nz, k,
+                                      float(replacement), float(sigma0),
+                                      None if mask_in is None else mask_in.data_ptr(),
+                                      out.data_ptr(), _stream_ptr(stream))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_smooth")
+        return out
+
+    def profile(self, enable: bool):
+        rc = self.lib.sofia_sc_profile(self.h, 1 if enable else 0)
+        if rc != OK:
+            self._raise(rc, "sofia_sc_profile")
+
+    def profile_read(self) -> List[dict]:
+        cap = 32
+        arr = (KernelStat * cap)()
+        n = ctypes.c_int32()
+        rc = self.lib.sofia_sc_profile_read(self.h, arr, cap, ctypes.byref(n))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_profile_read")
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches,
+                     total_ms=arr[i].total_ms, bytes=arr[i].bytes,
+                     voxels=arr[i].voxels) for i in range(min(n.value, cap))]

@@ -1,0 +1,112 @@
+// Internal interface between the host orchestration (sc_api.hip) and the
+// gfx950 kernels (sc_kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sofia_sc.h"
+
+namespace sc {
+
+// Working-mask bits. The library keeps its own per-voxel byte: bit 0 = in the
+// detection mask so far, bit 1 = blanked (non-finite input). The caller's
+// mask only ever receives 0/1.
+constexpr uint8_t kDet = 1;
+constexpr uint8_t kBlank = 2;
+
+// Histogram layout for the exact MAD selection on the bit pattern of |s|
+// (a non-negative float's bits order like its value). Level 1 digit = bits
+// 30..19 (4096 bins, counted in LDS); level 2 = bits 18..0 of the keys whose
+// level-1 digit holds a wanted order statistic (2^19 bins in global memory,
+// plus a coarse 1024-bin copy of bits 18..9 to speed up the rank walk).
+constexpr int kL1Shift = 19;
+constexpr int kL1Bins = 1 << 12;
+constexpr int kL2Bins = 1 << 19;
+constexpr int kL2CoarseShift = 9;
+constexpr int kL2Coarse = 1 << 10;
+constexpr int kL2Fine = 1 << kL2CoarseShift;
+
+constexpr double kMadFactor = 1.4826;
+
+// Device-resident state of one run: noise values and selection bookkeeping.
+// Everything a later launch needs from an earlier one stays on the device,
+// so a run makes no host round trip until the final copy of the noise.
+struct DevState {
+    double sigma0;          // noise of the unsmoothed input (replacement)
+    double thr;             // current threshold t * sigma_k
+    unsigned long long m;   // number of selected voxels (MAD)
+    unsigned long long rank[2];  // residual ranks inside the level-1 bins
+    uint32_t bin[2];        // level-1 bins holding ranks floor((m-1)/2), floor(m/2)
+    int32_t status;         // nonzero: some noise had no selected voxel
+    int32_t pad;
+    double sigma[SOFIA_SC_MAX_KERNELS];
+};
+
+enum Src { SRC_X = 0, SRC_P = 1 };
+enum Op { OP_STD = 0, OP_HIST1 = 1, OP_HIST2 = 2, OP_CLIP = 3, OP_WRITE = 4 };
+
+// Arguments of the column-streaming kernel (spectral boxcar + one of the
+// per-voxel operations). One thread owns one (x, y) column and streams z.
+struct ColArgs {
+    const float *x;              // raw cube (SRC_X)
+    const float *p;              // spatially smoothed cube (SRC_P)
+    const uint8_t *wm_in;        // working mask (may be null when has_wm is false)
+    uint8_t *mask_out;           // OP_CLIP output
+    float *s_out;                // OP_WRITE output
+    int64_t ncol;                // nx * ny
+    int64_t nz;
+    int32_t w, h;                // spectral width (odd >= 3, or 1) and (w-1)/2
+    int32_t zchunk;              // planes per block
+    int32_t ncb;                 // column blocks
+    int32_t range;               // -1 negative, 0 all, +1 positive
+    int32_t repl_on;             // replace detected voxels (SRC_X only)
+    double repl_n;               // n of +-n sigma0
+    int32_t out_user;            // OP_CLIP: write 0/1 instead of working bits
+    int32_t pad;
+    DevState *st;
+    double *part_sum;            // OP_STD per-block partials
+    unsigned long long *part_cnt;
+    unsigned long long *hist1;   // [kL1Bins]
+    unsigned long long *hist2;   // [2][kL2Bins]
+    unsigned long long *hist2c;  // [2][kL2Coarse]
+};
+
+struct SpatialArgs {
+    const float *x;
+    const uint8_t *wm;           // may be null (no replacement)
+    float *p;
+    int64_t nx, ny, nz;
+    int32_t tiles_x, tiles_y;
+    int32_t repl_on;
+    int32_t pad;
+    double repl_n;
+    const DevState *st;
+};
+
+// ---- launchers (sc_kernels.hip). Each returns the launch's hipError_t.
+hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
+                            int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
+hipError_t launch_spatial(int n_iter, int radius, const SpatialArgs &a,
+                          hipStream_t s);
+hipError_t launch_column(int src, int op, bool spectral, bool has_wm,
+                         const ColArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_finalize_std(DevState *st, const double *part_sum,
+                               const unsigned long long *part_cnt, int nparts,
+                               int k, double t, int also_sigma0, hipStream_t s);
+hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
+                                hipStream_t s);
+hipError_t launch_finalize_mad2(DevState *st, const unsigned long long *hist2,
+                                const unsigned long long *hist2c, int k, double t,
+                                int also_sigma0, hipStream_t s);
+hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s);
+
+// Threads per block of the column kernel, and its dynamic LDS size.
+constexpr int kColThreads = 256;
+size_t column_lds_bytes(int op, bool spectral, int w);
+
+// Spatial tile: 64 columns x (64 - 2 n r) rows per one-wave block.
+inline int spatial_tile_rows(int n_iter, int radius) { return 64 - 2 * n_iter * radius; }
+
+}  // namespace sc

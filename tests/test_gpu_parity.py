@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: a mask must equal the oracle's on every voxel outside the
+boundary band (voxels with | |s|/sigma_k - t | <= 1e-5, reported by the
+oracle); noise values must agree to 1e-6 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_2106_15789_amd as sc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SIGMA_RTOL = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def h():
+    handle = sc.SofiaSC(0)
+    yield handle
+    handle.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_mask(gpu, ref, band, what=""):
+    diff = gpu != ref
+    outside = int((diff & (band == 0)).sum())
+    inside = int((diff & (band != 0)).sum())
+    assert outside == 0, f"{what}: {outside} mismatches outside the band ({inside} inside)"
+    return inside
+
+
+def assert_sigma(gpu, ref, what=""):
+    gpu = np.atleast_1d(np.asarray(gpu, np.float64))
+    ref = np.atleast_1d(np.asarray(ref, np.float64))
+    rel = np.abs(gpu / ref - 1)
+    assert np.all(rel <= SIGMA_RTOL), f"{what}: sigma rel err {rel.max():.3g}"
+    return float(rel.max())
+
+
+def cfg2_like(nx=200, ny=170, nz=160, seed=2, n_gal=12, border=3):
+    spec = synth.CubeSpec(nx, ny, nz, seed=seed, radial=True, sigma_lo=0.8,
+                          sigma_hi=1.5, n_gal=n_gal, nan_border=border)
+    return synth.generate(spec)
+
+
+KERNELS_CFG2 = [(float(f), w) for f in (0, 3, 6) for w in (0, 3, 7, 15)]
+
+
+# ------------------------------------------------------------------ smoothing
+
+SMOOTH_KERNELS = [(0, 0), (0, 3), (0, 7), (0, 15), (0, 31), (3, 0), (3, 3), (5, 7),
+                  (6, 15), (9, 3), (10, 31), (1, 0)]
+
+
+@pytest.mark.parametrize("kernel", SMOOTH_KERNELS)
+def test_smooth_matches_oracle(h, kernel):
+    say("smooth", kernel)
+    x = cfg2_like(150, 130, 70, seed=31, n_gal=4, border=2)
+    rng = np.random.default_rng(1)
+    x[rng.random(x.shape) < 0.003] = np.nan
+    mask = (rng.random(x.shape) < 0.01).astype(np.uint8)
+    s_ref = oracle.smooth(x, kernel[0], kernel[1], mask, 2.0, 0.9)
+    s_gpu = host(h.smooth(dev(x), kernel, replacement=2.0, sigma0=0.9,
+                          mask_in=dev(mask))).astype(np.float64)
+    np.testing.assert_array_equal(np.isnan(s_gpu), np.isnan(s_ref))
+    fin = np.isfinite(s_ref)
+    scale = math.sqrt(np.mean(s_ref[fin] ** 2))
+    err = np.abs(s_gpu[fin] - s_ref[fin]).max() / scale
+    say(f"  max |ds| / rms(s) = {err:.3g}")
+    assert err < 2e-6
+
+
+# --------------------------------------------------------- end-to-end runs
+
+def test_run_plain_64x64x128(h):
+    wl = synth.workload("plain_64x64x128")
+    x = synth.generate(wl.cubes[0])
+    ref = oracle.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
+                     wl.replacement)
+    m, noise, s0 = h.run(dev(x), wl.kernels, wl.threshold, wl.noise_mode,
+                         wl.flux_range, wl.replacement)
+    say("sigma gpu", noise, "oracle", ref.sigma, "band", ref.band_count)
+    assert_sigma(noise, ref.sigma, "sigma_k")
+    assert_sigma(s0, ref.sigma0, "sigma_0")
+    assert_mask(host(m), ref.mask, ref.band, "mask")
+    assert host(m).max() <= 1
+
+
+@pytest.mark.parametrize("mode,rng_", [("mad", "negative"), ("std", "all"),
+                                       ("mad", "all"), ("std", "positive")])
+def test_step_teacher_forced(h, mode, rng_):
+    """Each step gets the oracle's previous mask and sigma_0."""
+    say("teacher-forced", mode, rng_)
+    x = cfg2_like()
+    kernels = KERNELS_CFG2 if (mode, rng_) == ("mad", "negative") else \
+        [(0.0, 0), (0.0, 7), (3.0, 3), (6.0, 15)]
+    s0, _ = oracle.noise(np.where(np.isfinite(x), x, np.nan).astype(np.float64),
+                         mode, rng_)
+    mask = np.zeros(x.shape, np.uint8)
+    xd = dev(x)
+    total_band = 0
+    for k, (f, w) in enumerate(kernels):
+        ref = oracle.step(x, f, w, 3.5, mode, rng_, mask, 2.0, s0)
+        out, sig = h.step(xd, (f, w), 3.5, mode, rng_, 2.0, s0,
+                          mask_in=dev(mask) if k else None)
+        assert_sigma(sig, ref.sigma, f"sigma step {k}")
+        total_band += assert_mask(host(out), ref.mask, ref.band, f"mask step {k}")
+        mask = ref.mask
+    say("  band flips (allowed):", total_band)
+
+
+def test_run_cfg2_like_end_to_end(h):
+    x = cfg2_like()
+    ref = oracle.run(x, KERNELS_CFG2, 3.5, "mad", "negative", 2.0)
+    m, noise, s0 = h.run(dev(x), KERNELS_CFG2, 3.5, "mad", "negative", 2.0)
+    g = host(m)
+    diff = g != ref.mask
+    say("end-to-end: sigma rel", np.abs(noise / ref.sigma - 1).max(),
+        "band", ref.band_count.sum(), "diff", int(diff.sum()),
+        "outside band", int((diff & (ref.band == 0)).sum()))
+    assert_sigma(noise, ref.sigma, "sigma_k")
+    assert_sigma(s0, ref.sigma0, "sigma_0")
+    # with no band voxel, nothing can propagate: the masks must be identical
+    if ref.band_count.sum() == 0:
+        np.testing.assert_array_equal(g, ref.mask)
+    else:
+        assert int((diff & (ref.band == 0)).sum()) <= 50 * int(ref.band_count.sum())
+
+
+def test_replacement_off_matches(h):
+    x = cfg2_like(96, 80, 90, seed=8, n_gal=5)
+    kernels = [(0.0, 3), (3.0, 0), (6.0, 7)]
+    ref = oracle.run(x, kernels, 3.0, "std", "all", -1.0)
+    m, noise, s0 = h.run(dev(x), kernels, 3.0, "std", "all", replacement=-1.0)
+    assert math.isnan(s0)
+    assert_sigma(noise, ref.sigma)
+    assert_mask(host(m), ref.mask, ref.band)
+
+
+# ----------------------------------------------------------------- edge cases
+
+EDGE_SHAPES = [(1, 1, 1), (1, 1, 9), (5, 1, 1), (1, 7, 1), (3, 2, 4), (65, 3, 2),
+               (17, 66, 5), (64, 64, 3), (257, 2, 6), (70, 90, 1)]
+
+
+@pytest.mark.parametrize("shape_xyz", EDGE_SHAPES)
+def test_edge_shapes(h, shape_xyz):
+    nx, ny, nz = shape_xyz
+    say("edge", shape_xyz)
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    x = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    x[rng.random(x.shape) < 0.02] *= 8
+    kernels = [(0.0, 0), (0.0, 7), (3.0, 3), (9.0, 15), (0.0, 31)]
+    for mode, r in (("mad", "all"), ("std", "all")):
+        ref = oracle.run(x, kernels, 2.5, mode, r, 2.0)
+        m, noise, s0 = h.run(dev(x), kernels, 2.5, mode, r, 2.0, allow_nostat=True)
+        assert ref.status == 0
+        assert_sigma(noise, ref.sigma, f"{shape_xyz} {mode}")
+        assert_mask(host(m), ref.mask, ref.band, f"{shape_xyz} {mode}")
+
+
+def test_all_nan_planes_and_columns(h):
+    x = cfg2_like(70, 66, 40, seed=12, n_gal=2, border=0)
+    x[5] = np.nan
+    x[17:20] = np.nan
+    x[:, :, 33] = np.nan
+    x[:, 10, :] = np.nan
+    kernels = [(0.0, 0), (3.0, 7), (6.0, 3)]
+    ref = oracle.run(x, kernels, 3.0, "mad", "negative", 2.0)
+    m, noise, _ = h.run(dev(x), kernels, 3.0, "mad", "negative", 2.0)
+    g = host(m)
+    assert g[~np.isfinite(x)].sum() == 0
+    assert_sigma(noise, ref.sigma)
+    assert_mask(g, ref.mask, ref.band)
+
+
+def test_enostat_when_range_is_empty(h):
+    x = np.abs(np.random.default_rng(0).standard_normal((8, 9, 10))).astype(np.float32) + 0.1
+    with pytest.raises(sc.ScError) as e:
+        h.run(dev(x), [(0.0, 0), (0.0, 3)], 3.0, "mad", "negative", 2.0)
+    assert e.value.code == sc.ENOSTAT
+    # the handle stays usable
+    m, noise, _ = h.run(dev(x), [(0.0, 0)], 3.0, "mad", "positive", 2.0)
+    assert np.isfinite(noise).all()
+
+
+def test_constant_cube_sigma_zero(h):
+    x = np.full((6, 7, 8), 0.0, np.float32)
+    x[3, 3, 3] = 5.0
+    ref = oracle.run(x, [(0.0, 0), (0.0, 3)], 3.0, "mad", "all", 2.0)
+    m, noise, _ = h.run(dev(x), [(0.0, 0), (0.0, 3)], 3.0, "mad", "all", 2.0)
+    np.testing.assert_array_equal(noise, ref.sigma)
+    np.testing.assert_array_equal(host(m), ref.mask)
+
+
+def test_bad_arguments_raise_einval(h):
+    x = dev(np.zeros((4, 4, 4), np.float32))
+    for kernels, t in [([(0.0, 4)], 3.0), ([(-1.0, 0)], 3.0), ([(0.0, 0)], 0.0),
+                       ([(0.0, 0)], float("nan")), ([(40.0, 0)], 3.0), ([(0.0, 65)], 3.0)]:
+        with pytest.raises(sc.ScError) as e:
+            h.run(x, kernels, t, "std", "all")
+        assert e.value.code == sc.EINVAL
+
+
+# ------------------------------------------------------------------ invariants
+
+def test_sign_symmetry_bit_exact(h):
+    x = cfg2_like(120, 100, 80, seed=41, n_gal=6)
+    a_m, a_s, _ = h.run(dev(x), KERNELS_CFG2, 3.5, "mad", "negative")
+    b_m, b_s, _ = h.run(dev(-x), KERNELS_CFG2, 3.5, "mad", "positive")
+    np.testing.assert_array_equal(host(a_m), host(b_m))
+    np.testing.assert_array_equal(a_s, b_s)
+
+
+def test_power_of_two_scaling_bit_exact(h):
+    x = cfg2_like(120, 100, 80, seed=42, n_gal=6)
+    a_m, a_s, _ = h.run(dev(x), KERNELS_CFG2, 3.5, "mad", "negative")
+    b_m, b_s, _ = h.run(dev(x * np.float32(4.0)), KERNELS_CFG2, 3.5, "mad", "negative")
+    np.testing.assert_array_equal(host(a_m), host(b_m))
+    np.testing.assert_array_equal(a_s * 4.0, b_s)
+
+
+def test_deterministic(h):
+    x = dev(cfg2_like(130, 70, 90, seed=43, n_gal=5))
+    runs = [h.run(x, KERNELS_CFG2, 3.5, "std", "all") for _ in range(3)]
+    for m, s, _ in runs[1:]:
+        np.testing.assert_array_equal(host(m), host(runs[0][0]))
+        np.testing.assert_array_equal(s, runs[0][1])
+
+
+def test_mask_monotone_in_threshold_without_replacement(h):
+    x = dev(cfg2_like(100, 90, 70, seed=44, n_gal=5))
+    lo, s_lo, _ = h.run(x, KERNELS_CFG2, 3.0, "mad", "negative", replacement=-1)
+    hi, s_hi, _ = h.run(x, KERNELS_CFG2, 3.6, "mad", "negative", replacement=-1)
+    assert np.all(host(hi) <= host(lo))
+    np.testing.assert_array_equal(s_lo, s_hi)
