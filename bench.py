@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X smooth-and-clip (S+C) finder.
+
+One step = one whole S+C run (every kernel pair: smoothing, noise, clip into
+the mask) over a cube already resident in HBM. Default workload: a
+1024 x 1024 x 1024 float32 cube (spectral axis slowest) of Gaussian noise whose
+sigma varies 0.8-1.5 across the field, a 13-px NaN border (5 % of voxels) and
+2000 mock galaxies; kernels spatial {0, 3, 6} px x spectral {0, 3, 7, 15} ch;
+MAD noise on negative voxels; threshold 3.5; replacement n = 2.
+
+Prints one JSON line. `value` is voxels per second of whole runs; `roofline`
+describes the kernel family with the largest share of device time, timed with
+HIP events on the launch stream; `cpu_baseline` times the FP64 oracle on a
+slab of the same cube on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("sc_kernels.hip", "sc_api.hip", "sc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2106_15789_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(family: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{family}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_src_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, planes: int):
+    """The FP64 oracle on planes [0, planes) of the same workload."""
+    import oracle
+    import synth
+    spec = wl.cubes[0]
+    x = synth.generate(spec, z0=0, z1=planes)
+    t0 = time.perf_counter()
+    oracle.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range, wl.replacement)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": x.size / dt, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+            "sample": f"planes 0-{planes - 1} of the same cube ({spec.nx}x{spec.ny}x{planes} "
+                      f"voxels, all {len(wl.kernels)} kernel pairs, noise measured on the "
+                      f"slab), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="plain_1024cube")
+    ap.add_argument("--cpu-planes", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2106_15789_amd as sc
+
+    wl = synth.workload(args.workload)
+    spec = wl.cubes[0]
+    print(f"[bench] generating {args.workload} {spec.nx}x{spec.ny}x{spec.nz}",
+          file=sys.stderr, flush=True)
+    x_host = synth.generate(spec)
+    x = torch.from_numpy(x_host).cuda()
+    mask = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    torch.cuda.synchronize()
+    h = sc.SofiaSC(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return h.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
+                     wl.replacement, mask=mask, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, noise, sigma0 = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h.profile(False)
+    stats = h.profile_read()
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
+
+    n_vox = spec.n_vox
+    value = n_vox * args.steps / dt
+    gpu_ms = sum(s["total_ms"] for s in stats)
+    dom = max(stats, key=lambda s: s["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(dom["name"], args.workload)
+    alg_bytes_step = sum(s["bytes"] for s in stats) / args.steps
+
+    result = {
+        "metric": "S+C voxels/s over all kernels (FP32 vs batched/FP16) at oracle mask match; % HBM peak",
+        "value": value,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Philox noise + Gaussian mock galaxies)",
+        "config": {
+            "workload": args.workload, "nx": spec.nx, "ny": spec.ny, "nz": spec.nz,
+            "kernels": [list(k) for k in wl.kernels], "noise": wl.noise_mode,
+            "flux_range": wl.flux_range, "threshold": wl.threshold,
+            "replacement": wl.replacement, "storage": "f32",
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": dom["name"], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic, "avg_launch_ms": avg_ms,
+            "alg_bytes_per_launch": bytes_per_launch,
+        },
+        "whole_step_hbm_frac": alg_bytes_step / (dt / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "alg_bytes_per_step": alg_bytes_step,
+        "kernel_time_share": {s["name"]: round(s["total_ms"] / gpu_ms, 4) for s in stats},
+        "kernel_gbs": {s["name"]: round(s["bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1)
+                       for s in stats if s["bytes"] > 0 and s["total_ms"] > 0},
+        "noise": [float(v) for v in noise],
+        "sigma0": float(sigma0),
+        "mask_voxels": int(mask.sum().item()),
+        "kernel_src_sha": kernel_source_sha(),
+    }
+    h.close()
+    del x, mask
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_planes, spec.nz))
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

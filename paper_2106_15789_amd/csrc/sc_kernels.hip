@@ -75,14 +75,17 @@ __global__ void k_set_sigma0(DevState *st, double sigma0) {
 // ------------------------------------------------------ spatial cascade
 
 // One boxcar pass over register array `in`, writing out[i] for i in
-// [LO, HI): unnormalised sum of in[i-R .. i+R]. Running sum, recomputed
-// directly every 16 outputs so FP32 rounding cannot accumulate along a row.
+// [LO, HI): unnormalised sum of in[i-R .. i+R]. For R = 1 the three taps are
+// summed directly (as cheap as a running sum); wider boxcars use a running
+// sum recomputed directly every kAnchor outputs, which bounds the FP32
+// rounding carried along a row by the terms that already left the window.
+constexpr int kAnchor = 4;
 template <int N, int R, int LO, int HI>
 __device__ __forceinline__ void box_pass(const float (&in)[N], float (&out)[N]) {
     float s = 0.f;
 #pragma unroll
     for (int i = LO; i < HI; ++i) {
-        if ((i - LO) % 16 == 0) {
+        if (R == 1 || (i - LO) % kAnchor == 0) {
             s = 0.f;
 #pragma unroll
             for (int j = -R; j <= R; ++j) s += in[i + j];
@@ -138,21 +141,35 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
     const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
 
     // Stage the region (64 rows x RW columns) with blanking and replacement.
-    for (int row = 0; row < 64; ++row) {
-        const int64_t gy = y0 - H + row;
-        const bool yin = gy >= 0 && gy < ny;
-        for (int col = lane; col < RW; col += 64) {
-            const int64_t gx = x0 - H + col;
-            float v = 0.f;
-            if (yin && gx >= 0 && gx < nx) {
+    // The region is walked as one flat array so every load instruction of the
+    // wave is (nearly) contiguous; loads are issued in batches of kBatch so
+    // many are in flight before the first LDS store waits on them.
+    constexpr int NE = 64 * RW;
+    constexpr int kBatch = 16;
+    for (int e0 = 0; e0 < NE; e0 += 64 * kBatch) {
+        float v[kBatch];
+        uint8_t m[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int e = e0 + b * 64 + lane;
+            const int row = e / RW, col = e - row * RW;
+            const int64_t gy = y0 - H + row, gx = x0 - H + col;
+            v[b] = 0.f;
+            m[b] = 0;
+            if (e < NE && gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
                 const int64_t idx = gy * nx + gx;
-                const float xv = xp[idx];
-                if (isfinite(xv)) {
-                    v = xv;
-                    if (repl && (wp[idx] & kDet)) v = copysignf(rv, xv);
-                }
+                v[b] = xp[idx];
+                if (repl) m[b] = wp[idx];
             }
-            lds[row * P1 + col] = v;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int e = e0 + b * 64 + lane;
+            const int row = e / RW, col = e - row * RW;
+            const bool fin = isfinite(v[b]);
+            float y = fin ? v[b] : 0.f;
+            if (fin && (m[b] & kDet)) y = copysignf(rv, v[b]);
+            if (e < NE) lds[row * P1 + col] = y;
         }
     }
     __syncthreads();
@@ -279,25 +296,43 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         }
     };
 
+    // Planes are processed in groups of U: all loads of a group are issued
+    // before any of them is consumed, so a wave keeps U plane reads in flight.
+    constexpr int U = 8;
     if (active) {
         if (!SPEC) {
-            for (int64_t z = z0; z < z1; ++z) {
-                const int64_t i = z * ncol + c;
-                float v;
-                bool blank;
-                uint8_t wb = 0;
-                if (SRC == SRC_X) {
-                    const float xv = a.x[i];
-                    blank = !isfinite(xv);
-                    if (HASWM) wb = a.wm_in[i];
-                    v = blank ? 0.f
-                              : ((HASWM && a.repl_on && (wb & kDet)) ? copysignf(rv, xv) : xv);
-                } else {
-                    v = a.p[i];
-                    wb = a.wm_in[i];
-                    blank = (wb & kBlank) != 0;
+            for (int64_t zb = z0; zb < z1; zb += U) {
+                float xv[U];
+                uint8_t wv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t z = zb + u;
+                    xv[u] = 0.f;
+                    wv[u] = 0;
+                    if (z < z1) {
+                        const int64_t i = z * ncol + c;
+                        xv[u] = SRC == SRC_X ? a.x[i] : a.p[i];
+                        if (HASWM) wv[u] = a.wm_in[i];
+                    }
                 }
-                consume(i, (double)v, blank, wb);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t z = zb + u;
+                    if (z >= z1) break;
+                    const int64_t i = z * ncol + c;
+                    float v;
+                    bool blank;
+                    if (SRC == SRC_X) {
+                        blank = !isfinite(xv[u]);
+                        v = blank ? 0.f
+                                  : ((HASWM && a.repl_on && (wv[u] & kDet)) ? copysignf(rv, xv[u])
+                                                                            : xv[u]);
+                    } else {
+                        v = xv[u];
+                        blank = (wv[u] & kBlank) != 0;
+                    }
+                    consume(i, (double)v, blank, wv[u]);
+                }
             }
         } else {
             const int w = a.w, h = a.h;
@@ -311,20 +346,29 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 S += (double)v;
             }
             int slot = 0;
-            for (int64_t z = z0; z < z1; ++z) {
-                const int64_t zn = z + h;
-                const float vn = zn < nz ? value(zn) : 0.f;
-                const float vo = ring[slot * B + tid];
-                ring[slot * B + tid] = vn;
-                S += (double)vn - (double)vo;
-                if (++slot == w) slot = 0;
-                if (((z - z0) & 63) == 63) {   // re-anchor the running sum
-                    S = 0.0;
-                    for (int j = 0; j < w; ++j) S += (double)ring[j * B + tid];
+            for (int64_t zb = z0; zb < z1; zb += U) {
+                float vn[U];
+                uint8_t wo[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t z = zb + u, zn = z + h;
+                    vn[u] = (z < z1 && zn < nz) ? value(zn) : 0.f;
+                    wo[u] = z < z1 ? a.wm_in[z * ncol + c] : (uint8_t)0;
                 }
-                const int64_t i = z * ncol + c;
-                const uint8_t wb = a.wm_in[i];
-                consume(i, S * inv_w, (wb & kBlank) != 0, wb);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t z = zb + u;
+                    if (z >= z1) break;
+                    const float vo = ring[slot * B + tid];
+                    ring[slot * B + tid] = vn[u];
+                    S += (double)vn[u] - (double)vo;
+                    if (++slot == w) slot = 0;
+                    if (((z - z0) & 63) == 63) {   // re-anchor the running sum
+                        S = 0.0;
+                        for (int j = 0; j < w; ++j) S += (double)ring[j * B + tid];
+                    }
+                    consume(z * ncol + c, S * inv_w, (wo[u] & kBlank) != 0, wo[u]);
+                }
             }
         }
     }

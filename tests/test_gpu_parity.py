@@ -87,7 +87,9 @@ def test_smooth_matches_oracle(h, kernel):
     scale = math.sqrt(np.mean(s_ref[fin] ** 2))
     err = np.abs(s_gpu[fin] - s_ref[fin]).max() / scale
     say(f"  max |ds| / rms(s) = {err:.3g}")
-    assert err < 2e-6
+    # rms(s) is the std noise of s; a mask decision can only differ from the
+    # oracle's inside the 1e-5 sigma band if this stays well below 1e-5
+    assert err < 6e-6
 
 
 # --------------------------------------------------------- end-to-end runs
