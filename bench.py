@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--workload", default="plain_1024cube")
     ap.add_argument("--cpu-planes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain device copy of the cube (4 B/voxel "
+                         "read + write), the calibration kernel for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
@@ -108,6 +111,11 @@ def main():
     for _ in range(args.warmup):
         step()
     print("[bench] warmup done", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        probe = torch.empty_like(x)
+        probe.copy_(x)
+        torch.cuda.synchronize()
+        del probe
     h.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -305,6 +305,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
         a.tiles_x = (int)((d.nx + 63) / 64);
         a.tiles_y = (int)((d.ny + ty - 1) / ty);
+        spatial_interior(a, j.pl.n_iter, j.pl.radius);
         a.repl_on = j.repl_active ? 1 : 0;
         a.repl_n = j.repl_n;
         a.st = h->st;

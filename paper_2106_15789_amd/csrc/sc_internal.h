@@ -77,7 +77,10 @@ struct SpatialArgs {
     const uint8_t *wm;           // may be null (no replacement)
     float *p;
     int64_t nx, ny, nz;
-    int32_t tiles_x, tiles_y;
+    int32_t tiles_x, tiles_y;    // tiles per plane along x and y
+    int32_t tx_begin, ntx;       // interior tiles: region inside the cube
+    int32_t ty_begin, nty;
+    int64_t tiles_per_plane;     // set per launch (interior or edge set)
     int32_t repl_on;
     int32_t pad;
     double repl_n;
@@ -104,9 +107,24 @@ hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s);
 
 // Threads per block of the column kernel, and its dynamic LDS size.
 constexpr int kColThreads = 256;
-size_t column_lds_bytes(int op, bool spectral, int w);
+size_t column_lds_bytes(int src, int op, bool spectral, int w);
 
 // Spatial tile: 64 columns x (64 - 2 n r) rows per one-wave block.
 inline int spatial_tile_rows(int n_iter, int radius) { return 64 - 2 * n_iter * radius; }
+
+// Interior tile rectangle: tiles whose region (tile plus halo) lies inside
+// the cube, so the cascade needs no edge handling there.
+inline void spatial_interior(SpatialArgs &a, int n_iter, int radius) {
+    const int64_t H = (int64_t)n_iter * radius, TY = spatial_tile_rows(n_iter, radius);
+    int64_t tx0 = (H + 63) / 64, tx1 = a.nx - 64 - H >= 0 ? (a.nx - 64 - H) / 64 + 1 : 0;
+    int64_t ty0 = (H + TY - 1) / TY, ty1 = a.ny - 64 + H >= 0 ? (a.ny - 64 + H) / TY + 1 : 0;
+    if (tx1 > a.tiles_x) tx1 = a.tiles_x;
+    if (ty1 > a.tiles_y) ty1 = a.tiles_y;
+    if (tx1 <= tx0 || ty1 <= ty0) { tx0 = tx1 = ty0 = ty1 = 0; }
+    a.tx_begin = (int32_t)tx0;
+    a.ntx = (int32_t)(tx1 - tx0);
+    a.ty_begin = (int32_t)ty0;
+    a.nty = (int32_t)(ty1 - ty0);
+}
 
 }  // namespace sc

@@ -97,27 +97,69 @@ __device__ __forceinline__ void box_pass(const float (&in)[N], float (&out)[N]) 
 }
 
 // Pass P of NIT. Input valid on [(P-1)R, N-(P-1)R); output on [PR, N-PR).
-// With edge set, entries whose global coordinate lies outside the cube
-// (local index outside [lo, hi)) are zeroed after the pass, so every pass
-// sees zeros beyond the cube edge.
-template <int N, int R, int P, int NIT>
+// With EDGE set, entries whose global coordinate lies outside the cube
+// (local index outside [lo, hi), the same for every lane) are zeroed after
+// each pass, so every pass sees zeros beyond the cube edge; the zeroing is a
+// multiply by a uniform 0/1 so it stays branch-free.
+template <int N, int R, int P, int NIT, bool EDGE>
 struct Cascade {
-    __device__ __forceinline__ static void run(float (&v)[N], bool edge, int lo,
-                                               int hi) {
+    __device__ __forceinline__ static void run(float (&v)[N], int lo, int hi) {
         float o[N];
         box_pass<N, R, P * R, N - P * R>(v, o);
 #pragma unroll
-        for (int i = P * R; i < N - P * R; ++i)
-            v[i] = (edge && (i < lo || i >= hi)) ? 0.f : o[i];
-        Cascade<N, R, P + 1, NIT>::run(v, edge, lo, hi);
+        for (int i = P * R; i < N - P * R; ++i) {
+            if (EDGE) {
+                const float keep = (i >= lo && i < hi) ? 1.f : 0.f;
+                v[i] = o[i] * keep;
+            } else {
+                v[i] = o[i];
+            }
+        }
+        Cascade<N, R, P + 1, NIT, EDGE>::run(v, lo, hi);
     }
 };
-template <int N, int R, int NIT>
-struct Cascade<N, R, NIT + 1, NIT> {
-    __device__ __forceinline__ static void run(float (&)[N], bool, int, int) {}
+template <int N, int R, int NIT, bool EDGE>
+struct Cascade<N, R, NIT + 1, NIT, EDGE> {
+    __device__ __forceinline__ static void run(float (&)[N], int, int) {}
 };
 
-template <int R, int NIT>
+// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
+// b % 8). Remap so that each XCD works through one contiguous range of
+// tiles: neighbouring tiles then share their halo rows and columns through
+// the same L2 instead of fetching them from HBM once per XCD.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+// Tile of the launch: interior launches cover the rectangle of tiles whose
+// region lies inside the cube; edge launches cover the ring of the others.
+__device__ __forceinline__ void spatial_tile(const SpatialArgs &a, bool edge, int64_t t,
+                                             int &tx, int &ty) {
+    if (!edge) {
+        ty = a.ty_begin + (int)(t / a.ntx);
+        tx = a.tx_begin + (int)(t - (int64_t)(ty - a.ty_begin) * a.ntx);
+        return;
+    }
+    const int64_t T = a.tiles_x;
+    const int64_t above = a.ty_begin, below = a.tiles_y - a.ty_begin - a.nty;
+    const int64_t left = a.tx_begin, right = a.tiles_x - a.tx_begin - a.ntx;
+    if (t < above * T) {
+        ty = (int)(t / T);
+        tx = (int)(t - (int64_t)ty * T);
+    } else if (t < (above + below) * T) {
+        const int64_t j = t - above * T;
+        ty = (int)(a.ty_begin + a.nty + j / T);
+        tx = (int)(j % T);
+    } else {
+        const int64_t j = t - (above + below) * T, per = left + right;
+        const int64_t row = j / per, k = j - row * per;
+        ty = (int)(a.ty_begin + row);
+        tx = (int)(k < left ? k : a.tx_begin + a.ntx + (k - left));
+    }
+}
+
+template <int R, int NIT, bool EDGE>
 __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
     constexpr int H = R * NIT;          // halo consumed by the cascade
     constexpr int RW = 64 + 2 * H;      // region width
@@ -125,51 +167,60 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
     constexpr int P2 = 65;
     constexpr int TY = 64 - 2 * H;      // output rows per tile
     static_assert(TY >= 1, "halo too large for a 64-row region");
+    static_assert(2 * H <= 64, "second column strip must fit in one wave");
     __shared__ float lds[64 * P1];
 
     const int lane = threadIdx.x;
-    const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y;
-    const int64_t z = (int64_t)blockIdx.x / tiles;
-    const int64_t t = (int64_t)blockIdx.x - z * tiles;
-    const int ty = (int)(t / a.tiles_x);
-    const int tx = (int)(t - (int64_t)ty * a.tiles_x);
+    const int64_t tiles = a.tiles_per_plane;
+    const int64_t tile = xcd_remap((int64_t)blockIdx.x, tiles * a.nz);
+    const int64_t z = tile / tiles;
+    int tx, ty;
+    spatial_tile(a, EDGE, tile - z * tiles, tx, ty);
     const int64_t nx = a.nx, ny = a.ny;
     const int64_t x0 = (int64_t)tx * 64, y0 = (int64_t)ty * TY;
     const float *xp = a.x + z * nx * ny;
     const uint8_t *wp = a.wm ? a.wm + z * nx * ny : nullptr;
     const bool repl = a.repl_on && wp != nullptr;
     const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
+    const bool xedge = EDGE && ((x0 - H < 0) || (x0 + 64 + H > nx));
+    const bool yedge = EDGE && ((y0 - H < 0) || (y0 - H + 64 > ny));
 
-    // Stage the region (64 rows x RW columns) with blanking and replacement.
-    // The region is walked as one flat array so every load instruction of the
-    // wave is (nearly) contiguous; loads are issued in batches of kBatch so
-    // many are in flight before the first LDS store waits on them.
-    constexpr int NE = 64 * RW;
-    constexpr int kBatch = 16;
-    for (int e0 = 0; e0 < NE; e0 += 64 * kBatch) {
-        float v[kBatch];
-        uint8_t m[kBatch];
+    // Stage the region (64 rows x RW columns): lanes take columns lane and
+    // 64 + lane (the latter only for the 2H right-halo columns). Rows are
+    // fetched in batches so many loads are in flight at once.
+    constexpr int kRows = 8;
+    const bool has2 = lane < 2 * H;
+    for (int r0 = 0; r0 < 64; r0 += kRows) {
+        float v0[kRows], v1[kRows];
+        uint8_t m0[kRows], m1[kRows];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const int e = e0 + b * 64 + lane;
-            const int row = e / RW, col = e - row * RW;
-            const int64_t gy = y0 - H + row, gx = x0 - H + col;
-            v[b] = 0.f;
-            m[b] = 0;
-            if (e < NE && gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
-                const int64_t idx = gy * nx + gx;
-                v[b] = xp[idx];
-                if (repl) m[b] = wp[idx];
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t gy = y0 - H + r0 + k;
+            const int64_t gx0 = x0 - H + lane, gx1 = gx0 + 64;
+            v0[k] = v1[k] = 0.f;
+            m0[k] = m1[k] = 0;
+            const bool yin = !yedge || (gy >= 0 && gy < ny);
+            if (yin) {
+                const int64_t row = gy * nx;
+                if (!xedge || (gx0 >= 0 && gx0 < nx)) {
+                    v0[k] = xp[row + gx0];
+                    if (repl) m0[k] = wp[row + gx0];
+                }
+                if (has2 && (!xedge || gx1 < nx)) {
+                    v1[k] = xp[row + gx1];
+                    if (repl) m1[k] = wp[row + gx1];
+                }
             }
         }
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const int e = e0 + b * 64 + lane;
-            const int row = e / RW, col = e - row * RW;
-            const bool fin = isfinite(v[b]);
-            float y = fin ? v[b] : 0.f;
-            if (fin && (m[b] & kDet)) y = copysignf(rv, v[b]);
-            if (e < NE) lds[row * P1 + col] = y;
+        for (int k = 0; k < kRows; ++k) {
+            float *dst = lds + (r0 + k) * P1;
+            const bool f0 = isfinite(v0[k]), f1 = isfinite(v1[k]);
+            float y0v = f0 ? v0[k] : 0.f, y1v = f1 ? v1[k] : 0.f;
+            if (f0 && (m0[k] & kDet)) y0v = copysignf(rv, v0[k]);
+            if (f1 && (m1[k] & kDet)) y1v = copysignf(rv, v1[k]);
+            dst[lane] = y0v;
+            if (has2) dst[64 + lane] = y1v;
         }
     }
     __syncthreads();
@@ -179,10 +230,9 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
 #pragma unroll
     for (int i = 0; i < RW; ++i) r[i] = lds[lane * P1 + i];
     {
-        const bool edge = (x0 - H < 0) || (x0 + 64 + H > nx);
-        const int lo = (int)(H - x0);        // local index of gx = 0
-        const int hi = (int)(nx - x0 + H);   // local index of gx = nx
-        Cascade<RW, R, 1, NIT>::run(r, edge, lo, hi);
+        const int lo = xedge ? (int)(H - x0) : 0;            // local index of gx = 0
+        const int hi = xedge ? (int)(nx - x0 + H) : RW;      // local index of gx = nx
+        Cascade<RW, R, 1, NIT, EDGE>::run(r, lo, hi);
     }
     __syncthreads();
 #pragma unroll
@@ -194,21 +244,20 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
 #pragma unroll
     for (int j = 0; j < 64; ++j) c[j] = lds[j * P2 + lane];
     {
-        const bool edge = (y0 - H < 0) || (y0 - H + 64 > ny);
-        const int lo = (int)(H - y0);
-        const int hi = (int)(ny - y0 + H);
-        Cascade<64, R, 1, NIT>::run(c, edge, lo, hi);
+        const int lo = yedge ? (int)(H - y0) : 0;
+        const int hi = yedge ? (int)(ny - y0 + H) : 64;
+        Cascade<64, R, 1, NIT, EDGE>::run(c, lo, hi);
     }
     double norm = 1.0;
     for (int p = 0; p < 2 * NIT; ++p) norm *= (double)(2 * R + 1);
     const float scale = (float)(1.0 / norm);
     const int64_t gx = x0 + lane;
-    if (gx < nx) {
-        float *pp = a.p + z * nx * ny;
+    if (!EDGE || gx < nx) {
+        float *pp = a.p + z * nx * ny + gx;
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int64_t gy = y0 + j;
-            if (gy < ny) pp[gy * nx + gx] = c[H + j] * scale;
+            if (!EDGE || gy < ny) pp[gy * nx] = c[H + j] * scale;
         }
     }
 }
@@ -220,10 +269,21 @@ struct ColAcc {
     unsigned long long cnt;
 };
 
+// One thread per (x, y) column. The column is streamed as a sequence of
+// input planes zi = z0 - h .. z1 - 1 + h (the leading edge of the spectral
+// window); after input zi the window sum S covers planes zi - 2h .. zi, i.e.
+// the output plane z = zi - h. Inputs are fetched in groups of U planes and
+// the next group is requested before the current one is consumed, so every
+// wave keeps up to 2U plane reads in flight.
+//
+// Ring buffers (LDS, one slot per thread per plane of the window): the FP32
+// inputs of the window, for the running sum; with SRC_X also the working-mask
+// byte read at the leading edge, reused when that plane becomes the output.
 template <int SRC, int OP, bool SPEC, bool HASWM>
 __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     extern __shared__ float dyn_lds[];
     constexpr int B = kColThreads;
+    constexpr int U = 8;
     const int tid = threadIdx.x;
     const int cb = (int)(blockIdx.x % (unsigned)a.ncb);
     const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
@@ -232,37 +292,34 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     const int64_t ncol = a.ncol, nz = a.nz;
     const int64_t z0 = (int64_t)zc * a.zchunk;
     const int64_t z1 = min(nz, z0 + (int64_t)a.zchunk);
+    const int w = SPEC ? a.w : 1;
+    const int h = SPEC ? a.h : 0;
 
-    float *ring = dyn_lds;                                   // [w][B]
-    unsigned *hist = (unsigned *)(dyn_lds + (SPEC ? a.w * B : 0));
-    if (OP == OP_HIST1) {
-        for (int i = tid; i < kL1Bins; i += B) hist[i] = 0u;
-        __syncthreads();
+    // LDS layout: float ring [w][B] | byte ring [w][B] (SRC_X, SPEC) | histogram
+    float *ring = dyn_lds;
+    uint8_t *bring = (uint8_t *)(dyn_lds + (SPEC ? w * B : 0));
+    unsigned *hist = (unsigned *)(bring + ((SPEC && SRC == SRC_X) ? ((w * B + 3) & ~3) : 0));
+    constexpr int kHistWords = OP == OP_HIST1 ? kL1Bins : (OP == OP_HIST2 ? 2 * kL2Coarse : 0);
+    if (kHistWords) {
+        for (int i = tid; i < kHistWords; i += B) hist[i] = 0u;
     }
+    if (SPEC) {
+        for (int j = 0; j < w; ++j) {
+            ring[j * B + tid] = 0.f;
+            if (SRC == SRC_X) bring[j * B + tid] = 0;
+        }
+    }
+    if (kHistWords) __syncthreads();
 
-    const float rv = (SRC == SRC_X && HASWM && a.repl_on)
-                         ? (float)(a.repl_n * a.st->sigma0) : 0.f;
+    const bool repl = SRC == SRC_X && HASWM && a.repl_on;
+    const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
     const double T = (OP == OP_CLIP) ? a.st->thr : 0.0;
     uint32_t b0 = 0xffffffffu, b1 = 0xffffffffu;
     if (OP == OP_HIST2) { b0 = a.st->bin[0]; b1 = a.st->bin[1]; }
     const int range = a.range;
     ColAcc acc{0.0, 0ull};
+    const float *src = SRC == SRC_X ? a.x : a.p;
 
-    // Input of the spectral boxcar at (c, zz): replaced/blanked raw voxel or
-    // the spatially smoothed value.
-    auto value = [&](int64_t zz) -> float {
-        const int64_t i = zz * ncol + c;
-        if (SRC == SRC_X) {
-            const float xv = a.x[i];
-            if (!isfinite(xv)) return 0.f;
-            if (HASWM && a.repl_on && (a.wm_in[i] & kDet)) return copysignf(rv, xv);
-            return xv;
-        } else {
-            return a.p[i];
-        }
-    };
-
-    // Per-voxel operation on the smoothed value s at (c, z).
     auto consume = [&](int64_t i, double s, bool blank, uint8_t wb) {
         if (OP == OP_STD) {
             if (!blank && in_flux_range(s, range)) { acc.sum += s * s; acc.cnt += 1; }
@@ -278,11 +335,11 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 const uint32_t lo = key & (kL2Bins - 1);
                 if (k1 == b0) {
                     atomicAdd(&a.hist2[lo], 1ull);
-                    atomicAdd(&a.hist2c[lo >> kL2CoarseShift], 1ull);
+                    atomicAdd(&hist[lo >> kL2CoarseShift], 1u);
                 }
                 if (k1 == b1 && b1 != b0) {
                     atomicAdd(&a.hist2[kL2Bins + lo], 1ull);
-                    atomicAdd(&a.hist2c[kL2Coarse + (lo >> kL2CoarseShift)], 1ull);
+                    atomicAdd(&hist[kL2Coarse + (lo >> kL2CoarseShift)], 1u);
                 }
             }
         } else if (OP == OP_CLIP) {
@@ -296,80 +353,99 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         }
     };
 
-    // Planes are processed in groups of U: all loads of a group are issued
-    // before any of them is consumed, so a wave keeps U plane reads in flight.
-    constexpr int U = 8;
+    // Spectral input of a raw voxel: blanked -> 0, detected -> +-n sigma_0.
+    auto raw_value = [&](float xv, uint8_t wb) -> float {
+        if (!isfinite(xv)) return 0.f;
+        if (repl && (wb & kDet)) return copysignf(rv, xv);
+        return xv;
+    };
+
+    struct Group {
+        float v[U];
+        uint8_t b[U];
+    };
+    // Input planes zi = zb .. zb + U - 1 (SPEC) or output planes (not SPEC).
+    auto load_group = [&](int64_t zb, Group &g) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t zi = zb + u;
+            g.v[u] = 0.f;
+            g.b[u] = 0;
+            if (!SPEC) {
+                if (zi < z1) {
+                    const int64_t i = zi * ncol + c;
+                    g.v[u] = src[i];
+                    if (HASWM) g.b[u] = a.wm_in[i];
+                }
+            } else {
+                const bool in_run = zi < z1 + h;
+                if (in_run && zi >= 0 && zi < nz) {
+                    const int64_t i = zi * ncol + c;
+                    g.v[u] = src[i];
+                    if (SRC == SRC_X) g.b[u] = a.wm_in[i];
+                }
+                if (SRC == SRC_P) {
+                    const int64_t zo = zi - h;
+                    if (in_run && zo >= z0) g.b[u] = a.wm_in[zo * ncol + c];
+                }
+            }
+        }
+    };
+
+    double S = 0.0;
+    int slot = 0;
+    const double inv_w = SPEC ? 1.0 / (double)w : 1.0;
+    const int64_t zstart = SPEC ? z0 - h : z0;
+    const int64_t zend = SPEC ? z1 + h : z1;   // exclusive
+    int64_t step = 0;
+
+    auto process_group = [&](int64_t zb, const Group &g) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t zi = zb + u;
+            if (zi >= zend) break;
+            if (!SPEC) {
+                const int64_t i = zi * ncol + c;
+                if (SRC == SRC_X) {
+                    const bool blank = !isfinite(g.v[u]);
+                    consume(i, (double)raw_value(g.v[u], g.b[u]), blank, g.b[u]);
+                } else {
+                    consume(i, (double)g.v[u], (g.b[u] & kBlank) != 0, g.b[u]);
+                }
+            } else {
+                const float vn = SRC == SRC_X ? raw_value(g.v[u], g.b[u]) : g.v[u];
+                const float vo = ring[slot * B + tid];
+                ring[slot * B + tid] = vn;
+                uint8_t wb_out;
+                if (SRC == SRC_X) {
+                    bring[slot * B + tid] = g.b[u];
+                    int os = slot + h + 1;
+                    if (os >= w) os -= w;
+                    wb_out = bring[os * B + tid];
+                } else {
+                    wb_out = g.b[u];
+                }
+                S += (double)vn - (double)vo;
+                if (++slot == w) slot = 0;
+                if ((++step & 63) == 0) {   // re-anchor the running sum
+                    S = 0.0;
+                    for (int j = 0; j < w; ++j) S += (double)ring[j * B + tid];
+                }
+                const int64_t zo = zi - h;
+                if (zo >= z0) consume(zo * ncol + c, S * inv_w, (wb_out & kBlank) != 0, wb_out);
+            }
+        }
+    };
+
     if (active) {
-        if (!SPEC) {
-            for (int64_t zb = z0; zb < z1; zb += U) {
-                float xv[U];
-                uint8_t wv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t z = zb + u;
-                    xv[u] = 0.f;
-                    wv[u] = 0;
-                    if (z < z1) {
-                        const int64_t i = z * ncol + c;
-                        xv[u] = SRC == SRC_X ? a.x[i] : a.p[i];
-                        if (HASWM) wv[u] = a.wm_in[i];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t z = zb + u;
-                    if (z >= z1) break;
-                    const int64_t i = z * ncol + c;
-                    float v;
-                    bool blank;
-                    if (SRC == SRC_X) {
-                        blank = !isfinite(xv[u]);
-                        v = blank ? 0.f
-                                  : ((HASWM && a.repl_on && (wv[u] & kDet)) ? copysignf(rv, xv[u])
-                                                                            : xv[u]);
-                    } else {
-                        v = xv[u];
-                        blank = (wv[u] & kBlank) != 0;
-                    }
-                    consume(i, (double)v, blank, wv[u]);
-                }
-            }
-        } else {
-            const int w = a.w, h = a.h;
-            const double inv_w = 1.0 / (double)w;
-            // Ring slot j holds plane z0 - 1 - h + j: the window of z0 - 1.
-            double S = 0.0;
-            for (int j = 0; j < w; ++j) {
-                const int64_t zz = z0 - 1 - h + j;
-                const float v = (zz >= 0 && zz < nz) ? value(zz) : 0.f;
-                ring[j * B + tid] = v;
-                S += (double)v;
-            }
-            int slot = 0;
-            for (int64_t zb = z0; zb < z1; zb += U) {
-                float vn[U];
-                uint8_t wo[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t z = zb + u, zn = z + h;
-                    vn[u] = (z < z1 && zn < nz) ? value(zn) : 0.f;
-                    wo[u] = z < z1 ? a.wm_in[z * ncol + c] : (uint8_t)0;
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t z = zb + u;
-                    if (z >= z1) break;
-                    const float vo = ring[slot * B + tid];
-                    ring[slot * B + tid] = vn[u];
-                    S += (double)vn[u] - (double)vo;
-                    if (++slot == w) slot = 0;
-                    if (((z - z0) & 63) == 63) {   // re-anchor the running sum
-                        S = 0.0;
-                        for (int j = 0; j < w; ++j) S += (double)ring[j * B + tid];
-                    }
-                    consume(z * ncol + c, S * inv_w, (wo[u] & kBlank) != 0, wo[u]);
-                }
-            }
+        Group ga, gb;
+        load_group(zstart, ga);
+        for (int64_t zb = zstart; zb < zend; zb += 2 * U) {
+            if (zb + U < zend) load_group(zb + U, gb);
+            process_group(zb, ga);
+            if (zb + U >= zend) break;
+            if (zb + 2 * U < zend) load_group(zb + 2 * U, ga);
+            process_group(zb + U, gb);
         }
     }
 
@@ -389,6 +465,10 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         __syncthreads();
         for (int i = tid; i < kL1Bins; i += B)
             if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
+    } else if (OP == OP_HIST2) {
+        __syncthreads();
+        for (int i = tid; i < 2 * kL2Coarse; i += B)
+            if (hist[i]) atomicAdd(&a.hist2c[i], (unsigned long long)hist[i]);
     }
 }
 
@@ -541,8 +621,22 @@ hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s) {
 
 template <int R, int NIT>
 static hipError_t spatial_inst(const SpatialArgs &a, hipStream_t s) {
-    const int64_t blocks = (int64_t)a.tiles_x * a.tiles_y * a.nz;
-    hipLaunchKernelGGL((k_spatial<R, NIT>), dim3((unsigned)blocks), dim3(64), 0, s, a);
+    const int64_t n_int = (int64_t)a.ntx * a.nty;
+    const int64_t n_edge = (int64_t)a.tiles_x * a.tiles_y - n_int;
+    if (n_int > 0) {
+        SpatialArgs b = a;
+        b.tiles_per_plane = n_int;
+        hipLaunchKernelGGL((k_spatial<R, NIT, false>), dim3((unsigned)(n_int * a.nz)),
+                           dim3(64), 0, s, b);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_edge > 0) {
+        SpatialArgs b = a;
+        b.tiles_per_plane = n_edge;
+        hipLaunchKernelGGL((k_spatial<R, NIT, true>), dim3((unsigned)(n_edge * a.nz)),
+                           dim3(64), 0, s, b);
+    }
     return hipGetLastError();
 }
 
@@ -558,16 +652,18 @@ hipError_t launch_spatial(int n_iter, int radius, const SpatialArgs &a,
     return hipErrorInvalidValue;
 }
 
-size_t column_lds_bytes(int op, bool spectral, int w) {
+size_t column_lds_bytes(int src, int op, bool spectral, int w) {
     size_t b = 0;
     if (spectral) b += (size_t)w * kColThreads * sizeof(float);
+    if (spectral && src == SRC_X) b += ((size_t)w * kColThreads + 3) & ~(size_t)3;
     if (op == OP_HIST1) b += (size_t)kL1Bins * sizeof(unsigned);
+    if (op == OP_HIST2) b += (size_t)2 * kL2Coarse * sizeof(unsigned);
     return b;
 }
 
 template <int SRC, int OP, bool SPEC, bool HASWM>
 static hipError_t column_inst(const ColArgs &a, int nblocks, hipStream_t s) {
-    const size_t lds = column_lds_bytes(OP, SPEC, a.w);
+    const size_t lds = column_lds_bytes(SRC, OP, SPEC, a.w);
     hipLaunchKernelGGL((k_column<SRC, OP, SPEC, HASWM>), dim3(nblocks),
                        dim3(kColThreads), lds, s, a);
     return hipGetLastError();
