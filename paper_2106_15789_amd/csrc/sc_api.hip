@@ -18,17 +18,20 @@ using namespace sc;
 namespace {
 
 enum Family {
-    F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_HIST1, F_COL_HIST2,
-    F_COL_CLIP, F_COL_WRITE, F_FINALIZE, F_COUNT
+    F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
+    F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
+    F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
-    "init_mask", "fill", "spatial_cascade", "column_std", "column_hist1",
-    "column_hist2", "column_clip", "column_write", "finalize"};
+    "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
+    "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
+    "column_clip", "column_write", "finalize"};
 
 struct LaunchRec {
     int fam;
     double bytes, vox;
     hipEvent_t e0, e1;
+    int cond;   // >= 0: the launch only works if bit `cond` of DevState::fallback is set
 };
 
 struct Agg {
@@ -58,6 +61,8 @@ struct sofia_sc {
     double *part_sum = nullptr;
     unsigned long long *part_cnt = nullptr;
     size_t part_cap = 0;
+    uint32_t *cap_buf = nullptr;
+    size_t cap_cap = 0;
     bool prof = false;
     std::vector<LaunchRec> recs;
     std::vector<hipEvent_t> pool;
@@ -66,11 +71,27 @@ struct sofia_sc {
 
 namespace {
 
-constexpr size_t kHistWords = (size_t)kL1Bins + 2 * (size_t)kL2Coarse + 2 * (size_t)kL2Bins;
+// Histogram workspace, zeroed before every MAD measurement: level 1 |
+// level-2 coarse | level 2 | sampled level 1 | capture count | selection counts.
+constexpr size_t kOffL2c = kL1Bins;
+constexpr size_t kOffL2 = kOffL2c + 2 * (size_t)kL2Coarse;
+constexpr size_t kOffSample = kOffL2 + 2 * (size_t)kL2Bins;
+constexpr size_t kOffCapCount = kOffSample + kL1Bins;
+constexpr size_t kOffSelCounts = kOffCapCount + 2;
+constexpr size_t kHistWords = kOffSelCounts + 2;
+// Columns blocks visited by the sampling pass: every 17th (a stride coprime
+// to the usual blocks-per-row counts spreads the sample over x and y).
+constexpr int kSampleStride = 17;
 
 unsigned long long *hist1_of(sofia_sc *h) { return h->hist; }
-unsigned long long *hist2c_of(sofia_sc *h) { return h->hist + kL1Bins; }
-unsigned long long *hist2_of(sofia_sc *h) { return h->hist + kL1Bins + 2 * kL2Coarse; }
+unsigned long long *hist2c_of(sofia_sc *h) { return h->hist + kOffL2c; }
+unsigned long long *hist2_of(sofia_sc *h) { return h->hist + kOffL2; }
+unsigned long long *hist_s_of(sofia_sc *h) { return h->hist + kOffSample; }
+unsigned long long *cap_count_of(sofia_sc *h) { return h->hist + kOffCapCount; }
+unsigned long long *sel_counts_of(sofia_sc *h) { return h->hist + kOffSelCounts; }
+
+// Capture buffer: up to N/8 keys (at least 2^20).
+size_t capture_capacity(int64_t N) { return std::max<size_t>((size_t)N / 8, (size_t)1 << 20); }
 
 int fail(sofia_sc *h, int code, const std::string &msg) {
     if (h) h->err = msg;
@@ -195,6 +216,15 @@ int ensure_workspace(sofia_sc *h, int64_t N, bool need_p, size_t parts) {
             return fail(h, SOFIA_SC_ENOMEM, std::string("plane buffer: ") + hipGetErrorString(e));
         h->p_cap = (size_t)N;
     }
+    const size_t cap = capture_capacity(N);
+    if (cap > h->cap_cap) {
+        if (h->cap_buf) (void)hipFree(h->cap_buf);
+        h->cap_buf = nullptr;
+        h->cap_cap = 0;
+        if ((e = hipMalloc(&h->cap_buf, cap * sizeof(uint32_t))) != hipSuccess)
+            return fail(h, SOFIA_SC_ENOMEM, std::string("capture buffer: ") + hipGetErrorString(e));
+        h->cap_cap = cap;
+    }
     if (parts > h->part_cap) {
         if (h->part_sum) (void)hipFree(h->part_sum);
         if (h->part_cnt) (void)hipFree(h->part_cnt);
@@ -223,7 +253,8 @@ hipEvent_t take_event(sofia_sc *h) {
 }
 
 template <typename F>
-int launch(sofia_sc *h, hipStream_t s, int fam, double bytes, double vox, F &&f) {
+int launch(sofia_sc *h, hipStream_t s, int fam, double bytes, double vox, F &&f,
+           int cond = -1) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->prof) {
         e0 = take_event(h);
@@ -234,7 +265,7 @@ int launch(sofia_sc *h, hipStream_t s, int fam, double bytes, double vox, F &&f)
     if (e != hipSuccess) return hip_fail(h, e, kFamilyName[fam]);
     if (h->prof && e0 && e1) {
         (void)hipEventRecord(e1, s);
-        h->recs.push_back({fam, bytes, vox, e0, e1});
+        h->recs.push_back({fam, bytes, vox, e0, e1, cond});
     }
     return SOFIA_SC_OK;
 }
@@ -244,7 +275,9 @@ void collect_profile(sofia_sc *h) {
     for (auto &r : h->recs) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
-            Agg &a = h->agg[r.fam];
+            const bool skipped = r.cond >= 0 && !((h->st_host->fallback >> r.cond) & 1ull);
+            Agg &a = h->agg[skipped ? F_FALLBACK_SKIPPED : r.fam];
+            if (skipped) { r.bytes = 0; r.vox = 0; }
             a.launches += 1;
             a.ms += ms;
             a.bytes += r.bytes;
@@ -335,6 +368,11 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     c.hist1 = hist1_of(h);
     c.hist2 = hist2_of(h);
     c.hist2c = hist2c_of(h);
+    c.cb_stride = 1;
+    c.cap_buf = h->cap_buf;
+    c.cap_count = cap_count_of(h);
+    c.cap_capacity = (unsigned long long)h->cap_cap;
+    c.sel_counts = sel_counts_of(h);
     const int src = spatial ? SRC_P : SRC_X;
     const double rd = N * (4.0 + (has_wm ? 1.0 : 0.0));
     auto col = [&](int op, int fam, double bytes) {
@@ -356,19 +394,78 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         });
         if (rc) return rc;
     } else {
+        // Exact MAD. A sample of columns predicts the median; one pass counts
+        // the selected voxels and those below a window around the prediction
+        // and captures the keys inside it; the two central order statistics
+        // are then found among the captured keys (radix walk, 12+10+9 bits).
+        // If the window missed them, full level-1 and level-2 passes over the
+        // cube run instead (each launch checks the flag and exits otherwise).
         rc = launch(h, s, F_FILL, 8.0 * kHistWords, 0, [&] {
             return launch_fill_u64(h->hist, (int64_t)kHistWords, s);
         });
         if (rc) return rc;
-        if ((rc = col(OP_HIST1, F_COL_HIST1, rd))) return rc;
+        {
+            // The sample touches 1/17 of the columns: split z finer so the
+            // launch still has a few blocks per CU.
+            ColArgs cs = c;
+            cs.cb_stride = kSampleStride;
+            cs.ncb = (g.ncb + kSampleStride - 1) / kSampleStride;
+            cs.hist1 = hist_s_of(h);
+            int nzc = (int)std::min<int64_t>((2048 + cs.ncb - 1) / cs.ncb,
+                                             std::max<int64_t>(1, d.nz / 32));
+            nzc = std::max(nzc, 1);
+            cs.zchunk = (int)((d.nz + nzc - 1) / nzc);
+            nzc = (int)((d.nz + cs.zchunk - 1) / cs.zchunk);
+            const int nb = cs.ncb * nzc;
+            rc = launch(h, s, F_COL_SAMPLE, rd * cs.ncb / g.ncb, N * cs.ncb / g.ncb, [&] {
+                return launch_column(src, OP_HIST1, spec, has_wm, cs, nb, s);
+            });
+            if (rc) return rc;
+        }
+        rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
+            return launch_finalize_predict(h->st, hist_s_of(h), s);
+        });
+        if (rc) return rc;
+        if ((rc = col(OP_SELECT, F_COL_SELECT, rd))) return rc;
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
+            return launch_finalize_select(h->st, sel_counts_of(h), cap_count_of(h),
+                                          (unsigned long long)h->cap_cap, j.k, s);
+        });
+        if (rc) return rc;
+        const int cond = j.k >= 0 ? j.k : 63;
+        rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
+            return launch_capture_l1(h->st, h->cap_buf, cap_count_of(h), hist1_of(h), s);
+        });
+        if (rc) return rc;
+        c.skip_if_captured = 1;
+        rc = launch(h, s, F_COL_HIST1, rd, N, [&] {
+            return launch_column(src, OP_HIST1, spec, has_wm, c, g.blocks(), s);
+        }, cond);
+        if (rc) return rc;
         rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
             return launch_finalize_mad1(h->st, hist1_of(h), s);
         });
         if (rc) return rc;
-        if ((rc = col(OP_HIST2, F_COL_HIST2, rd))) return rc;
-        rc = launch(h, s, F_FINALIZE, 8.0 * (2 * kL2Coarse + 2 * kL2Fine), 0, [&] {
-            return launch_finalize_mad2(h->st, hist2_of(h), hist2c_of(h), j.k, j.t,
-                                        j.also_sigma0 ? 1 : 0, s);
+        rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
+            return launch_capture_coarse(h->st, h->cap_buf, cap_count_of(h), hist2c_of(h), s);
+        });
+        if (rc) return rc;
+        rc = launch(h, s, F_COL_HIST2, rd, N, [&] {
+            return launch_column(src, OP_HIST2, spec, has_wm, c, g.blocks(), s);
+        }, cond);
+        c.skip_if_captured = 0;
+        if (rc) return rc;
+        rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Coarse, 0, [&] {
+            return launch_finalize_mad2a(h->st, hist2c_of(h), s);
+        });
+        if (rc) return rc;
+        rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
+            return launch_capture_fine(h->st, h->cap_buf, cap_count_of(h), hist2_of(h), s);
+        });
+        if (rc) return rc;
+        rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Fine, 0, [&] {
+            return launch_finalize_mad2b(h->st, hist2_of(h), j.k, j.t,
+                                         j.also_sigma0 ? 1 : 0, s);
         });
         if (rc) return rc;
     }
@@ -517,6 +614,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->hist) (void)hipFree(h->hist);
         if (h->part_sum) (void)hipFree(h->part_sum);
         if (h->part_cnt) (void)hipFree(h->part_cnt);
+        if (h->cap_buf) (void)hipFree(h->cap_buf);
     }
     delete h;
 }

@@ -39,12 +39,23 @@ struct DevState {
     unsigned long long rank[2];  // residual ranks inside the level-1 bins
     uint32_t bin[2];        // level-1 bins holding ranks floor((m-1)/2), floor(m/2)
     int32_t status;         // nonzero: some noise had no selected voxel
-    int32_t pad;
+    int32_t use_capture;    // order statistics resolved from the captured keys
+    uint32_t klo, khi;      // captured key window [klo, khi] (bit patterns of |s|)
+    unsigned long long below;  // selected keys below klo (capture path), else 0
+    uint32_t cbin[2];       // level-2 coarse bins (bits 18..9) of the two ranks
+    unsigned long long crank[2];  // residual ranks inside the coarse bins
+    unsigned long long fallback;  // bit k: kernel k needed the full level-2 pass
     double sigma[SOFIA_SC_MAX_KERNELS];
 };
 
+// Keys captured per wave in LDS before one bulk append to global memory:
+// room for the flush threshold plus one whole group of planes (every lane
+// of the wave may capture on every plane of a group).
+constexpr int kCapFlushAt = 256;
+constexpr int kCapPerWave(int group) { return kCapFlushAt + 64 * group; }
+
 enum Src { SRC_X = 0, SRC_P = 1 };
-enum Op { OP_STD = 0, OP_HIST1 = 1, OP_HIST2 = 2, OP_CLIP = 3, OP_WRITE = 4 };
+enum Op { OP_STD = 0, OP_HIST1 = 1, OP_HIST2 = 2, OP_CLIP = 3, OP_WRITE = 4, OP_SELECT = 5 };
 
 // Arguments of the column-streaming kernel (spectral boxcar + one of the
 // per-voxel operations). One thread owns one (x, y) column and streams z.
@@ -70,6 +81,12 @@ struct ColArgs {
     unsigned long long *hist1;   // [kL1Bins]
     unsigned long long *hist2;   // [2][kL2Bins]
     unsigned long long *hist2c;  // [2][kL2Coarse]
+    int32_t cb_stride;           // column blocks visited: every cb_stride-th
+    int32_t skip_if_captured;    // OP_HIST1/2: do nothing when st->use_capture
+    uint32_t *cap_buf;           // OP_SELECT: captured keys
+    unsigned long long *cap_count;
+    unsigned long long cap_capacity;
+    unsigned long long *sel_counts;  // OP_SELECT: [selected voxels, keys below klo]
 };
 
 struct SpatialArgs {
@@ -100,9 +117,24 @@ hipError_t launch_finalize_std(DevState *st, const double *part_sum,
                                int k, double t, int also_sigma0, hipStream_t s);
 hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
                                 hipStream_t s);
-hipError_t launch_finalize_mad2(DevState *st, const unsigned long long *hist2,
-                                const unsigned long long *hist2c, int k, double t,
-                                int also_sigma0, hipStream_t s);
+hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_counts,
+                                  const unsigned long long *cap_count,
+                                  unsigned long long cap_capacity, int k, hipStream_t s);
+hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
+                             const unsigned long long *cap_count,
+                             unsigned long long *hist1, hipStream_t s);
+hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_s,
+                                   hipStream_t s);
+hipError_t launch_capture_coarse(const DevState *st, const uint32_t *cap_buf,
+                                 const unsigned long long *cap_count,
+                                 unsigned long long *hist2c, hipStream_t s);
+hipError_t launch_capture_fine(const DevState *st, const uint32_t *cap_buf,
+                               const unsigned long long *cap_count,
+                               unsigned long long *hist2, hipStream_t s);
+hipError_t launch_finalize_mad2a(DevState *st, const unsigned long long *hist2c,
+                                 hipStream_t s);
+hipError_t launch_finalize_mad2b(DevState *st, const unsigned long long *hist2, int k,
+                                 double t, int also_sigma0, hipStream_t s);
 hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s);
 
 // Threads per block of the column kernel, and its dynamic LDS size.

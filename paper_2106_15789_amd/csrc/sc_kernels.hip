@@ -68,6 +68,11 @@ __global__ void k_set_sigma0(DevState *st, double sigma0) {
         st->status = 0;
         st->thr = 0.0;
         st->m = 0;
+        st->use_capture = 0;
+        st->klo = 1u;
+        st->khi = 0u;
+        st->below = 0ull;
+        st->fallback = 0ull;
         for (int k = 0; k < SOFIA_SC_MAX_KERNELS; ++k) st->sigma[k] = NAN;
     }
 }
@@ -272,41 +277,54 @@ struct ColAcc {
 // One thread per (x, y) column. The column is streamed as a sequence of
 // input planes zi = z0 - h .. z1 - 1 + h (the leading edge of the spectral
 // window); after input zi the window sum S covers planes zi - 2h .. zi, i.e.
-// the output plane z = zi - h. Inputs are fetched in groups of U planes and
+// the output plane z = zi - h. Inputs are fetched in groups of G planes and
 // the next group is requested before the current one is consumed, so every
-// wave keeps up to 2U plane reads in flight.
+// wave keeps up to 2G plane reads in flight. Every plane access of a block is
+// one contiguous run of 256 voxels: a uniform row pointer plus the lane.
 //
-// Ring buffers (LDS, one slot per thread per plane of the window): the FP32
-// inputs of the window, for the running sum; with SRC_X also the working-mask
-// byte read at the leading edge, reused when that plane becomes the output.
-template <int SRC, int OP, bool SPEC, bool HASWM>
+// W is the spectral width: 1 = no spectral smoothing; an odd W >= 3 keeps the
+// window in registers with compile-time ring slots (G is a multiple of W, so
+// every group starts at slot 0); W = 0 takes the width at run time and keeps
+// the window ring in LDS. The window sum is an FP64 running sum of the FP32
+// inputs (exact while the inputs span fewer than 2^29 ulps), recomputed from
+// the ring every eight groups.
+template <int W>
+struct ColGroup {
+    static constexpr int G = W >= 3 ? W * ((8 + W - 1) / W) : 8;
+};
+
+template <int SRC, int OP, bool HASWM, int W>
 __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     extern __shared__ float dyn_lds[];
     constexpr int B = kColThreads;
-    constexpr int U = 8;
+    constexpr bool SPEC = W != 1;
+    constexpr bool LDSRING = W == 0;
+    constexpr int G = ColGroup<W>::G;
     const int tid = threadIdx.x;
-    const int cb = (int)(blockIdx.x % (unsigned)a.ncb);
+    if ((OP == OP_HIST1 || OP == OP_HIST2) && a.skip_if_captured && a.st->use_capture) return;
+    const int cb = (int)(blockIdx.x % (unsigned)a.ncb) * a.cb_stride;
     const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
-    const int64_t c = (int64_t)cb * B + tid;
-    const bool active = c < a.ncol;
-    const int64_t ncol = a.ncol, nz = a.nz;
-    const int64_t z0 = (int64_t)zc * a.zchunk;
-    const int64_t z1 = min(nz, z0 + (int64_t)a.zchunk);
-    const int w = SPEC ? a.w : 1;
-    const int h = SPEC ? a.h : 0;
+    const int64_t ncol = a.ncol;
+    const int64_t col0 = (int64_t)cb * B;
+    const bool active = col0 + tid < ncol;
+    const int nz = (int)a.nz;
+    const int z0 = zc * a.zchunk;
+    const int z1 = min(nz, z0 + a.zchunk);
+    const int w = W == 0 ? a.w : (W >= 3 ? W : 1);
+    const int h = (w - 1) / 2;
 
-    // LDS layout: float ring [w][B] | byte ring [w][B] (SRC_X, SPEC) | histogram
-    float *ring = dyn_lds;
-    uint8_t *bring = (uint8_t *)(dyn_lds + (SPEC ? w * B : 0));
-    unsigned *hist = (unsigned *)(bring + ((SPEC && SRC == SRC_X) ? ((w * B + 3) & ~3) : 0));
+    // LDS: [ring floats [w][B] | ring bytes [w][B] (W = 0 only)] | histogram | capture
+    float *lring = dyn_lds;
+    uint8_t *lbring = (uint8_t *)(dyn_lds + (LDSRING ? w * B : 0));
+    unsigned *hist = (unsigned *)(lbring + ((LDSRING && SRC == SRC_X) ? ((w * B + 3) & ~3) : 0));
     constexpr int kHistWords = OP == OP_HIST1 ? kL1Bins : (OP == OP_HIST2 ? 2 * kL2Coarse : 0);
     if (kHistWords) {
         for (int i = tid; i < kHistWords; i += B) hist[i] = 0u;
     }
-    if (SPEC) {
+    if (LDSRING) {
         for (int j = 0; j < w; ++j) {
-            ring[j * B + tid] = 0.f;
-            if (SRC == SRC_X) bring[j * B + tid] = 0;
+            lring[j * B + tid] = 0.f;
+            if (SRC == SRC_X) lbring[j * B + tid] = 0;
         }
     }
     if (kHistWords) __syncthreads();
@@ -320,13 +338,59 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     ColAcc acc{0.0, 0ull};
     const float *src = SRC == SRC_X ? a.x : a.p;
 
-    auto consume = [&](int64_t i, double s, bool blank, uint8_t wb) {
+    // Selection pass: count the selected voxels and the keys below the
+    // predicted window [klo, khi], and append the keys inside it, per wave, to
+    // an LDS buffer that is flushed to the global key list with one atomic
+    // per flush.
+    constexpr bool capture = OP == OP_SELECT;
+    uint32_t klo = 1, khi = 0;
+    if (capture) { klo = a.st->klo; khi = a.st->khi; }
+    unsigned n_sel = 0, n_below = 0;
+    uint32_t *capw = (uint32_t *)(hist + kHistWords) + (tid >> 6) * kCapPerWave(G);
+    int fill = 0;   // entries in this wave's buffer (same in every lane)
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long act = __ballot(1);
+        const int leader = __ffsll((long long)act) - 1;
+        const int wlane = tid & 63;
+        unsigned long long base = 0;
+        if (wlane == leader) base = atomicAdd(a.cap_count, (unsigned long long)fill);
+        const uint32_t lo32 = __shfl((uint32_t)base, leader);
+        const uint32_t hi32 = __shfl((uint32_t)(base >> 32), leader);
+        base = ((unsigned long long)hi32 << 32) | lo32;
+        // copy with the lanes that are active (a wave may be partly idle)
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+        const int nact = __popcll(act);
+        for (int i = rank; i < fill; i += nact)
+            if (base + i < a.cap_capacity) a.cap_buf[base + i] = capw[i];
+        __builtin_amdgcn_wave_barrier();
+        fill = 0;
+    };
+
+    // Per-voxel operation on the smoothed value s of output plane zo.
+    auto consume = [&](int zo, double s, bool blank, uint8_t wb) {
         if (OP == OP_STD) {
             if (!blank && in_flux_range(s, range)) { acc.sum += s * s; acc.cnt += 1; }
         } else if (OP == OP_HIST1) {
             if (!blank && in_flux_range(s, range)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
+            }
+        } else if (OP == OP_SELECT) {
+            const bool sel = !blank && in_flux_range(s, range);
+            const uint32_t key = __float_as_uint(fabsf((float)s));
+            n_sel += sel ? 1u : 0u;
+            n_below += (sel && key < klo) ? 1u : 0u;
+            const bool want = sel && key >= klo && key <= khi;
+            const unsigned long long bal = __ballot(want);
+            if (bal) {
+                if (want) {
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    capw[fill + below] = key;
+                }
+                fill += __popcll(bal);
             }
         } else if (OP == OP_HIST2) {
             if (!blank && in_flux_range(s, range)) {
@@ -347,9 +411,9 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             uint8_t out;
             if (a.out_user) out = (uint8_t)((wb & kDet) | det);
             else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
-            a.mask_out[i] = out;
+            (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
         } else {  // OP_WRITE
-            a.s_out[i] = blank ? NAN : (float)s;
+            (a.s_out + (int64_t)zo * ncol + col0)[tid] = blank ? NAN : (float)s;
         }
     };
 
@@ -361,92 +425,104 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     };
 
     struct Group {
-        float v[U];
-        uint8_t b[U];
+        float v[G];
+        uint8_t b[G];    // working-mask byte of the input plane (SRC_X) or of
+                         // the output plane (SRC_P)
     };
-    // Input planes zi = zb .. zb + U - 1 (SPEC) or output planes (not SPEC).
-    auto load_group = [&](int64_t zb, Group &g) {
+    const int zs = SPEC ? z0 - h : z0;
+    const int ze = SPEC ? z1 + h : z1;   // exclusive
+    auto load_group = [&](int zb, Group &g) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t zi = zb + u;
-            g.v[u] = 0.f;
-            g.b[u] = 0;
-            if (!SPEC) {
-                if (zi < z1) {
-                    const int64_t i = zi * ncol + c;
-                    g.v[u] = src[i];
-                    if (HASWM) g.b[u] = a.wm_in[i];
-                }
-            } else {
-                const bool in_run = zi < z1 + h;
-                if (in_run && zi >= 0 && zi < nz) {
-                    const int64_t i = zi * ncol + c;
-                    g.v[u] = src[i];
-                    if (SRC == SRC_X) g.b[u] = a.wm_in[i];
-                }
-                if (SRC == SRC_P) {
-                    const int64_t zo = zi - h;
-                    if (in_run && zo >= z0) g.b[u] = a.wm_in[zo * ncol + c];
-                }
+        for (int j = 0; j < G; ++j) {
+            const int zi = zb + j;
+            g.v[j] = 0.f;
+            g.b[j] = 0;
+            if (zi < ze && zi >= 0 && zi < nz) {
+                const int64_t off = (int64_t)zi * ncol + col0;
+                g.v[j] = (src + off)[tid];
+                if (SRC == SRC_X && HASWM) g.b[j] = (a.wm_in + off)[tid];
+            }
+            if (SRC == SRC_P) {
+                const int zo = zi - h;
+                if (zi < ze && zo >= z0) g.b[j] = (a.wm_in + (int64_t)zo * ncol + col0)[tid];
             }
         }
     };
 
-    double S = 0.0;
-    int slot = 0;
-    const double inv_w = SPEC ? 1.0 / (double)w : 1.0;
-    const int64_t zstart = SPEC ? z0 - h : z0;
-    const int64_t zend = SPEC ? z1 + h : z1;   // exclusive
-    int64_t step = 0;
-
-    auto process_group = [&](int64_t zb, const Group &g) {
+    float ring[W >= 3 ? W : 1];
+    uint8_t bring[W >= 3 ? W : 1];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t zi = zb + u;
-            if (zi >= zend) break;
+    for (int j = 0; j < (W >= 3 ? W : 1); ++j) { ring[j] = 0.f; bring[j] = 0; }
+    int lslot = 0;           // W = 0: LDS ring slot of the next input
+    double S = 0.0;
+    const double inv_w = 1.0 / (double)w;
+    int groups = 0;
+
+    auto process_group = [&](int zb, const Group &g) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int zi = zb + j;
+            if (zi >= ze) break;
             if (!SPEC) {
-                const int64_t i = zi * ncol + c;
                 if (SRC == SRC_X) {
-                    const bool blank = !isfinite(g.v[u]);
-                    consume(i, (double)raw_value(g.v[u], g.b[u]), blank, g.b[u]);
+                    const bool blank = !isfinite(g.v[j]);
+                    consume(zi, (double)raw_value(g.v[j], g.b[j]), blank, g.b[j]);
                 } else {
-                    consume(i, (double)g.v[u], (g.b[u] & kBlank) != 0, g.b[u]);
+                    consume(zi, (double)g.v[j], (g.b[j] & kBlank) != 0, g.b[j]);
                 }
-            } else {
-                const float vn = SRC == SRC_X ? raw_value(g.v[u], g.b[u]) : g.v[u];
-                const float vo = ring[slot * B + tid];
-                ring[slot * B + tid] = vn;
-                uint8_t wb_out;
+                continue;
+            }
+            const float vn = SRC == SRC_X ? raw_value(g.v[j], g.b[j]) : g.v[j];
+            float vo;
+            uint8_t wb_out = g.b[j];
+            if (LDSRING) {
+                vo = lring[lslot * B + tid];
+                lring[lslot * B + tid] = vn;
                 if (SRC == SRC_X) {
-                    bring[slot * B + tid] = g.b[u];
-                    int os = slot + h + 1;
+                    lbring[lslot * B + tid] = g.b[j];
+                    int os = lslot + h + 1;
                     if (os >= w) os -= w;
-                    wb_out = bring[os * B + tid];
-                } else {
-                    wb_out = g.b[u];
+                    wb_out = lbring[os * B + tid];
                 }
-                S += (double)vn - (double)vo;
-                if (++slot == w) slot = 0;
-                if ((++step & 63) == 0) {   // re-anchor the running sum
-                    S = 0.0;
-                    for (int j = 0; j < w; ++j) S += (double)ring[j * B + tid];
+                if (++lslot == w) lslot = 0;
+            } else {
+                constexpr int kW = W >= 3 ? W : 1;
+                const int sl = j % kW;
+                vo = ring[sl];
+                ring[sl] = vn;
+                if (SRC == SRC_X) {
+                    bring[sl] = g.b[j];
+                    wb_out = bring[(j + kW - (kW - 1) / 2) % kW];
                 }
-                const int64_t zo = zi - h;
-                if (zo >= z0) consume(zo * ncol + c, S * inv_w, (wb_out & kBlank) != 0, wb_out);
+            }
+            S += (double)vn - (double)vo;
+            const int zo = zi - h;
+            if (zo >= z0) consume(zo, S * inv_w, (wb_out & kBlank) != 0, wb_out);
+        }
+        // The buffer holds one more group on top of kCapFlushAt entries.
+        if (capture && fill > kCapFlushAt) flush();
+        if (SPEC && (++groups & 7) == 0) {   // re-anchor the running sum
+            S = 0.0;
+            if (LDSRING) {
+                for (int j = 0; j < w; ++j) S += (double)lring[j * B + tid];
+            } else {
+#pragma unroll
+                for (int j = 0; j < (W >= 3 ? W : 1); ++j) S += (double)ring[j];
             }
         }
     };
 
     if (active) {
         Group ga, gb;
-        load_group(zstart, ga);
-        for (int64_t zb = zstart; zb < zend; zb += 2 * U) {
-            if (zb + U < zend) load_group(zb + U, gb);
+        load_group(zs, ga);
+        for (int zb = zs; zb < ze; zb += 2 * G) {
+            if (zb + G < ze) load_group(zb + G, gb);
             process_group(zb, ga);
-            if (zb + U >= zend) break;
-            if (zb + 2 * U < zend) load_group(zb + 2 * U, ga);
-            process_group(zb + U, gb);
+            if (zb + G >= ze) break;
+            if (zb + 2 * G < ze) load_group(zb + 2 * G, ga);
+            process_group(zb + G, gb);
         }
+        if (capture && fill > 0) flush();
     }
 
     if (OP == OP_STD) {
@@ -465,6 +541,19 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         __syncthreads();
         for (int i = tid; i < kL1Bins; i += B)
             if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
+    } else if (OP == OP_SELECT) {
+        __shared__ unsigned long long rc[2][B];
+        rc[0][tid] = n_sel;
+        rc[1][tid] = n_below;
+        __syncthreads();
+        for (int off = B / 2; off > 0; off >>= 1) {
+            if (tid < off) { rc[0][tid] += rc[0][tid + off]; rc[1][tid] += rc[1][tid + off]; }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (rc[0][0]) atomicAdd(&a.sel_counts[0], rc[0][0]);
+            if (rc[1][0]) atomicAdd(&a.sel_counts[1], rc[1][0]);
+        }
     } else if (OP == OP_HIST2) {
         __syncthreads();
         for (int i = tid; i < 2 * kL2Coarse; i += B)
@@ -513,30 +602,31 @@ __global__ __launch_bounds__(256) void k_finalize_std(
     }
 }
 
-// Level 1: locate the bins holding order statistics floor((m-1)/2) and
-// floor(m/2) of the selected |s| and the ranks left inside them.
+// Level 1: locate the level-1 bins holding order statistics floor((m-1)/2)
+// and floor(m/2) of the selected |s|, and the ranks left inside them. The
+// histogram counts either every selected key (full pass; below = 0) or only
+// the captured keys, which sit above `below` smaller ones.
 __global__ __launch_bounds__(256) void k_finalize_mad1(
     DevState *st, const unsigned long long *hist1) {
     __shared__ unsigned long long buf[256];
     constexpr int PER = kL1Bins / 256;
     const int tid = threadIdx.x;
+    const unsigned long long m = st->m;
+    if (tid == 0) {
+        st->bin[0] = st->bin[1] = 0xffffffffu;
+        st->rank[0] = st->rank[1] = 0ull;
+    }
+    __syncthreads();
+    if (m == 0) return;
     unsigned long long loc[PER];
     unsigned long long tot = 0;
 #pragma unroll
     for (int j = 0; j < PER; ++j) { loc[j] = hist1[tid * PER + j]; tot += loc[j]; }
     const unsigned long long incl = block_scan_incl(tot, buf);
     const unsigned long long excl = incl - tot;
-    const unsigned long long m = buf[255];
-    if (tid == 0) {
-        st->m = m;
-        st->bin[0] = st->bin[1] = 0xffffffffu;
-        st->rank[0] = st->rank[1] = 0ull;
-        if (m == 0) st->status |= 1;
-    }
-    __syncthreads();
-    if (m == 0) return;
+    const unsigned long long below = st->below;
     for (int q = 0; q < 2; ++q) {
-        const unsigned long long r = q ? m / 2 : (m - 1) / 2;
+        const unsigned long long r = (q ? m / 2 : (m - 1) / 2) - below;
         if (r >= excl && r < incl) {
             unsigned long long run = excl;
             for (int j = 0; j < PER; ++j) {
@@ -551,37 +641,203 @@ __global__ __launch_bounds__(256) void k_finalize_mad1(
     }
 }
 
-// Level 2: walk the coarse then the fine histogram of each wanted bin to the
-// exact key, and turn the two order statistics into sigma = 1.4826 x median.
-__global__ __launch_bounds__(1024) void k_finalize_mad2(
-    DevState *st, const unsigned long long *hist2,
-    const unsigned long long *hist2c, int k, double t, int also0) {
-    __shared__ unsigned long long buf[1024];
-    __shared__ uint32_t key[2];
-    __shared__ uint32_t cbin;
-    __shared__ unsigned long long crank;
+// After the selection pass: the captured keys decide the order statistics
+// when the count below the window and the captured count bracket both ranks
+// (and nothing was dropped); otherwise the full level-1/level-2 passes run.
+__global__ void k_finalize_select(DevState *st, const unsigned long long *sel_counts,
+                                  const unsigned long long *cap_count,
+                                  unsigned long long cap_capacity, int k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long m = sel_counts[0], below = sel_counts[1], cin = *cap_count;
+    st->m = m;
+    st->below = 0ull;
+    if (m == 0) {                 // no voxel in the flux range
+        st->status |= 1;
+        st->use_capture = 1;      // nothing to select: skip every later pass
+        return;
+    }
+    const unsigned long long r_lo = (m - 1) / 2, r_hi = m / 2;
+    const bool ok = cin <= cap_capacity && below <= r_lo && r_hi < below + cin;
+    st->use_capture = ok ? 1 : 0;
+    if (ok) st->below = below;
+    else st->fallback |= 1ull << (k >= 0 ? k : 63);
+}
+
+// Predict the median of |s| from the level-1 histogram of a sample of
+// columns (linear interpolation inside the bin that holds each central rank)
+// and set the capture window to that estimate -/+ delta, with
+// delta = 2 % + 3 / sqrt(sample size).
+__global__ __launch_bounds__(256) void k_finalize_predict(
+    DevState *st, const unsigned long long *hist_s) {
+    __shared__ unsigned long long buf[256];
+    __shared__ float est[2];
+    constexpr int PER = kL1Bins / 256;
     const int tid = threadIdx.x;
-    const unsigned long long m = st->m;
-    if (m == 0) {
+    unsigned long long loc[PER];
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) { loc[j] = hist_s[tid * PER + j]; tot += loc[j]; }
+    const unsigned long long incl = block_scan_incl(tot, buf);
+    const unsigned long long excl = incl - tot;
+    const unsigned long long m = buf[255];
+    if (tid == 0) { est[0] = 0.f; est[1] = 0.f; }
+    __syncthreads();
+    if (m > 0) {
+        for (int q = 0; q < 2; ++q) {
+            const unsigned long long r = q ? m / 2 : (m - 1) / 2;
+            if (r >= excl && r < incl) {
+                unsigned long long run = excl;
+                for (int j = 0; j < PER; ++j) {
+                    if (r < run + loc[j]) {
+                        const double f = ((double)(r - run) + 0.5) / (double)loc[j];
+                        const uint32_t b = (uint32_t)(tid * PER + j);
+                        const uint32_t key =
+                            (b << kL1Shift) + (uint32_t)(f * (double)(1u << kL1Shift));
+                        est[q] = __uint_as_float(key);
+                        break;
+                    }
+                    run += loc[j];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (m == 0) {   // empty sample: capture nothing; the full passes decide
+            st->klo = 1u;
+            st->khi = 0u;
+        } else {
+            const double delta = 0.02 + 3.0 / sqrt((double)m);
+            const double lo = (double)est[0] * (1.0 - delta);
+            const double hi = (double)est[1] * (1.0 + delta);
+            st->klo = lo > 0.0 ? __float_as_uint((float)lo) : 0u;
+            st->khi = hi < 3.0e38 ? __float_as_uint((float)hi) : 0x7f800000u;
+        }
+    }
+}
+
+// Level-1 histogram of the captured keys (capture path only).
+__global__ __launch_bounds__(256) void k_capture_l1(
+    const DevState *st, const uint32_t *cap_buf, const unsigned long long *cap_count,
+    unsigned long long *hist1) {
+    if (!st->use_capture || st->m == 0) return;
+    __shared__ unsigned hl[kL1Bins];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kL1Bins; i += 256) hl[i] = 0u;
+    __syncthreads();
+    const unsigned long long n = *cap_count;
+    const unsigned long long stride = (unsigned long long)gridDim.x * 256;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + tid; i < n; i += stride)
+        atomicAdd(&hl[cap_buf[i] >> kL1Shift], 1u);
+    __syncthreads();
+    for (int i = tid; i < kL1Bins; i += 256)
+        if (hl[i]) atomicAdd(&hist1[i], (unsigned long long)hl[i]);
+}
+
+// Level 2 from the captured keys (instead of a second pass over the cube),
+// when the median bins fell inside the captured window. Two short passes
+// over the key list with LDS histograms: first the coarse digit (bits
+// 18..9) of the keys in each wanted level-1 bin, then, once the coarse bin
+// of each order statistic is known, the fine digit (bits 8..0) of the keys
+// in that coarse bin. The counts land in the same arrays the full level-2
+// pass fills, so the rank walk is shared.
+__global__ __launch_bounds__(256) void k_capture_coarse(
+    const DevState *st, const uint32_t *cap_buf, const unsigned long long *cap_count,
+    unsigned long long *hist2c) {
+    if (!st->use_capture || st->m == 0) return;
+    __shared__ unsigned hc[2 * kL2Coarse];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 2 * kL2Coarse; i += 256) hc[i] = 0u;
+    __syncthreads();
+    const uint32_t b0 = st->bin[0], b1 = st->bin[1];
+    const unsigned long long n = *cap_count;
+    const unsigned long long stride = (unsigned long long)gridDim.x * 256;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + tid; i < n; i += stride) {
+        const uint32_t key = cap_buf[i];
+        const uint32_t k1 = key >> kL1Shift;
+        const uint32_t cbin = (key & (kL2Bins - 1)) >> kL2CoarseShift;
+        if (k1 == b0) atomicAdd(&hc[cbin], 1u);
+        if (k1 == b1 && b1 != b0) atomicAdd(&hc[kL2Coarse + cbin], 1u);
+    }
+    __syncthreads();
+    for (int i = tid; i < 2 * kL2Coarse; i += 256)
+        if (hc[i]) atomicAdd(&hist2c[i], (unsigned long long)hc[i]);
+}
+
+__global__ __launch_bounds__(256) void k_capture_fine(
+    const DevState *st, const uint32_t *cap_buf, const unsigned long long *cap_count,
+    unsigned long long *hist2) {
+    if (!st->use_capture || st->m == 0) return;
+    __shared__ unsigned hf[2 * kL2Fine];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 2 * kL2Fine; i += 256) hf[i] = 0u;
+    __syncthreads();
+    // (level-1 bin, coarse bin) prefix of each order statistic
+    const uint32_t p0 = (st->bin[0] << kL1Shift) | (st->cbin[0] << kL2CoarseShift);
+    const uint32_t p1 = (st->bin[1] << kL1Shift) | (st->cbin[1] << kL2CoarseShift);
+    const int arr1 = st->bin[1] != st->bin[0] ? 1 : 0;
+    const bool second = p1 != p0;   // else both ranks share one fine histogram
+    const unsigned long long n = *cap_count;
+    const unsigned long long stride = (unsigned long long)gridDim.x * 256;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + tid; i < n; i += stride) {
+        const uint32_t key = cap_buf[i];
+        const uint32_t pre = key & ~(uint32_t)(kL2Fine - 1);
+        const uint32_t f = key & (kL2Fine - 1);
+        if (pre == p0) atomicAdd(&hf[f], 1u);
+        if (second && pre == p1) atomicAdd(&hf[kL2Fine + f], 1u);
+    }
+    __syncthreads();
+    // Fine counts go to the level-2 array at (arr, coarse bin, fine digit).
+    for (int i = tid; i < 2 * kL2Fine; i += 256) {
+        if (!hf[i]) continue;
+        const int q = i / kL2Fine, f = i % kL2Fine;
+        const int arr = q == 0 ? 0 : arr1;
+        const uint32_t cb = st->cbin[q];
+        atomicAdd(&hist2[(size_t)arr * kL2Bins + (size_t)cb * kL2Fine + f],
+                  (unsigned long long)hf[i]);
+    }
+}
+
+// Level 2, coarse walk: for each wanted order statistic find the coarse bin
+// (bits 18..9) inside its level-1 bin and the rank left inside it.
+__global__ __launch_bounds__(1024) void k_finalize_mad2a(
+    DevState *st, const unsigned long long *hist2c) {
+    __shared__ unsigned long long buf[1024];
+    const int tid = threadIdx.x;
+    if (st->m == 0) return;
+    for (int q = 0; q < 2; ++q) {
+        const int arr = (q == 1 && st->bin[1] != st->bin[0]) ? 1 : 0;
+        const unsigned long long r = st->rank[q];
+        if (tid == 0) { st->cbin[q] = 0u; st->crank[q] = 0ull; }
+        __syncthreads();
+        const unsigned long long v = hist2c[arr * kL2Coarse + tid];
+        const unsigned long long incl = block_scan_incl(v, buf);
+        if (r >= incl - v && r < incl) { st->cbin[q] = (uint32_t)tid; st->crank[q] = r - (incl - v); }
+        __syncthreads();
+    }
+}
+
+// Level 2, fine walk: the exact key of each order statistic, then
+// sigma = 1.4826 x median (mean of the two central order statistics).
+__global__ __launch_bounds__(512) void k_finalize_mad2b(
+    DevState *st, const unsigned long long *hist2, int k, double t, int also0) {
+    __shared__ unsigned long long buf[512];
+    __shared__ uint32_t key[2];
+    const int tid = threadIdx.x;
+    if (st->m == 0) {
         if (tid == 0) put_sigma(st, k, also0, NAN, t);
         return;
     }
     for (int q = 0; q < 2; ++q) {
         const uint32_t bq = st->bin[q];
         const int arr = (q == 1 && bq != st->bin[0]) ? 1 : 0;
-        const unsigned long long r = st->rank[q];
-        if (tid == 0) { cbin = 0; crank = 0; key[q] = bq << kL1Shift; }
+        const uint32_t cb = st->cbin[q] < (uint32_t)kL2Coarse ? st->cbin[q] : 0u;
+        const unsigned long long rr = st->crank[q];
+        if (tid == 0) key[q] = (bq << kL1Shift) | (cb << kL2CoarseShift);
         __syncthreads();
-        const unsigned long long v = hist2c[arr * kL2Coarse + tid];
-        const unsigned long long incl = block_scan_incl(v, buf);
-        if (r >= incl - v && r < incl) { cbin = (uint32_t)tid; crank = r - (incl - v); }
-        __syncthreads();
-        const uint32_t cb = cbin < (uint32_t)kL2Coarse ? cbin : 0u;
-        const unsigned long long rr = crank;
-        const unsigned long long fv =
-            tid < kL2Fine ? hist2[(size_t)arr * kL2Bins + (size_t)cb * kL2Fine + tid] : 0ull;
+        const unsigned long long fv = hist2[(size_t)arr * kL2Bins + (size_t)cb * kL2Fine + tid];
         const unsigned long long fincl = block_scan_incl(fv, buf);
-        if (tid < kL2Fine && rr >= fincl - fv && rr < fincl)
+        if (rr >= fincl - fv && rr < fincl)
             key[q] = (bq << kL1Shift) | (cb << kL2CoarseShift) | (uint32_t)tid;
         __syncthreads();
     }
@@ -652,33 +908,64 @@ hipError_t launch_spatial(int n_iter, int radius, const SpatialArgs &a,
     return hipErrorInvalidValue;
 }
 
+// Spectral widths with a register ring; any other odd width up to
+// SOFIA_SC_MAX_WIDTH uses the LDS ring.
+static int ring_template_width(int w) {
+    switch (w) {
+        case 1: case 3: case 5: case 7: case 9: case 11: case 15: case 21: case 31: return w;
+    }
+    return 0;
+}
+
 size_t column_lds_bytes(int src, int op, bool spectral, int w) {
     size_t b = 0;
-    if (spectral) b += (size_t)w * kColThreads * sizeof(float);
-    if (spectral && src == SRC_X) b += ((size_t)w * kColThreads + 3) & ~(size_t)3;
+    const bool lds_ring = spectral && ring_template_width(w) == 0;
+    if (lds_ring) b += (size_t)w * kColThreads * sizeof(float);
+    if (lds_ring && src == SRC_X) b += ((size_t)w * kColThreads + 3) & ~(size_t)3;
     if (op == OP_HIST1) b += (size_t)kL1Bins * sizeof(unsigned);
+    if (op == OP_SELECT) {
+        const int tw = spectral ? ring_template_width(w) : 1;
+        const int group = tw >= 3 ? tw * ((8 + tw - 1) / tw) : 8;
+        b += (size_t)(kColThreads / 64) * kCapPerWave(group) * sizeof(uint32_t);
+    }
     if (op == OP_HIST2) b += (size_t)2 * kL2Coarse * sizeof(unsigned);
     return b;
 }
 
-template <int SRC, int OP, bool SPEC, bool HASWM>
+template <int SRC, int OP, bool HASWM, int W>
 static hipError_t column_inst(const ColArgs &a, int nblocks, hipStream_t s) {
-    const size_t lds = column_lds_bytes(SRC, OP, SPEC, a.w);
-    hipLaunchKernelGGL((k_column<SRC, OP, SPEC, HASWM>), dim3(nblocks),
-                       dim3(kColThreads), lds, s, a);
+    const size_t lds = column_lds_bytes(SRC, OP, W != 1, a.w);
+    hipLaunchKernelGGL((k_column<SRC, OP, HASWM, W>), dim3(nblocks), dim3(kColThreads), lds,
+                       s, a);
     return hipGetLastError();
+}
+
+template <int SRC, int OP, bool HASWM>
+static hipError_t column_width(int w, const ColArgs &a, int nb, hipStream_t s) {
+    switch (ring_template_width(w)) {
+        case 1: return column_inst<SRC, OP, HASWM, 1>(a, nb, s);
+        case 3: return column_inst<SRC, OP, HASWM, 3>(a, nb, s);
+        case 5: return column_inst<SRC, OP, HASWM, 5>(a, nb, s);
+        case 7: return column_inst<SRC, OP, HASWM, 7>(a, nb, s);
+        case 9: return column_inst<SRC, OP, HASWM, 9>(a, nb, s);
+        case 11: return column_inst<SRC, OP, HASWM, 11>(a, nb, s);
+        case 15: return column_inst<SRC, OP, HASWM, 15>(a, nb, s);
+        case 21: return column_inst<SRC, OP, HASWM, 21>(a, nb, s);
+        case 31: return column_inst<SRC, OP, HASWM, 31>(a, nb, s);
+        default: return column_inst<SRC, OP, HASWM, 0>(a, nb, s);
+    }
 }
 
 template <int SRC, int OP>
 static hipError_t column_op(bool spec, bool has_wm, const ColArgs &a, int nb,
                             hipStream_t s) {
+    const int w = spec ? a.w : 1;
     if (SRC == SRC_P || spec) {
         if (!has_wm) return hipErrorInvalidValue;
-        return spec ? column_inst<SRC, OP, true, true>(a, nb, s)
-                    : column_inst<SRC, OP, false, true>(a, nb, s);
+        return column_width<SRC, OP, true>(w, a, nb, s);
     }
-    return has_wm ? column_inst<SRC, OP, false, true>(a, nb, s)
-                  : column_inst<SRC, OP, false, false>(a, nb, s);
+    return has_wm ? column_inst<SRC, OP, true, 1>(a, nb, s)
+                  : column_inst<SRC, OP, false, 1>(a, nb, s);
 }
 
 template <int SRC>
@@ -690,6 +977,7 @@ static hipError_t column_src(int op, bool spec, bool has_wm, const ColArgs &a,
         case OP_HIST2: return column_op<SRC, OP_HIST2>(spec, has_wm, a, nb, s);
         case OP_CLIP: return column_op<SRC, OP_CLIP>(spec, has_wm, a, nb, s);
         case OP_WRITE: return column_op<SRC, OP_WRITE>(spec, has_wm, a, nb, s);
+        case OP_SELECT: return column_op<SRC, OP_SELECT>(spec, has_wm, a, nb, s);
     }
     return hipErrorInvalidValue;
 }
@@ -714,11 +1002,54 @@ hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_mad2(DevState *st, const unsigned long long *hist2,
-                                const unsigned long long *hist2c, int k, double t,
-                                int also_sigma0, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_mad2, dim3(1), dim3(1024), 0, s, st, hist2,
-                       hist2c, k, t, also_sigma0);
+hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_counts,
+                                  const unsigned long long *cap_count,
+                                  unsigned long long cap_capacity, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(64), 0, s, st, sel_counts,
+                       cap_count, cap_capacity, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
+                             const unsigned long long *cap_count,
+                             unsigned long long *hist1, hipStream_t s) {
+    hipLaunchKernelGGL(k_capture_l1, dim3(512), dim3(256), 0, s, st, cap_buf, cap_count,
+                       hist1);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_s,
+                                   hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_predict, dim3(1), dim3(256), 0, s, st, hist_s);
+    return hipGetLastError();
+}
+
+hipError_t launch_capture_coarse(const DevState *st, const uint32_t *cap_buf,
+                                 const unsigned long long *cap_count,
+                                 unsigned long long *hist2c, hipStream_t s) {
+    hipLaunchKernelGGL(k_capture_coarse, dim3(1024), dim3(256), 0, s, st, cap_buf,
+                       cap_count, hist2c);
+    return hipGetLastError();
+}
+
+hipError_t launch_capture_fine(const DevState *st, const uint32_t *cap_buf,
+                               const unsigned long long *cap_count,
+                               unsigned long long *hist2, hipStream_t s) {
+    hipLaunchKernelGGL(k_capture_fine, dim3(1024), dim3(256), 0, s, st, cap_buf,
+                       cap_count, hist2);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_mad2a(DevState *st, const unsigned long long *hist2c,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_mad2a, dim3(1), dim3(1024), 0, s, st, hist2c);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_mad2b(DevState *st, const unsigned long long *hist2, int k,
+                                 double t, int also_sigma0, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_mad2b, dim3(1), dim3(512), 0, s, st, hist2, k, t,
+                       also_sigma0);
     return hipGetLastError();
 }
 

@@ -256,3 +256,60 @@ def test_mask_monotone_in_threshold_without_replacement(h):
     hi, s_hi, _ = h.run(x, KERNELS_CFG2, 3.6, "mad", "negative", replacement=-1)
     assert np.all(host(hi) <= host(lo))
     np.testing.assert_array_equal(s_lo, s_hi)
+
+
+# ------------------------------------------- exact MAD: capture and fallback
+
+def _families(h):
+    return {s["name"]: s for s in h.profile_read()}
+
+
+def test_mad_capture_path_used_on_regular_cube(h):
+    x = cfg2_like(160, 140, 120, seed=51, n_gal=6)
+    h.profile(True)
+    m, noise, s0 = h.run(dev(x), KERNELS_CFG2[:6], 3.5, "mad", "negative")
+    h.profile(False)
+    fam = _families(h)
+    assert "column_hist2" not in fam and "column_hist1" not in fam, \
+        "prediction missed on a regular cube"
+    assert fam["fallback_skipped"]["launches"] >= 12
+    ref = oracle.run(x, KERNELS_CFG2[:6], 3.5, "mad", "negative", 2.0)
+    assert_sigma(noise, ref.sigma)
+    assert_mask(host(m), ref.mask, ref.band)
+
+
+def test_mad_fallback_when_sample_is_unrepresentative(h):
+    """Rows read by the sampling pass are scaled 100x: the predicted window
+    misses the true median and the full level-2 pass must run, still exact."""
+    nx, ny, nz = 256, 120, 90          # one column block per row
+    rng = np.random.default_rng(52)
+    x = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    x[:, ::17, :] *= 100.0             # blocks 0, 17, 34, ... are sampled
+    kernels = [(0.0, 0), (0.0, 3), (3.0, 0)]
+    h.profile(True)
+    m, noise, _ = h.run(dev(x), kernels, 3.5, "mad", "negative")
+    h.profile(False)
+    fam = _families(h)
+    assert fam.get("column_hist2", {}).get("launches", 0) >= 1, fam.keys()
+    ref = oracle.run(x, kernels, 3.5, "mad", "negative", 2.0)
+    assert_sigma(noise, ref.sigma)
+    assert_mask(host(m), ref.mask, ref.band)
+
+
+def test_mad_fallback_on_capture_overflow(h):
+    """Most voxels share one value: the captured keys exceed the buffer
+    (N/8) and the full level-2 pass must take over."""
+    nz, ny, nx = 256, 256, 256
+    rng = np.random.default_rng(53)
+    x = np.full((nz, ny, nx), -1.0, np.float32)
+    noisy = rng.random(x.shape) < 0.1
+    x[noisy] = rng.standard_normal(int(noisy.sum())).astype(np.float32)
+    kernels = [(0.0, 0), (0.0, 3)]
+    h.profile(True)
+    m, noise, _ = h.run(dev(x), kernels, 3.5, "mad", "negative")
+    h.profile(False)
+    fam = _families(h)
+    assert fam.get("column_hist2", {}).get("launches", 0) >= 1, fam.keys()
+    ref = oracle.run(x, kernels, 3.5, "mad", "negative", 2.0)
+    assert_sigma(noise, ref.sigma)
+    assert_mask(host(m), ref.mask, ref.band)
