@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="plain_1024cube")
     ap.add_argument("--cpu-planes", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
+                    help="cube storage inside the run (16-bit: noise-scaled copy)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the cube (4 B/voxel "
                          "read + write), the calibration kernel for HBM counters")
@@ -106,7 +108,7 @@ def main():
 
     def step():
         return h.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
-                     wl.replacement, mask=mask, stream=stream)
+                     wl.replacement, mask=mask, stream=stream, storage=args.storage)
 
     for _ in range(args.warmup):
         step()
@@ -134,7 +136,7 @@ def main():
     avg_ms = dom["total_ms"] / dom["launches"]
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(dom["name"], args.workload)
+    traffic = read_traffic(dom["name"], args.workload) if args.storage == "f32" else None
     alg_bytes_step = sum(s["bytes"] for s in stats) / args.steps
 
     result = {
@@ -154,7 +156,7 @@ def main():
             "workload": args.workload, "nx": spec.nx, "ny": spec.ny, "nz": spec.nz,
             "kernels": [list(k) for k in wl.kernels], "noise": wl.noise_mode,
             "flux_range": wl.flux_range, "threshold": wl.threshold,
-            "replacement": wl.replacement, "storage": "f32",
+            "replacement": wl.replacement, "storage": args.storage,
         },
         "roofline": {
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved,

@@ -49,6 +49,13 @@ typedef struct {
 } sofia_sc_kernel;
 
 enum { SOFIA_SC_NOISE_STD = 0, SOFIA_SC_NOISE_MAD = 1 };
+
+/* Storage of the cube inside a run. F32 reads the caller's cube directly.
+ * F16 / BF16 first measure sigma_0 (or take opt->sigma0), then store the
+ * noise-scaled cube q = x / sigma_0 once, rounded to the 16-bit format, and
+ * run every pass on q: half the input bytes per pass; all arithmetic stays
+ * FP32 (smoothing) and FP64 (sums, noise). See sofia_sc_quantize. */
+enum { SOFIA_SC_STORE_F32 = 0, SOFIA_SC_STORE_F16 = 1, SOFIA_SC_STORE_BF16 = 2 };
 enum { SOFIA_SC_FLUX_NEGATIVE = -1, SOFIA_SC_FLUX_ALL = 0, SOFIA_SC_FLUX_POSITIVE = 1 };
 
 enum {
@@ -69,10 +76,16 @@ typedef struct {
     uint32_t struct_size;   /* = sizeof(sofia_sc_options) */
     double replacement;     /* n of +-n sigma_0 (Sect. 6.2.4); < 0 disables
                                replacement; default 2.0 */
+    double sigma0;          /* noise of the unsmoothed input used for
+                               replacement and 16-bit scaling: NaN = measure
+                               it (default); finite > 0 = use as given */
+    int32_t storage;        /* SOFIA_SC_STORE_*; default F32 */
+    int32_t reserved;       /* must be 0 */
     void *stream;           /* hipStream_t to run on; NULL = null stream */
 } sofia_sc_options;
 
-/* Fill opt with defaults (replacement 2.0, null stream). */
+/* Fill opt with defaults (replacement 2.0, sigma0 measured, F32 storage,
+ * null stream). */
 void sofia_sc_default_options(sofia_sc_options *opt);
 
 /* Create a handle on a HIP device. The handle owns all device workspace
@@ -101,8 +114,10 @@ int sofia_sc_run(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                  uint8_t *mask, double *noise);
 
 /* sofia_sc_run with options. sigma0 (host, may be NULL) receives the noise
- * of the unsmoothed input that replacement uses (NaN when replacement is
- * off). EINVAL also for opt == NULL or a struct_size mismatch. */
+ * of the unsmoothed input that replacement and 16-bit scaling use (NaN when
+ * neither needs it). Noise values are always in the cube's own units.
+ * EINVAL also for opt == NULL, a struct_size mismatch, an unknown storage or
+ * a given sigma0 that is not finite and > 0. */
 int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     int64_t nz, const sofia_sc_kernel *kernels,
                     int32_t n_kernels, double threshold, int32_t noise_mode,
@@ -123,6 +138,18 @@ int sofia_sc_step(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                   double sigma0, const uint8_t *mask_in, uint8_t *mask_out,
                   double *noise, void *stream);
 
+/* sofia_sc_step with options: opt->replacement, opt->sigma0 and opt->stream
+ * take the place of the replacement, sigma0 and stream arguments, and
+ * opt->storage selects the storage as in sofia_sc_run_ex. With F16/BF16 the
+ * cube is stored as a run stores it, scaled by opt->sigma0, which must then
+ * be given (finite and > 0); the noise is returned in the cube's own units.
+ * EINVAL as sofia_sc_step, and for opt == NULL, a struct_size mismatch, an
+ * unknown storage or a nonzero reserved field. */
+int sofia_sc_step_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                     int64_t nz, sofia_sc_kernel kernel, double threshold,
+                     int32_t noise_mode, int32_t flux_range, const uint8_t *mask_in,
+                     uint8_t *mask_out, double *noise, const sofia_sc_options *opt);
+
 /* The smoothed cube s of one kernel, as float32 (NaN at blanked voxels),
  * with replacement applied as in sofia_sc_step. out: device, float32
  * [nz][ny][nx]. For inspection and tests; S+C itself never stores s. */
@@ -130,6 +157,16 @@ int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     int64_t nz, sofia_sc_kernel kernel, double replacement,
                     double sigma0, const uint8_t *mask_in, float *out,
                     void *stream);
+
+/* Noise-scaled 16-bit copy of a cube, exactly as a F16/BF16 run stores it:
+ * q = RN_T( RN_f32( x * RN_f64(1 / scale) ) ), RN = round to nearest even,
+ * T = binary16 (SOFIA_SC_STORE_F16) or bfloat16 (SOFIA_SC_STORE_BF16); finite
+ * values beyond T's range saturate to its largest finite value; NaN and Inf
+ * stay non-finite (blanked). cube: device float32[n]; out: device
+ * uint16[n] (bit patterns). EINVAL: NULL, n < 1, scale not finite and > 0,
+ * storage not F16/BF16. */
+int sofia_sc_quantize(sofia_sc *h, const float *cube, int64_t n, double scale,
+                      int32_t storage, uint16_t *out, void *stream);
 
 /* Spatial cascade for a FWHM: n_iter boxcars of radius r per axis, chosen to
  * match the Gaussian variance, sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2, with

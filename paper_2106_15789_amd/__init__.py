@@ -18,8 +18,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libsofia_sc.so")
 HEADER = os.path.join(ROOT, "include", "sofia_sc.h")
-SOURCES = [os.path.join(_HERE, "csrc", "sc_kernels.hip"),
-           os.path.join(_HERE, "csrc", "sc_api.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
+    "sc_kernels.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip",
+    "sc_col_clip.hip", "sc_col_write.hip", "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
 NOISE = {"std": 0, "mad": 1}
@@ -28,27 +29,46 @@ RANGE = {"negative": -1, "all": 0, "positive": 1}
 # Every symbol include/sofia_sc.h declares.
 EXPORTS = [
     "sofia_sc_default_options", "sofia_sc_create", "sofia_sc_destroy",
-    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step", "sofia_sc_smooth",
-    "sofia_sc_plan", "sofia_sc_profile", "sofia_sc_profile_read",
+    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step", "sofia_sc_step_ex", "sofia_sc_smooth",
+    "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
 ]
 
 
-def hipcc_command(out: str) -> List[str]:
-    return ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17",
-            "-fPIC", "-shared",
-            # packed FP32 instructions stay off (see the design notes)
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I" + os.path.join(ROOT, "include"), *SOURCES, "-o", out]
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+               # packed FP32 instructions stay off (see the design notes)
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the HIP library for gfx950 (cross-compiles without a GPU)."""
-    tmp = LIB_PATH + ".tmp"
-    cmd = hipcc_command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile the HIP library for gfx950 (cross-compiles without a GPU).
+
+    Each translation unit is compiled in its own hipcc process, in parallel,
+    then linked into libsofia_sc.so.
+    """
+    import tempfile
+    hipcc = "/opt/rocm/bin/hipcc"
+    inc = "-I" + os.path.join(ROOT, "include")
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 1)))
+    with tempfile.TemporaryDirectory(prefix="sofia_sc_build_") as tmpd:
+        objs, procs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpd, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmd = [hipcc, *HIPCC_FLAGS, inc, "-c", src, "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append(subprocess.Popen(cmd))
+            while sum(p.poll() is None for p in procs) >= jobs:
+                procs[[p.poll() is None for p in procs].index(True)].wait()
+        bad = [src for src, p in zip(SOURCES, procs) if p.wait() != 0]
+        if bad:
+            raise RuntimeError("hipcc failed for " + ", ".join(bad))
+        tmp = LIB_PATH + ".tmp"
+        cmd = [hipcc, *HIPCC_FLAGS, "-shared", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -61,7 +81,13 @@ class Kernel(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32),
                 ("replacement", ctypes.c_double),
+                ("sigma0", ctypes.c_double),
+                ("storage", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
+
+
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 
 class KernelStat(ctypes.Structure):
@@ -96,8 +122,11 @@ def load():
                                     ctypes.POINTER(Options), ctypes.POINTER(dbl)]
     lib.sofia_sc_step.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, dbl,
                                   dbl, vp, vp, ctypes.POINTER(dbl), vp]
+    lib.sofia_sc_step_ex.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, vp, vp,
+                                     ctypes.POINTER(dbl), ctypes.POINTER(Options)]
     lib.sofia_sc_smooth.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, dbl, vp, vp, vp]
     lib.sofia_sc_plan.argtypes = [dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sofia_sc_quantize.argtypes = [vp, vp, i64, dbl, i32, vp, vp]
     lib.sofia_sc_profile.argtypes = [vp, ctypes.c_int]
     lib.sofia_sc_profile_read.argtypes = [vp, ctypes.POINTER(KernelStat), i32,
                                           ctypes.POINTER(i32)]
@@ -106,7 +135,8 @@ def load():
     lib.sofia_sc_strerror.argtypes = [ctypes.c_int]
     lib.sofia_sc_strerror.restype = ctypes.c_char_p
     for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step",
-                 "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_profile",
+                 "sofia_sc_step_ex",
+                 "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
                  "sofia_sc_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -191,7 +221,8 @@ class SofiaSC:
 
     def run(self, cube, kernels, threshold: float, noise_mode: str = "mad",
             flux_range: str = "negative", replacement: float = 2.0, mask=None,
-            stream=None, allow_nostat: bool = False):
+            stream=None, allow_nostat: bool = False, storage: str = "f32",
+            sigma0: float = float("nan")):
         """Whole S+C run. Returns (mask uint8 tensor, noise[K] ndarray, sigma0)."""
         import torch
         nx, ny, nz = _check_cube(cube)
@@ -204,6 +235,8 @@ class SofiaSC:
         opt = Options()
         self.lib.sofia_sc_default_options(ctypes.byref(opt))
         opt.replacement = float(replacement)
+        opt.sigma0 = float(sigma0)
+        opt.storage = STORAGE[storage]
         opt.stream = _stream_ptr(stream)
         rc = self.lib.sofia_sc_run_ex(self.h, cube.data_ptr(), nx, ny, nz,
                                       _kernels(kernels), K, float(threshold),
@@ -236,6 +269,34 @@ class SofiaSC:
             self._raise(rc, "sofia_sc_step")
         return mask_out, noise.value
 
+    def step_ex(self, cube, kernel, threshold: float, noise_mode: str, flux_range: str,
+                mask_in=None, mask_out=None, replacement: float = 2.0,
+                sigma0: float = float("nan"), storage: str = "f32", stream=None,
+                allow_nostat: bool = False):
+        """step with options (storage among them). Returns (mask_out, noise)."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        _check_like(mask_in, cube, torch.uint8, "mask_in")
+        _check_like(mask_out, cube, torch.uint8, "mask_out")
+        if mask_out is None:
+            mask_out = torch.empty(cube.shape, dtype=torch.uint8, device=cube.device)
+        noise = ctypes.c_double()
+        opt = Options()
+        self.lib.sofia_sc_default_options(ctypes.byref(opt))
+        opt.replacement = float(replacement)
+        opt.sigma0 = float(sigma0)
+        opt.storage = STORAGE[storage]
+        opt.stream = _stream_ptr(stream)
+        k = Kernel(float(kernel[0]), int(kernel[1]))
+        rc = self.lib.sofia_sc_step_ex(self.h, cube.data_ptr(), nx, ny, nz, k,
+                                       float(threshold), NOISE[noise_mode], RANGE[flux_range],
+                                       None if mask_in is None else mask_in.data_ptr(),
+                                       mask_out.data_ptr(), ctypes.byref(noise),
+                                       ctypes.byref(opt))
+        if rc != OK and not (allow_nostat and rc == ENOSTAT):
+            self._raise(rc, "sofia_sc_step_ex")
+        return mask_out, noise.value
+
     def smooth(self, cube, kernel, replacement: float = -1.0,
                sigma0: float = float("nan"), mask_in=None, out=None, stream=None):
         """Smoothed cube s (float32, NaN at blanked voxels) of one kernel."""
@@ -252,6 +313,23 @@ class SofiaSC:
                                       out.data_ptr(), _stream_ptr(stream))
         if rc != OK:
             self._raise(rc, "sofia_sc_smooth")
+        return out
+
+    def quantize(self, cube, scale: float, storage: str = "f16", out=None, stream=None):
+        """The 16-bit noise-scaled copy a F16/BF16 run stores (uint16 bit patterns)."""
+        import torch
+        if not (isinstance(cube, torch.Tensor) and cube.is_cuda and cube.dtype == torch.float32
+                and cube.is_contiguous()):
+            raise ValueError("cube must be a contiguous float32 CUDA tensor")
+        if out is None:
+            out = torch.empty(cube.shape, dtype=torch.int16, device=cube.device)
+        if not (out.dtype == torch.int16 and out.is_contiguous() and
+                out.numel() == cube.numel() and out.device == cube.device):
+            raise ValueError("out must be a contiguous int16 tensor of the cube's size")
+        rc = self.lib.sofia_sc_quantize(self.h, cube.data_ptr(), cube.numel(), float(scale),
+                                        STORAGE[storage], out.data_ptr(), _stream_ptr(stream))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_quantize")
         return out
 
     def profile(self, enable: bool):

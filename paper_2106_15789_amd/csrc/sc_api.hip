@@ -20,12 +20,12 @@ namespace {
 enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
-    F_COUNT
+    F_QUANTIZE, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
-    "column_clip", "column_write", "finalize"};
+    "column_clip", "column_write", "finalize", "quantize"};
 
 struct LaunchRec {
     int fam;
@@ -63,6 +63,8 @@ struct sofia_sc {
     size_t part_cap = 0;
     uint32_t *cap_buf = nullptr;
     size_t cap_cap = 0;
+    uint16_t *xq = nullptr;
+    size_t xq_cap = 0;
     bool prof = false;
     std::vector<LaunchRec> recs;
     std::vector<hipEvent_t> pool;
@@ -187,6 +189,19 @@ ColGrid col_grid(int64_t ncol, int64_t nz) {
     return g;
 }
 
+// 16-bit copy of the cube for F16/BF16 storage.
+int ensure_q16(sofia_sc *h, int64_t N) {
+    if ((size_t)N <= h->xq_cap) return SOFIA_SC_OK;
+    if (h->xq) (void)hipFree(h->xq);
+    h->xq = nullptr;
+    h->xq_cap = 0;
+    const hipError_t e = hipMalloc(&h->xq, (size_t)N * sizeof(uint16_t));
+    if (e != hipSuccess)
+        return fail(h, SOFIA_SC_ENOMEM, std::string("16-bit cube: ") + hipGetErrorString(e));
+    h->xq_cap = (size_t)N;
+    return SOFIA_SC_OK;
+}
+
 int ensure_workspace(sofia_sc *h, int64_t N, bool need_p, size_t parts) {
     hipError_t e;
     if (!h->st) {
@@ -299,6 +314,8 @@ struct Dims {
 // the clip; write_out != null writes s instead of measuring the noise.
 struct PairJob {
     const float *x;
+    const uint16_t *xq;   // 16-bit noise-scaled cube (xtype != ST_F32)
+    int xtype;
     Dims d;
     Plan pl;
     int k;
@@ -320,6 +337,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     const bool spatial = j.pl.spatial();
     const bool spec = j.pl.spectral();
     const bool has_wm = j.wm_in != nullptr;
+    const double bx = j.xtype != ST_F32 ? 2.0 : 4.0;   // bytes per raw voxel
     if ((spatial || spec) && !has_wm)
         return fail(h, SOFIA_SC_EINVAL, "internal: smoothing without working mask");
 
@@ -333,6 +351,8 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
             return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
         SpatialArgs a{};
         a.x = j.x;
+        a.xq = j.xq;
+        a.xtype = j.xtype;
         a.wm = j.repl_active ? j.wm_in : nullptr;
         a.p = h->p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
@@ -342,7 +362,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         a.repl_on = j.repl_active ? 1 : 0;
         a.repl_n = j.repl_n;
         a.st = h->st;
-        const double bytes = N * (4.0 + (j.repl_active ? 1.0 : 0.0) + 4.0);
+        const double bytes = N * (bx + (j.repl_active ? 1.0 : 0.0) + 4.0);
         rc = launch(h, s, F_SPATIAL, bytes, N, [&] {
             return launch_spatial(j.pl.n_iter, j.pl.radius, a, s);
         });
@@ -351,6 +371,8 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
 
     ColArgs c{};
     c.x = j.x;
+    c.xq = j.xq;
+    c.xtype = j.xtype;
     c.p = h->p;
     c.wm_in = j.wm_in;
     c.ncol = d.ncol;
@@ -374,7 +396,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     c.cap_capacity = (unsigned long long)h->cap_cap;
     c.sel_counts = sel_counts_of(h);
     const int src = spatial ? SRC_P : SRC_X;
-    const double rd = N * (4.0 + (has_wm ? 1.0 : 0.0));
+    const double rd = N * ((spatial ? 4.0 : bx) + (has_wm ? 1.0 : 0.0));
     auto col = [&](int op, int fam, double bytes) {
         return launch(h, s, fam, bytes, N, [&] {
             return launch_column(src, op, spec, has_wm, c, g.blocks(), s);
@@ -522,8 +544,16 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     int rc;
     if ((rc = check_dims(h, nx, ny, nz))) return rc;
     if ((rc = check_modes(h, t, mode, range))) return rc;
-    if (!std::isfinite(opt->replacement) && !(opt->replacement < 0))
+    if (std::isnan(opt->replacement) || opt->replacement == INFINITY)
         return fail(h, SOFIA_SC_EINVAL, "replacement must be finite");
+    const int storage = opt->storage;
+    if (storage != SOFIA_SC_STORE_F32 && storage != SOFIA_SC_STORE_F16 &&
+        storage != SOFIA_SC_STORE_BF16)
+        return fail(h, SOFIA_SC_EINVAL, "unknown storage");
+    if (opt->reserved != 0) return fail(h, SOFIA_SC_EINVAL, "reserved option field must be 0");
+    const bool given0 = !std::isnan(opt->sigma0);
+    if (given0 && !(std::isfinite(opt->sigma0) && opt->sigma0 > 0.0))
+        return fail(h, SOFIA_SC_EINVAL, "sigma0 must be NaN (measure) or finite and > 0");
     std::vector<Plan> plans((size_t)K);
     bool any_spatial = false;
     for (int k = 0; k < K; ++k) {
@@ -535,11 +565,15 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     hipStream_t s = (hipStream_t)opt->stream;
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
     const ColGrid g = col_grid(d.ncol, d.nz);
+    const bool q16 = storage != SOFIA_SC_STORE_F32;
     if ((rc = ensure_workspace(h, d.N, any_spatial, (size_t)g.blocks()))) return rc;
+    if (q16 && (rc = ensure_q16(h, d.N))) return rc;
 
     const bool repl_on = opt->replacement >= 0.0;
     const bool first_identity = plans[0].identity();
-    rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_set_sigma0(h->st, NAN, s); });
+    rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
+        return launch_set_sigma0(h->st, given0 ? opt->sigma0 : NAN, s);
+    });
     if (rc) return rc;
     int cur = 0;
     bool have_wm = false;
@@ -550,17 +584,29 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
         if (rc) return rc;
         have_wm = true;
     }
-    if (repl_on && !first_identity) {
-        PairJob j{cube, d, Plan{0, 0, 1}, -1, false, 0.0, mode, range, t,
-                  h->wm[cur], nullptr, false, false, nullptr};
+    // sigma_0 on the FP32 cube when replacement or 16-bit scaling needs it and
+    // it cannot come from kernel 1 (a (0, 0) kernel measured on FP32 data).
+    if (!given0 && (q16 || (repl_on && !first_identity))) {
+        PairJob j{cube, nullptr, ST_F32, d, Plan{0, 0, 1}, -1, false, 0.0, mode, range, t,
+                  have_wm ? h->wm[cur] : nullptr, nullptr, false, false, nullptr};
         if ((rc = run_pair(h, s, j))) return rc;
+    }
+    int xtype = ST_F32;
+    if (q16) {
+        xtype = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
+        rc = launch(h, s, F_QUANTIZE, 6.0 * d.N, (double)d.N, [&] {
+            return launch_quantize(cube, h->st, 0.0, xtype, h->xq, d.N, s);
+        });
+        if (rc) return rc;
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(h->st, s); });
+        if (rc) return rc;
     }
     for (int k = 0; k < K; ++k) {
         const bool last = k == K - 1;
         uint8_t *out = last ? mask : (have_wm ? h->wm[1 - cur] : h->wm[cur]);
-        PairJob j{cube, d, plans[k], k, repl_on && k >= 1, opt->replacement, mode,
-                  range, t, have_wm ? h->wm[cur] : nullptr, out, last,
-                  k == 0 && first_identity && repl_on, nullptr};
+        PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, plans[k], k, repl_on && k >= 1,
+                  opt->replacement, mode, range, t, have_wm ? h->wm[cur] : nullptr, out, last,
+                  k == 0 && first_identity && repl_on && !given0 && !q16, nullptr};
         if ((rc = run_pair(h, s, j))) return rc;
         if (!last) {
             if (have_wm) cur = 1 - cur;
@@ -569,8 +615,9 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     }
     if ((rc = finish(h, s))) return rc;
     const DevState &hs = *h->st_host;
-    for (int k = 0; k < K; ++k) noise[k] = hs.sigma[k];
-    if (sigma0_out) *sigma0_out = repl_on ? hs.sigma0 : NAN;
+    const double scale = q16 ? hs.scale : 1.0;   // stored units -> cube units
+    for (int k = 0; k < K; ++k) noise[k] = hs.sigma[k] * scale;
+    if (sigma0_out) *sigma0_out = q16 ? hs.scale : (repl_on || given0 ? hs.sigma0 : NAN);
     if (hs.status) return fail(h, SOFIA_SC_ENOSTAT, "no finite voxel in the flux range for some kernel");
     return SOFIA_SC_OK;
 }
@@ -584,7 +631,33 @@ void sofia_sc_default_options(sofia_sc_options *opt) {
     std::memset(opt, 0, sizeof(*opt));
     opt->struct_size = sizeof(sofia_sc_options);
     opt->replacement = 2.0;
+    opt->sigma0 = NAN;
+    opt->storage = SOFIA_SC_STORE_F32;
+    opt->reserved = 0;
     opt->stream = nullptr;
+}
+
+int sofia_sc_quantize(sofia_sc *h, const float *cube, int64_t n, double scale,
+                      int32_t storage, uint16_t *out, void *stream) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err.clear();
+    if (!cube || !out || n < 1) return fail(h, SOFIA_SC_EINVAL, "NULL argument or n < 1");
+    if (!(std::isfinite(scale) && scale > 0.0))
+        return fail(h, SOFIA_SC_EINVAL, "scale must be finite and > 0");
+    if (storage != SOFIA_SC_STORE_F16 && storage != SOFIA_SC_STORE_BF16)
+        return fail(h, SOFIA_SC_EINVAL, "storage must be F16 or BF16");
+    DeviceGuard dg(h->device);
+    if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const int type = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
+    int rc = launch(h, s, F_QUANTIZE, 6.0 * n, (double)n, [&] {
+        return launch_quantize(cube, nullptr, scale, type, out, n, s);
+    });
+    if (rc) return rc;
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "stream");
+    if (h->prof) collect_profile(h);
+    return SOFIA_SC_OK;
 }
 
 int sofia_sc_create(sofia_sc **out, int device_ordinal) {
@@ -615,6 +688,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->part_sum) (void)hipFree(h->part_sum);
         if (h->part_cnt) (void)hipFree(h->part_cnt);
         if (h->cap_buf) (void)hipFree(h->cap_buf);
+        if (h->xq) (void)hipFree(h->xq);
     }
     delete h;
 }
@@ -642,7 +716,7 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                          int64_t nz, sofia_sc_kernel kernel, double threshold,
                          int32_t mode, int32_t range, double replacement,
                          double sigma0, const uint8_t *mask_in, uint8_t *mask_out,
-                         double *noise, float *write_out, void *stream) {
+                         double *noise, float *write_out, int32_t storage, void *stream) {
     if (!h) return SOFIA_SC_EINVAL;
     h->err.clear();
     if (noise) *noise = NAN;
@@ -658,6 +732,13 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     const bool repl = replacement >= 0.0;
     if (repl && !std::isfinite(sigma0))
         return fail(h, SOFIA_SC_EINVAL, "sigma0 must be finite when replacement is on");
+    if (storage != SOFIA_SC_STORE_F32 && storage != SOFIA_SC_STORE_F16 &&
+        storage != SOFIA_SC_STORE_BF16)
+        return fail(h, SOFIA_SC_EINVAL, "unknown storage");
+    const bool q16 = storage != SOFIA_SC_STORE_F32;
+    if (q16 && write_out) return fail(h, SOFIA_SC_EINVAL, "internal: 16-bit smoothed output");
+    if (q16 && !(std::isfinite(sigma0) && sigma0 > 0.0))
+        return fail(h, SOFIA_SC_EINVAL, "16-bit storage needs sigma0 finite and > 0");
     Plan pl;
     if ((rc = make_plan(h, kernel, &pl))) return rc;
     DeviceGuard dg(h->device);
@@ -666,21 +747,32 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
     const ColGrid g = col_grid(d.ncol, d.nz);
     if ((rc = ensure_workspace(h, d.N, pl.spatial(), (size_t)g.blocks()))) return rc;
+    if (q16 && (rc = ensure_q16(h, d.N))) return rc;
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
-        return launch_set_sigma0(h->st, repl ? sigma0 : NAN, s);
+        return launch_set_sigma0(h->st, (repl || q16) ? sigma0 : NAN, s);
     });
     if (rc) return rc;
     rc = launch(h, s, F_INIT, (mask_in ? 6.0 : 5.0) * d.N, (double)d.N, [&] {
         return launch_init_mask(cube, mask_in, h->wm[0], d.N, s);
     });
     if (rc) return rc;
-    PairJob j{cube, d, pl, 0, repl, replacement, write_out ? 0 : mode,
-              write_out ? 0 : range, write_out ? 1.0 : threshold, h->wm[0],
-              write_out ? nullptr : mask_out, true, false, write_out};
+    int xtype = ST_F32;
+    if (q16) {
+        xtype = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
+        rc = launch(h, s, F_QUANTIZE, 6.0 * d.N, (double)d.N, [&] {
+            return launch_quantize(cube, h->st, 0.0, xtype, h->xq, d.N, s);
+        });
+        if (rc) return rc;
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(h->st, s); });
+        if (rc) return rc;
+    }
+    PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, pl, 0, repl, replacement,
+              write_out ? 0 : mode, write_out ? 0 : range, write_out ? 1.0 : threshold,
+              h->wm[0], write_out ? nullptr : mask_out, true, false, write_out};
     if ((rc = run_pair(h, s, j))) return rc;
     if ((rc = finish(h, s))) return rc;
     if (write_out) return SOFIA_SC_OK;
-    *noise = h->st_host->sigma[0];
+    *noise = h->st_host->sigma[0] * (q16 ? h->st_host->scale : 1.0);
     if (h->st_host->status)
         return fail(h, SOFIA_SC_ENOSTAT, "no finite voxel in the flux range");
     return SOFIA_SC_OK;
@@ -693,7 +785,21 @@ int sofia_sc_step(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                   double *noise, void *stream) {
     return single_kernel(h, cube, nx, ny, nz, kernel, threshold, noise_mode,
                          flux_range, replacement, sigma0, mask_in, mask_out, noise,
-                         nullptr, stream);
+                         nullptr, SOFIA_SC_STORE_F32, stream);
+}
+
+int sofia_sc_step_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                     int64_t nz, sofia_sc_kernel kernel, double threshold,
+                     int32_t noise_mode, int32_t flux_range, const uint8_t *mask_in,
+                     uint8_t *mask_out, double *noise, const sofia_sc_options *opt) {
+    if (!h) return SOFIA_SC_EINVAL;
+    if (noise) *noise = NAN;
+    if (!opt || opt->struct_size != sizeof(sofia_sc_options))
+        return fail(h, SOFIA_SC_EINVAL, "options missing or of another size");
+    if (opt->reserved != 0) return fail(h, SOFIA_SC_EINVAL, "reserved option field must be 0");
+    return single_kernel(h, cube, nx, ny, nz, kernel, threshold, noise_mode, flux_range,
+                         opt->replacement, opt->sigma0, mask_in, mask_out, noise, nullptr,
+                         opt->storage, opt->stream);
 }
 
 int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
@@ -703,7 +809,7 @@ int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     if (!out) return fail(h, SOFIA_SC_EINVAL, "NULL argument");
     return single_kernel(h, cube, nx, ny, nz, kernel, 1.0, SOFIA_SC_NOISE_STD,
                          SOFIA_SC_FLUX_ALL, replacement, sigma0, mask_in, nullptr,
-                         nullptr, out, stream);
+                         nullptr, out, SOFIA_SC_STORE_F32, stream);
 }
 
 int sofia_sc_plan(double spatial_fwhm_px, int32_t *n_iter, int32_t *radius) {

@@ -1,0 +1,388 @@
+// Column-streaming kernel (spectral boxcar + one per-voxel operation),
+// shared by the per-operation translation units sc_col_*.hip so that its many
+// instantiations compile in parallel.
+#pragma once
+
+#include "sc_device.h"
+
+namespace sc {
+
+// ------------------------------------------------------ column streaming
+
+struct ColAcc {
+    double sum;
+    unsigned long long cnt;
+};
+
+// One thread per (x, y) column. The column is streamed as a sequence of
+// input planes zi = z0 - h .. z1 - 1 + h (the leading edge of the spectral
+// window); after input zi the window sum S covers planes zi - 2h .. zi, i.e.
+// the output plane z = zi - h. Inputs are fetched in groups of G planes and
+// the next group is requested before the current one is consumed, so every
+// wave keeps up to 2G plane reads in flight. Every plane access of a block is
+// one contiguous run of 256 voxels: a uniform row pointer plus the lane.
+//
+// W is the spectral width: 1 = no spectral smoothing; an odd W >= 3 keeps the
+// window in registers with compile-time ring slots (G is a multiple of W, so
+// every group starts at slot 0); W = 0 takes the width at run time and keeps
+// the window ring in LDS. The window sum is an FP64 running sum of the FP32
+// inputs (exact while the inputs span fewer than 2^29 ulps), recomputed from
+// the ring every eight groups.
+template <int W>
+struct ColGroup {
+    static constexpr int G = W >= 3 ? W * ((8 + W - 1) / W) : 8;
+};
+
+template <int SRC, int OP, bool HASWM, int W, int XT>
+__global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
+    extern __shared__ float dyn_lds[];
+    constexpr int B = kColThreads;
+    constexpr bool SPEC = W != 1;
+    constexpr bool LDSRING = W == 0;
+    constexpr int G = ColGroup<W>::G;
+    const int tid = threadIdx.x;
+    if ((OP == OP_HIST1 || OP == OP_HIST2) && a.skip_if_captured && a.st->use_capture) return;
+    const int cb = (int)(blockIdx.x % (unsigned)a.ncb) * a.cb_stride;
+    const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
+    const int64_t ncol = a.ncol;
+    const int64_t col0 = (int64_t)cb * B;
+    const bool active = col0 + tid < ncol;
+    const int nz = (int)a.nz;
+    const int z0 = zc * a.zchunk;
+    const int z1 = min(nz, z0 + a.zchunk);
+    const int w = W == 0 ? a.w : (W >= 3 ? W : 1);
+    const int h = (w - 1) / 2;
+
+    // LDS: [ring floats [w][B] | ring bytes [w][B] (W = 0 only)] | histogram | capture
+    float *lring = dyn_lds;
+    uint8_t *lbring = (uint8_t *)(dyn_lds + (LDSRING ? w * B : 0));
+    unsigned *hist = (unsigned *)(lbring + ((LDSRING && SRC == SRC_X) ? ((w * B + 3) & ~3) : 0));
+    constexpr int kHistWords = OP == OP_HIST1 ? kL1Bins : (OP == OP_HIST2 ? 2 * kL2Coarse : 0);
+    if (kHistWords) {
+        for (int i = tid; i < kHistWords; i += B) hist[i] = 0u;
+    }
+    if (LDSRING) {
+        for (int j = 0; j < w; ++j) {
+            lring[j * B + tid] = 0.f;
+            if (SRC == SRC_X) lbring[j * B + tid] = 0;
+        }
+    }
+    if (kHistWords) __syncthreads();
+
+    const bool repl = SRC == SRC_X && HASWM && a.repl_on;
+    const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
+    const double T = (OP == OP_CLIP) ? a.st->thr : 0.0;
+    uint32_t b0 = 0xffffffffu, b1 = 0xffffffffu;
+    if (OP == OP_HIST2) { b0 = a.st->bin[0]; b1 = a.st->bin[1]; }
+    const int range = a.range;
+    ColAcc acc{0.0, 0ull};
+    const float *src = SRC == SRC_X ? a.x : a.p;
+
+    // Selection pass: count the selected voxels and the keys below the
+    // predicted window [klo, khi], and append the keys inside it, per wave, to
+    // an LDS buffer that is flushed to the global key list with one atomic
+    // per flush.
+    constexpr bool capture = OP == OP_SELECT;
+    uint32_t klo = 1, khi = 0;
+    if (capture) { klo = a.st->klo; khi = a.st->khi; }
+    unsigned n_sel = 0, n_below = 0;
+    uint32_t *capw = (uint32_t *)(hist + kHistWords) + (tid >> 6) * kCapPerWave(G);
+    int fill = 0;   // entries in this wave's buffer (same in every lane)
+    auto flush = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long act = __ballot(1);
+        const int leader = __ffsll((long long)act) - 1;
+        const int wlane = tid & 63;
+        unsigned long long base = 0;
+        if (wlane == leader) base = atomicAdd(a.cap_count, (unsigned long long)fill);
+        const uint32_t lo32 = __shfl((uint32_t)base, leader);
+        const uint32_t hi32 = __shfl((uint32_t)(base >> 32), leader);
+        base = ((unsigned long long)hi32 << 32) | lo32;
+        // copy with the lanes that are active (a wave may be partly idle)
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+        const int nact = __popcll(act);
+        for (int i = rank; i < fill; i += nact)
+            if (base + i < a.cap_capacity) a.cap_buf[base + i] = capw[i];
+        __builtin_amdgcn_wave_barrier();
+        fill = 0;
+    };
+
+    // Per-voxel operation on the smoothed value s of output plane zo.
+    auto consume = [&](int zo, double s, bool blank, uint8_t wb) {
+        if (OP == OP_STD) {
+            if (!blank && in_flux_range(s, range)) { acc.sum += s * s; acc.cnt += 1; }
+        } else if (OP == OP_HIST1) {
+            if (!blank && in_flux_range(s, range)) {
+                const uint32_t key = __float_as_uint(fabsf((float)s));
+                atomicAdd(&hist[key >> kL1Shift], 1u);
+            }
+        } else if (OP == OP_SELECT) {
+            const bool sel = !blank && in_flux_range(s, range);
+            const uint32_t key = __float_as_uint(fabsf((float)s));
+            n_sel += sel ? 1u : 0u;
+            n_below += (sel && key < klo) ? 1u : 0u;
+            const bool want = sel && key >= klo && key <= khi;
+            const unsigned long long bal = __ballot(want);
+            if (bal) {
+                if (want) {
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    capw[fill + below] = key;
+                }
+                fill += __popcll(bal);
+            }
+        } else if (OP == OP_HIST2) {
+            if (!blank && in_flux_range(s, range)) {
+                const uint32_t key = __float_as_uint(fabsf((float)s));
+                const uint32_t k1 = key >> kL1Shift;
+                const uint32_t lo = key & (kL2Bins - 1);
+                if (k1 == b0) {
+                    atomicAdd(&a.hist2[lo], 1ull);
+                    atomicAdd(&hist[lo >> kL2CoarseShift], 1u);
+                }
+                if (k1 == b1 && b1 != b0) {
+                    atomicAdd(&a.hist2[kL2Bins + lo], 1ull);
+                    atomicAdd(&hist[kL2Coarse + (lo >> kL2CoarseShift)], 1u);
+                }
+            }
+        } else if (OP == OP_CLIP) {
+            const uint8_t det = (!blank && fabs(s) > T) ? kDet : 0;
+            uint8_t out;
+            if (a.out_user) out = (uint8_t)((wb & kDet) | det);
+            else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
+            (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
+        } else {  // OP_WRITE
+            (a.s_out + (int64_t)zo * ncol + col0)[tid] = blank ? NAN : (float)s;
+        }
+    };
+
+    // Spectral input of a raw voxel: blanked -> 0, detected -> +-n sigma_0.
+    auto raw_value = [&](float xv, uint8_t wb) -> float {
+        if (!isfinite(xv)) return 0.f;
+        if (repl && (wb & kDet)) return copysignf(rv, xv);
+        return xv;
+    };
+
+    // 16-bit storage is kept as raw bits until the group is consumed, so that
+    // prefetching the next group never waits on its loads.
+    constexpr bool Q16 = SRC == SRC_X && XT != ST_F32;
+    struct Group {
+        float v[G];
+        uint16_t q[G];
+        uint8_t b[G];    // working-mask byte of the input plane (SRC_X) or of
+                         // the output plane (SRC_P)
+    };
+    auto in_value = [&](const Group &g, int j) -> float {
+        if (!Q16) return g.v[j];
+        return XT == ST_F16 ? f16_bits_to_float(g.q[j]) : bf16_bits_to_float(g.q[j]);
+    };
+    const int zs = SPEC ? z0 - h : z0;
+    const int ze = SPEC ? z1 + h : z1;   // exclusive
+    auto load_group = [&](int zb, Group &g) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int zi = zb + j;
+            g.v[j] = 0.f;
+            g.q[j] = 0;
+            g.b[j] = 0;
+            if (zi < ze && zi >= 0 && zi < nz) {
+                const int64_t off = (int64_t)zi * ncol + col0;
+                if (Q16) g.q[j] = (a.xq + off)[tid];
+                else g.v[j] = (src + off)[tid];
+                if (SRC == SRC_X && HASWM) g.b[j] = (a.wm_in + off)[tid];
+            }
+            if (SRC == SRC_P) {
+                const int zo = zi - h;
+                if (zi < ze && zo >= z0) g.b[j] = (a.wm_in + (int64_t)zo * ncol + col0)[tid];
+            }
+        }
+    };
+
+    float ring[W >= 3 ? W : 1];
+    uint8_t bring[W >= 3 ? W : 1];
+#pragma unroll
+    for (int j = 0; j < (W >= 3 ? W : 1); ++j) { ring[j] = 0.f; bring[j] = 0; }
+    int lslot = 0;           // W = 0: LDS ring slot of the next input
+    double S = 0.0;
+    const double inv_w = 1.0 / (double)w;
+    int groups = 0;
+
+    auto process_group = [&](int zb, const Group &g) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int zi = zb + j;
+            if (zi >= ze) break;
+            if (!SPEC) {
+                const float xv = in_value(g, j);
+                if (SRC == SRC_X) {
+                    const bool blank = !isfinite(xv);
+                    consume(zi, (double)raw_value(xv, g.b[j]), blank, g.b[j]);
+                } else {
+                    consume(zi, (double)xv, (g.b[j] & kBlank) != 0, g.b[j]);
+                }
+                continue;
+            }
+            const float vn = SRC == SRC_X ? raw_value(in_value(g, j), g.b[j]) : g.v[j];
+            float vo;
+            uint8_t wb_out = g.b[j];
+            if (LDSRING) {
+                vo = lring[lslot * B + tid];
+                lring[lslot * B + tid] = vn;
+                if (SRC == SRC_X) {
+                    lbring[lslot * B + tid] = g.b[j];
+                    int os = lslot + h + 1;
+                    if (os >= w) os -= w;
+                    wb_out = lbring[os * B + tid];
+                }
+                if (++lslot == w) lslot = 0;
+            } else {
+                constexpr int kW = W >= 3 ? W : 1;
+                const int sl = j % kW;
+                vo = ring[sl];
+                ring[sl] = vn;
+                if (SRC == SRC_X) {
+                    bring[sl] = g.b[j];
+                    wb_out = bring[(j + kW - (kW - 1) / 2) % kW];
+                }
+            }
+            S += (double)vn - (double)vo;
+            const int zo = zi - h;
+            if (zo >= z0) consume(zo, S * inv_w, (wb_out & kBlank) != 0, wb_out);
+        }
+        // The buffer holds one more group on top of kCapFlushAt entries.
+        if (capture && fill > kCapFlushAt) flush();
+        if (SPEC && (++groups & 7) == 0) {   // re-anchor the running sum
+            S = 0.0;
+            if (LDSRING) {
+                for (int j = 0; j < w; ++j) S += (double)lring[j * B + tid];
+            } else {
+#pragma unroll
+                for (int j = 0; j < (W >= 3 ? W : 1); ++j) S += (double)ring[j];
+            }
+        }
+    };
+
+    if (active) {
+        Group ga, gb;
+        load_group(zs, ga);
+        for (int zb = zs; zb < ze; zb += 2 * G) {
+            if (zb + G < ze) load_group(zb + G, gb);
+            process_group(zb, ga);
+            if (zb + G >= ze) break;
+            if (zb + 2 * G < ze) load_group(zb + 2 * G, ga);
+            process_group(zb + G, gb);
+        }
+        if (capture && fill > 0) flush();
+    }
+
+    if (OP == OP_STD) {
+        // Block reduction in a fixed order: deterministic partials.
+        __shared__ double rs[B];
+        __shared__ unsigned long long rc[B];
+        rs[tid] = acc.sum;
+        rc[tid] = acc.cnt;
+        __syncthreads();
+        for (int off = B / 2; off > 0; off >>= 1) {
+            if (tid < off) { rs[tid] += rs[tid + off]; rc[tid] += rc[tid + off]; }
+            __syncthreads();
+        }
+        if (tid == 0) { a.part_sum[blockIdx.x] = rs[0]; a.part_cnt[blockIdx.x] = rc[0]; }
+    } else if (OP == OP_HIST1) {
+        __syncthreads();
+        for (int i = tid; i < kL1Bins; i += B)
+            if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
+    } else if (OP == OP_SELECT) {
+        __shared__ unsigned long long rc[2][B];
+        rc[0][tid] = n_sel;
+        rc[1][tid] = n_below;
+        __syncthreads();
+        for (int off = B / 2; off > 0; off >>= 1) {
+            if (tid < off) { rc[0][tid] += rc[0][tid + off]; rc[1][tid] += rc[1][tid + off]; }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            if (rc[0][0]) atomicAdd(&a.sel_counts[0], rc[0][0]);
+            if (rc[1][0]) atomicAdd(&a.sel_counts[1], rc[1][0]);
+        }
+    } else if (OP == OP_HIST2) {
+        __syncthreads();
+        for (int i = tid; i < 2 * kL2Coarse; i += B)
+            if (hist[i]) atomicAdd(&a.hist2c[i], (unsigned long long)hist[i]);
+    }
+}
+
+// Spectral widths with a register ring; any other odd width up to
+// SOFIA_SC_MAX_WIDTH uses the LDS ring.
+inline int ring_template_width(int w) {
+    switch (w) {
+        case 1: case 3: case 5: case 7: case 9: case 11: case 15: case 21: case 31: return w;
+    }
+    return 0;
+}
+
+inline size_t column_lds_bytes(int src, int op, bool spectral, int w) {
+    size_t b = 0;
+    const bool lds_ring = spectral && ring_template_width(w) == 0;
+    if (lds_ring) b += (size_t)w * kColThreads * sizeof(float);
+    if (lds_ring && src == SRC_X) b += ((size_t)w * kColThreads + 3) & ~(size_t)3;
+    if (op == OP_HIST1) b += (size_t)kL1Bins * sizeof(unsigned);
+    if (op == OP_SELECT) {
+        const int tw = spectral ? ring_template_width(w) : 1;
+        const int group = tw >= 3 ? tw * ((8 + tw - 1) / tw) : 8;
+        b += (size_t)(kColThreads / 64) * kCapPerWave(group) * sizeof(uint32_t);
+    }
+    if (op == OP_HIST2) b += (size_t)2 * kL2Coarse * sizeof(unsigned);
+    return b;
+}
+
+template <int SRC, int OP, bool HASWM, int W, int XT>
+hipError_t column_inst(const ColArgs &a, int nblocks, hipStream_t s) {
+    const size_t lds = column_lds_bytes(SRC, OP, W != 1, a.w);
+    hipLaunchKernelGGL((k_column<SRC, OP, HASWM, W, XT>), dim3(nblocks), dim3(kColThreads),
+                       lds, s, a);
+    return hipGetLastError();
+}
+
+template <int SRC, int OP, bool HASWM, int XT>
+hipError_t column_width(int w, const ColArgs &a, int nb, hipStream_t s) {
+    switch (ring_template_width(w)) {
+        case 1: return column_inst<SRC, OP, HASWM, 1, XT>(a, nb, s);
+        case 3: return column_inst<SRC, OP, HASWM, 3, XT>(a, nb, s);
+        case 5: return column_inst<SRC, OP, HASWM, 5, XT>(a, nb, s);
+        case 7: return column_inst<SRC, OP, HASWM, 7, XT>(a, nb, s);
+        case 9: return column_inst<SRC, OP, HASWM, 9, XT>(a, nb, s);
+        case 11: return column_inst<SRC, OP, HASWM, 11, XT>(a, nb, s);
+        case 15: return column_inst<SRC, OP, HASWM, 15, XT>(a, nb, s);
+        case 21: return column_inst<SRC, OP, HASWM, 21, XT>(a, nb, s);
+        case 31: return column_inst<SRC, OP, HASWM, 31, XT>(a, nb, s);
+        default: return column_inst<SRC, OP, HASWM, 0, XT>(a, nb, s);
+    }
+}
+
+template <int SRC, int OP, int XT>
+hipError_t column_op_xt(bool spec, bool has_wm, const ColArgs &a, int nb, hipStream_t s) {
+    const int w = spec ? a.w : 1;
+    if (SRC == SRC_P || spec) {
+        if (!has_wm) return hipErrorInvalidValue;
+        return column_width<SRC, OP, true, XT>(w, a, nb, s);
+    }
+    return has_wm ? column_inst<SRC, OP, true, 1, XT>(a, nb, s)
+                  : column_inst<SRC, OP, false, 1, XT>(a, nb, s);
+}
+
+// Launch one operation of the column kernel; the raw cube's storage only
+// matters for SRC_X (SRC_P is always the FP32 smoothed buffer).
+template <int OP>
+hipError_t launch_column_op(int src, bool spec, bool has_wm, const ColArgs &a, int nb,
+                            hipStream_t s) {
+    if (src == SRC_P) return column_op_xt<SRC_P, OP, ST_F32>(spec, has_wm, a, nb, s);
+    switch (a.xtype) {
+        case ST_F32: return column_op_xt<SRC_X, OP, ST_F32>(spec, has_wm, a, nb, s);
+        case ST_F16: return column_op_xt<SRC_X, OP, ST_F16>(spec, has_wm, a, nb, s);
+        case ST_BF16: return column_op_xt<SRC_X, OP, ST_BF16>(spec, has_wm, a, nb, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace sc

@@ -45,6 +45,7 @@ struct DevState {
     uint32_t cbin[2];       // level-2 coarse bins (bits 18..9) of the two ranks
     unsigned long long crank[2];  // residual ranks inside the coarse bins
     unsigned long long fallback;  // bit k: kernel k needed the full level-2 pass
+    double scale;           // 16-bit storage: cube units per stored unit (sigma_0)
     double sigma[SOFIA_SC_MAX_KERNELS];
 };
 
@@ -55,12 +56,16 @@ constexpr int kCapFlushAt = 256;
 constexpr int kCapPerWave(int group) { return kCapFlushAt + 64 * group; }
 
 enum Src { SRC_X = 0, SRC_P = 1 };
+enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 enum Op { OP_STD = 0, OP_HIST1 = 1, OP_HIST2 = 2, OP_CLIP = 3, OP_WRITE = 4, OP_SELECT = 5 };
 
 // Arguments of the column-streaming kernel (spectral boxcar + one of the
 // per-voxel operations). One thread owns one (x, y) column and streams z.
 struct ColArgs {
-    const float *x;              // raw cube (SRC_X)
+    const float *x;              // raw cube (SRC_X, ST_F32)
+    const uint16_t *xq;          // raw cube stored as 16 bits (SRC_X, ST_F16/ST_BF16)
+    int32_t xtype;               // Storage of the raw cube
+    int32_t pad0;
     const float *p;              // spatially smoothed cube (SRC_P)
     const uint8_t *wm_in;        // working mask (may be null when has_wm is false)
     uint8_t *mask_out;           // OP_CLIP output
@@ -91,6 +96,9 @@ struct ColArgs {
 
 struct SpatialArgs {
     const float *x;
+    const uint16_t *xq;          // 16-bit storage of the cube (xtype != ST_F32)
+    int32_t xtype;
+    int32_t pad0;
     const uint8_t *wm;           // may be null (no replacement)
     float *p;
     int64_t nx, ny, nz;
@@ -136,6 +144,11 @@ hipError_t launch_finalize_mad2a(DevState *st, const unsigned long long *hist2c,
 hipError_t launch_finalize_mad2b(DevState *st, const unsigned long long *hist2, int k,
                                  double t, int also_sigma0, hipStream_t s);
 hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s);
+// 16-bit noise-scaled copy; scale = st->sigma0 when st != null, else `scale`.
+hipError_t launch_quantize(const float *x, const DevState *st, double scale, int type,
+                           uint16_t *out, int64_t n, hipStream_t s);
+// After quantisation: keep sigma_0 as the scale and continue in scaled units.
+hipError_t launch_enter_scaled(DevState *st, hipStream_t s);
 
 // Threads per block of the column kernel, and its dynamic LDS size.
 constexpr int kColThreads = 256;

@@ -23,15 +23,13 @@
 //    on the device, so a run never waits on the host between launches.
 #include <math.h>
 
-#include "sc_internal.h"
+#include <type_traits>
+
+#include "sc_device.h"
 
 namespace sc {
 
 // ----------------------------------------------------------------- helpers
-
-__device__ __forceinline__ bool in_flux_range(double s, int range) {
-    return range < 0 ? (s < 0.0) : (range > 0 ? (s > 0.0) : true);
-}
 
 // Write a noise value and the threshold derived from it into the state.
 __device__ void put_sigma(DevState *st, int k, int also_sigma0, double sig,
@@ -62,6 +60,38 @@ __global__ void k_fill_u64(unsigned long long *p, int64_t n) {
         p[i] = 0ull;
 }
 
+// q = RN_T(RN_f32(x * RN_f64(1 / scale))); finite values saturate to the
+// largest finite value of T; non-finite values stay non-finite.
+template <int T>
+__global__ void k_quantize(const float *__restrict__ x, const DevState *st, double scale,
+                           uint16_t *__restrict__ out, int64_t n) {
+    const double inv = 1.0 / (st ? st->sigma0 : scale);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const float xv = x[i];
+        float y = (float)((double)xv * inv);
+        uint16_t q;
+        if (T == ST_F16) {
+            if (isfinite(xv) && !(fabsf(y) <= 65504.f)) y = copysignf(65504.f, y);
+            q = __builtin_bit_cast(uint16_t, (_Float16)y);
+        } else {
+            const float bmax = __uint_as_float(0x7f7f0000u);
+            if (isfinite(xv) && !(fabsf(y) <= bmax)) y = copysignf(bmax, y);
+            const uint32_t u = __float_as_uint(y);
+            if (isnan(y)) q = (uint16_t)((u >> 16) | 0x0040u);
+            else q = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+        }
+        out[i] = q;
+    }
+}
+
+__global__ void k_enter_scaled(DevState *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->scale = st->sigma0;
+        st->sigma0 = 1.0;
+    }
+}
+
 __global__ void k_set_sigma0(DevState *st, double sigma0) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->sigma0 = sigma0;
@@ -73,6 +103,7 @@ __global__ void k_set_sigma0(DevState *st, double sigma0) {
         st->khi = 0u;
         st->below = 0ull;
         st->fallback = 0ull;
+        st->scale = 1.0;
         for (int k = 0; k < SOFIA_SC_MAX_KERNELS; ++k) st->sigma[k] = NAN;
     }
 }
@@ -80,24 +111,23 @@ __global__ void k_set_sigma0(DevState *st, double sigma0) {
 // ------------------------------------------------------ spatial cascade
 
 // One boxcar pass over register array `in`, writing out[i] for i in
-// [LO, HI): unnormalised sum of in[i-R .. i+R]. For R = 1 the three taps are
-// summed directly (as cheap as a running sum); wider boxcars use a running
-// sum recomputed directly every kAnchor outputs, which bounds the FP32
-// rounding carried along a row by the terms that already left the window.
-constexpr int kAnchor = 4;
+// [LO, HI): the unnormalised sum of in[i-R .. i+R]. The running sum is kept
+// in FP64, which holds sums of FP32 values exactly, so each output carries a
+// single FP32 rounding; it is recomputed directly every kAnchor outputs.
+constexpr int kAnchor = 32;
 template <int N, int R, int LO, int HI>
 __device__ __forceinline__ void box_pass(const float (&in)[N], float (&out)[N]) {
-    float s = 0.f;
+    double s = 0.0;
 #pragma unroll
     for (int i = LO; i < HI; ++i) {
-        if (R == 1 || (i - LO) % kAnchor == 0) {
-            s = 0.f;
+        if ((i - LO) % kAnchor == 0) {
+            s = 0.0;
 #pragma unroll
-            for (int j = -R; j <= R; ++j) s += in[i + j];
+            for (int j = -R; j <= R; ++j) s += (double)in[i + j];
         } else {
-            s += in[i + R] - in[i - R - 1];
+            s += (double)in[i + R] - (double)in[i - R - 1];
         }
-        out[i] = s;
+        out[i] = (float)s;
     }
 }
 
@@ -183,7 +213,8 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
     spatial_tile(a, EDGE, tile - z * tiles, tx, ty);
     const int64_t nx = a.nx, ny = a.ny;
     const int64_t x0 = (int64_t)tx * 64, y0 = (int64_t)ty * TY;
-    const float *xp = a.x + z * nx * ny;
+    const float *xp = a.x ? a.x + z * nx * ny : nullptr;
+    const uint16_t *xqp = a.xq ? a.xq + z * nx * ny : nullptr;
     const uint8_t *wp = a.wm ? a.wm + z * nx * ny : nullptr;
     const bool repl = a.repl_on && wp != nullptr;
     const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
@@ -192,42 +223,64 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
 
     // Stage the region (64 rows x RW columns): lanes take columns lane and
     // 64 + lane (the latter only for the 2H right-halo columns). Rows are
-    // fetched in batches so many loads are in flight at once.
+    // fetched in batches so many loads are in flight at once. Every lane
+    // loads, from coordinates clamped into the cube, and what lies outside
+    // is zeroed afterwards: a load under a divergent branch makes the
+    // compiler merge or convert its result at once, which waits for it and
+    // serialises the batch. The clamped duplicates hit in cache.
     constexpr int kRows = 8;
     const bool has2 = lane < 2 * H;
-    for (int r0 = 0; r0 < 64; r0 += kRows) {
+    const int64_t gx0 = x0 - H + lane, gx1 = gx0 + 64;
+    const bool in0 = !xedge || (gx0 >= 0 && gx0 < nx);
+    const bool in1 = has2 && (!xedge || gx1 < nx);
+    const int64_t cx0 = xedge ? (gx0 < 0 ? 0 : (gx0 >= nx ? nx - 1 : gx0)) : gx0;
+    const int64_t cx1 = in1 ? gx1 : cx0;
+    // One batch of kRows region rows for a compile-time storage type XT and
+    // replacement flag RP (a run-time flag would put the mask loads under a
+    // branch, with the same effect).
+    auto stage = [&](auto xt, auto rp, int r0) {
+        constexpr int XT = decltype(xt)::value;
+        constexpr bool RP = decltype(rp)::value;
+        auto ld = [&](int64_t i) -> float {
+            if (XT == ST_F16) return f16_bits_to_float(xqp[i]);
+            if (XT == ST_BF16) return bf16_bits_to_float(xqp[i]);
+            return xp[i];
+        };
         float v0[kRows], v1[kRows];
-        uint8_t m0[kRows], m1[kRows];
+        uint32_t m0[kRows], m1[kRows];
+        bool yin[kRows];
 #pragma unroll
         for (int k = 0; k < kRows; ++k) {
             const int64_t gy = y0 - H + r0 + k;
-            const int64_t gx0 = x0 - H + lane, gx1 = gx0 + 64;
-            v0[k] = v1[k] = 0.f;
-            m0[k] = m1[k] = 0;
-            const bool yin = !yedge || (gy >= 0 && gy < ny);
-            if (yin) {
-                const int64_t row = gy * nx;
-                if (!xedge || (gx0 >= 0 && gx0 < nx)) {
-                    v0[k] = xp[row + gx0];
-                    if (repl) m0[k] = wp[row + gx0];
-                }
-                if (has2 && (!xedge || gx1 < nx)) {
-                    v1[k] = xp[row + gx1];
-                    if (repl) m1[k] = wp[row + gx1];
-                }
-            }
+            yin[k] = !yedge || (gy >= 0 && gy < ny);
+            const int64_t cy = yedge ? (gy < 0 ? 0 : (gy >= ny ? ny - 1 : gy)) : gy;
+            const int64_t row = cy * nx;
+            v0[k] = ld(row + cx0);
+            v1[k] = ld(row + cx1);
+            m0[k] = RP ? wp[row + cx0] : 0u;
+            m1[k] = RP ? wp[row + cx1] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kRows; ++k) {
             float *dst = lds + (r0 + k) * P1;
-            const bool f0 = isfinite(v0[k]), f1 = isfinite(v1[k]);
+            const bool f0 = yin[k] && in0 && isfinite(v0[k]);
+            const bool f1 = yin[k] && in1 && isfinite(v1[k]);
             float y0v = f0 ? v0[k] : 0.f, y1v = f1 ? v1[k] : 0.f;
-            if (f0 && (m0[k] & kDet)) y0v = copysignf(rv, v0[k]);
-            if (f1 && (m1[k] & kDet)) y1v = copysignf(rv, v1[k]);
+            if (RP && f0 && (m0[k] & kDet)) y0v = copysignf(rv, v0[k]);
+            if (RP && f1 && (m1[k] & kDet)) y1v = copysignf(rv, v1[k]);
             dst[lane] = y0v;
             if (has2) dst[64 + lane] = y1v;
         }
-    }
+    };
+    auto stage_all = [&](auto xt) {
+        for (int r0 = 0; r0 < 64; r0 += kRows) {
+            if (repl) stage(xt, std::true_type{}, r0);
+            else stage(xt, std::false_type{}, r0);
+        }
+    };
+    if (a.xtype == ST_F16) stage_all(std::integral_constant<int, ST_F16>{});
+    else if (a.xtype == ST_BF16) stage_all(std::integral_constant<int, ST_BF16>{});
+    else stage_all(std::integral_constant<int, ST_F32>{});
     __syncthreads();
 
     // x passes: lane = region row.
@@ -264,300 +317,6 @@ __global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
             const int64_t gy = y0 + j;
             if (!EDGE || gy < ny) pp[gy * nx] = c[H + j] * scale;
         }
-    }
-}
-
-// ------------------------------------------------------ column streaming
-
-struct ColAcc {
-    double sum;
-    unsigned long long cnt;
-};
-
-// One thread per (x, y) column. The column is streamed as a sequence of
-// input planes zi = z0 - h .. z1 - 1 + h (the leading edge of the spectral
-// window); after input zi the window sum S covers planes zi - 2h .. zi, i.e.
-// the output plane z = zi - h. Inputs are fetched in groups of G planes and
-// the next group is requested before the current one is consumed, so every
-// wave keeps up to 2G plane reads in flight. Every plane access of a block is
-// one contiguous run of 256 voxels: a uniform row pointer plus the lane.
-//
-// W is the spectral width: 1 = no spectral smoothing; an odd W >= 3 keeps the
-// window in registers with compile-time ring slots (G is a multiple of W, so
-// every group starts at slot 0); W = 0 takes the width at run time and keeps
-// the window ring in LDS. The window sum is an FP64 running sum of the FP32
-// inputs (exact while the inputs span fewer than 2^29 ulps), recomputed from
-// the ring every eight groups.
-template <int W>
-struct ColGroup {
-    static constexpr int G = W >= 3 ? W * ((8 + W - 1) / W) : 8;
-};
-
-template <int SRC, int OP, bool HASWM, int W>
-__global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
-    extern __shared__ float dyn_lds[];
-    constexpr int B = kColThreads;
-    constexpr bool SPEC = W != 1;
-    constexpr bool LDSRING = W == 0;
-    constexpr int G = ColGroup<W>::G;
-    const int tid = threadIdx.x;
-    if ((OP == OP_HIST1 || OP == OP_HIST2) && a.skip_if_captured && a.st->use_capture) return;
-    const int cb = (int)(blockIdx.x % (unsigned)a.ncb) * a.cb_stride;
-    const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
-    const int64_t ncol = a.ncol;
-    const int64_t col0 = (int64_t)cb * B;
-    const bool active = col0 + tid < ncol;
-    const int nz = (int)a.nz;
-    const int z0 = zc * a.zchunk;
-    const int z1 = min(nz, z0 + a.zchunk);
-    const int w = W == 0 ? a.w : (W >= 3 ? W : 1);
-    const int h = (w - 1) / 2;
-
-    // LDS: [ring floats [w][B] | ring bytes [w][B] (W = 0 only)] | histogram | capture
-    float *lring = dyn_lds;
-    uint8_t *lbring = (uint8_t *)(dyn_lds + (LDSRING ? w * B : 0));
-    unsigned *hist = (unsigned *)(lbring + ((LDSRING && SRC == SRC_X) ? ((w * B + 3) & ~3) : 0));
-    constexpr int kHistWords = OP == OP_HIST1 ? kL1Bins : (OP == OP_HIST2 ? 2 * kL2Coarse : 0);
-    if (kHistWords) {
-        for (int i = tid; i < kHistWords; i += B) hist[i] = 0u;
-    }
-    if (LDSRING) {
-        for (int j = 0; j < w; ++j) {
-            lring[j * B + tid] = 0.f;
-            if (SRC == SRC_X) lbring[j * B + tid] = 0;
-        }
-    }
-    if (kHistWords) __syncthreads();
-
-    const bool repl = SRC == SRC_X && HASWM && a.repl_on;
-    const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
-    const double T = (OP == OP_CLIP) ? a.st->thr : 0.0;
-    uint32_t b0 = 0xffffffffu, b1 = 0xffffffffu;
-    if (OP == OP_HIST2) { b0 = a.st->bin[0]; b1 = a.st->bin[1]; }
-    const int range = a.range;
-    ColAcc acc{0.0, 0ull};
-    const float *src = SRC == SRC_X ? a.x : a.p;
-
-    // Selection pass: count the selected voxels and the keys below the
-    // predicted window [klo, khi], and append the keys inside it, per wave, to
-    // an LDS buffer that is flushed to the global key list with one atomic
-    // per flush.
-    constexpr bool capture = OP == OP_SELECT;
-    uint32_t klo = 1, khi = 0;
-    if (capture) { klo = a.st->klo; khi = a.st->khi; }
-    unsigned n_sel = 0, n_below = 0;
-    uint32_t *capw = (uint32_t *)(hist + kHistWords) + (tid >> 6) * kCapPerWave(G);
-    int fill = 0;   // entries in this wave's buffer (same in every lane)
-    auto flush = [&]() {
-        __builtin_amdgcn_wave_barrier();
-        const unsigned long long act = __ballot(1);
-        const int leader = __ffsll((long long)act) - 1;
-        const int wlane = tid & 63;
-        unsigned long long base = 0;
-        if (wlane == leader) base = atomicAdd(a.cap_count, (unsigned long long)fill);
-        const uint32_t lo32 = __shfl((uint32_t)base, leader);
-        const uint32_t hi32 = __shfl((uint32_t)(base >> 32), leader);
-        base = ((unsigned long long)hi32 << 32) | lo32;
-        // copy with the lanes that are active (a wave may be partly idle)
-        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
-            (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
-        const int nact = __popcll(act);
-        for (int i = rank; i < fill; i += nact)
-            if (base + i < a.cap_capacity) a.cap_buf[base + i] = capw[i];
-        __builtin_amdgcn_wave_barrier();
-        fill = 0;
-    };
-
-    // Per-voxel operation on the smoothed value s of output plane zo.
-    auto consume = [&](int zo, double s, bool blank, uint8_t wb) {
-        if (OP == OP_STD) {
-            if (!blank && in_flux_range(s, range)) { acc.sum += s * s; acc.cnt += 1; }
-        } else if (OP == OP_HIST1) {
-            if (!blank && in_flux_range(s, range)) {
-                const uint32_t key = __float_as_uint(fabsf((float)s));
-                atomicAdd(&hist[key >> kL1Shift], 1u);
-            }
-        } else if (OP == OP_SELECT) {
-            const bool sel = !blank && in_flux_range(s, range);
-            const uint32_t key = __float_as_uint(fabsf((float)s));
-            n_sel += sel ? 1u : 0u;
-            n_below += (sel && key < klo) ? 1u : 0u;
-            const bool want = sel && key >= klo && key <= khi;
-            const unsigned long long bal = __ballot(want);
-            if (bal) {
-                if (want) {
-                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    capw[fill + below] = key;
-                }
-                fill += __popcll(bal);
-            }
-        } else if (OP == OP_HIST2) {
-            if (!blank && in_flux_range(s, range)) {
-                const uint32_t key = __float_as_uint(fabsf((float)s));
-                const uint32_t k1 = key >> kL1Shift;
-                const uint32_t lo = key & (kL2Bins - 1);
-                if (k1 == b0) {
-                    atomicAdd(&a.hist2[lo], 1ull);
-                    atomicAdd(&hist[lo >> kL2CoarseShift], 1u);
-                }
-                if (k1 == b1 && b1 != b0) {
-                    atomicAdd(&a.hist2[kL2Bins + lo], 1ull);
-                    atomicAdd(&hist[kL2Coarse + (lo >> kL2CoarseShift)], 1u);
-                }
-            }
-        } else if (OP == OP_CLIP) {
-            const uint8_t det = (!blank && fabs(s) > T) ? kDet : 0;
-            uint8_t out;
-            if (a.out_user) out = (uint8_t)((wb & kDet) | det);
-            else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
-            (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
-        } else {  // OP_WRITE
-            (a.s_out + (int64_t)zo * ncol + col0)[tid] = blank ? NAN : (float)s;
-        }
-    };
-
-    // Spectral input of a raw voxel: blanked -> 0, detected -> +-n sigma_0.
-    auto raw_value = [&](float xv, uint8_t wb) -> float {
-        if (!isfinite(xv)) return 0.f;
-        if (repl && (wb & kDet)) return copysignf(rv, xv);
-        return xv;
-    };
-
-    struct Group {
-        float v[G];
-        uint8_t b[G];    // working-mask byte of the input plane (SRC_X) or of
-                         // the output plane (SRC_P)
-    };
-    const int zs = SPEC ? z0 - h : z0;
-    const int ze = SPEC ? z1 + h : z1;   // exclusive
-    auto load_group = [&](int zb, Group &g) {
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            const int zi = zb + j;
-            g.v[j] = 0.f;
-            g.b[j] = 0;
-            if (zi < ze && zi >= 0 && zi < nz) {
-                const int64_t off = (int64_t)zi * ncol + col0;
-                g.v[j] = (src + off)[tid];
-                if (SRC == SRC_X && HASWM) g.b[j] = (a.wm_in + off)[tid];
-            }
-            if (SRC == SRC_P) {
-                const int zo = zi - h;
-                if (zi < ze && zo >= z0) g.b[j] = (a.wm_in + (int64_t)zo * ncol + col0)[tid];
-            }
-        }
-    };
-
-    float ring[W >= 3 ? W : 1];
-    uint8_t bring[W >= 3 ? W : 1];
-#pragma unroll
-    for (int j = 0; j < (W >= 3 ? W : 1); ++j) { ring[j] = 0.f; bring[j] = 0; }
-    int lslot = 0;           // W = 0: LDS ring slot of the next input
-    double S = 0.0;
-    const double inv_w = 1.0 / (double)w;
-    int groups = 0;
-
-    auto process_group = [&](int zb, const Group &g) {
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            const int zi = zb + j;
-            if (zi >= ze) break;
-            if (!SPEC) {
-                if (SRC == SRC_X) {
-                    const bool blank = !isfinite(g.v[j]);
-                    consume(zi, (double)raw_value(g.v[j], g.b[j]), blank, g.b[j]);
-                } else {
-                    consume(zi, (double)g.v[j], (g.b[j] & kBlank) != 0, g.b[j]);
-                }
-                continue;
-            }
-            const float vn = SRC == SRC_X ? raw_value(g.v[j], g.b[j]) : g.v[j];
-            float vo;
-            uint8_t wb_out = g.b[j];
-            if (LDSRING) {
-                vo = lring[lslot * B + tid];
-                lring[lslot * B + tid] = vn;
-                if (SRC == SRC_X) {
-                    lbring[lslot * B + tid] = g.b[j];
-                    int os = lslot + h + 1;
-                    if (os >= w) os -= w;
-                    wb_out = lbring[os * B + tid];
-                }
-                if (++lslot == w) lslot = 0;
-            } else {
-                constexpr int kW = W >= 3 ? W : 1;
-                const int sl = j % kW;
-                vo = ring[sl];
-                ring[sl] = vn;
-                if (SRC == SRC_X) {
-                    bring[sl] = g.b[j];
-                    wb_out = bring[(j + kW - (kW - 1) / 2) % kW];
-                }
-            }
-            S += (double)vn - (double)vo;
-            const int zo = zi - h;
-            if (zo >= z0) consume(zo, S * inv_w, (wb_out & kBlank) != 0, wb_out);
-        }
-        // The buffer holds one more group on top of kCapFlushAt entries.
-        if (capture && fill > kCapFlushAt) flush();
-        if (SPEC && (++groups & 7) == 0) {   // re-anchor the running sum
-            S = 0.0;
-            if (LDSRING) {
-                for (int j = 0; j < w; ++j) S += (double)lring[j * B + tid];
-            } else {
-#pragma unroll
-                for (int j = 0; j < (W >= 3 ? W : 1); ++j) S += (double)ring[j];
-            }
-        }
-    };
-
-    if (active) {
-        Group ga, gb;
-        load_group(zs, ga);
-        for (int zb = zs; zb < ze; zb += 2 * G) {
-            if (zb + G < ze) load_group(zb + G, gb);
-            process_group(zb, ga);
-            if (zb + G >= ze) break;
-            if (zb + 2 * G < ze) load_group(zb + 2 * G, ga);
-            process_group(zb + G, gb);
-        }
-        if (capture && fill > 0) flush();
-    }
-
-    if (OP == OP_STD) {
-        // Block reduction in a fixed order: deterministic partials.
-        __shared__ double rs[B];
-        __shared__ unsigned long long rc[B];
-        rs[tid] = acc.sum;
-        rc[tid] = acc.cnt;
-        __syncthreads();
-        for (int off = B / 2; off > 0; off >>= 1) {
-            if (tid < off) { rs[tid] += rs[tid + off]; rc[tid] += rc[tid + off]; }
-            __syncthreads();
-        }
-        if (tid == 0) { a.part_sum[blockIdx.x] = rs[0]; a.part_cnt[blockIdx.x] = rc[0]; }
-    } else if (OP == OP_HIST1) {
-        __syncthreads();
-        for (int i = tid; i < kL1Bins; i += B)
-            if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
-    } else if (OP == OP_SELECT) {
-        __shared__ unsigned long long rc[2][B];
-        rc[0][tid] = n_sel;
-        rc[1][tid] = n_below;
-        __syncthreads();
-        for (int off = B / 2; off > 0; off >>= 1) {
-            if (tid < off) { rc[0][tid] += rc[0][tid + off]; rc[1][tid] += rc[1][tid + off]; }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            if (rc[0][0]) atomicAdd(&a.sel_counts[0], rc[0][0]);
-            if (rc[1][0]) atomicAdd(&a.sel_counts[1], rc[1][0]);
-        }
-    } else if (OP == OP_HIST2) {
-        __syncthreads();
-        for (int i = tid; i < 2 * kL2Coarse; i += B)
-            if (hist[i]) atomicAdd(&a.hist2c[i], (unsigned long long)hist[i]);
     }
 }
 
@@ -870,6 +629,23 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_quantize(const float *x, const DevState *st, double scale, int type,
+                           uint16_t *out, int64_t n, hipStream_t s) {
+    const dim3 grid(grid_for(n, 256, 16384)), block(256);
+    if (type == ST_F16)
+        hipLaunchKernelGGL(k_quantize<ST_F16>, grid, block, 0, s, x, st, scale, out, n);
+    else if (type == ST_BF16)
+        hipLaunchKernelGGL(k_quantize<ST_BF16>, grid, block, 0, s, x, st, scale, out, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_enter_scaled(DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_enter_scaled, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s) {
     hipLaunchKernelGGL(k_set_sigma0, dim3(1), dim3(64), 0, s, st, sigma0);
     return hipGetLastError();
@@ -908,84 +684,21 @@ hipError_t launch_spatial(int n_iter, int radius, const SpatialArgs &a,
     return hipErrorInvalidValue;
 }
 
-// Spectral widths with a register ring; any other odd width up to
-// SOFIA_SC_MAX_WIDTH uses the LDS ring.
-static int ring_template_width(int w) {
-    switch (w) {
-        case 1: case 3: case 5: case 7: case 9: case 11: case 15: case 21: case 31: return w;
-    }
-    return 0;
-}
-
-size_t column_lds_bytes(int src, int op, bool spectral, int w) {
-    size_t b = 0;
-    const bool lds_ring = spectral && ring_template_width(w) == 0;
-    if (lds_ring) b += (size_t)w * kColThreads * sizeof(float);
-    if (lds_ring && src == SRC_X) b += ((size_t)w * kColThreads + 3) & ~(size_t)3;
-    if (op == OP_HIST1) b += (size_t)kL1Bins * sizeof(unsigned);
-    if (op == OP_SELECT) {
-        const int tw = spectral ? ring_template_width(w) : 1;
-        const int group = tw >= 3 ? tw * ((8 + tw - 1) / tw) : 8;
-        b += (size_t)(kColThreads / 64) * kCapPerWave(group) * sizeof(uint32_t);
-    }
-    if (op == OP_HIST2) b += (size_t)2 * kL2Coarse * sizeof(unsigned);
-    return b;
-}
-
-template <int SRC, int OP, bool HASWM, int W>
-static hipError_t column_inst(const ColArgs &a, int nblocks, hipStream_t s) {
-    const size_t lds = column_lds_bytes(SRC, OP, W != 1, a.w);
-    hipLaunchKernelGGL((k_column<SRC, OP, HASWM, W>), dim3(nblocks), dim3(kColThreads), lds,
-                       s, a);
-    return hipGetLastError();
-}
-
-template <int SRC, int OP, bool HASWM>
-static hipError_t column_width(int w, const ColArgs &a, int nb, hipStream_t s) {
-    switch (ring_template_width(w)) {
-        case 1: return column_inst<SRC, OP, HASWM, 1>(a, nb, s);
-        case 3: return column_inst<SRC, OP, HASWM, 3>(a, nb, s);
-        case 5: return column_inst<SRC, OP, HASWM, 5>(a, nb, s);
-        case 7: return column_inst<SRC, OP, HASWM, 7>(a, nb, s);
-        case 9: return column_inst<SRC, OP, HASWM, 9>(a, nb, s);
-        case 11: return column_inst<SRC, OP, HASWM, 11>(a, nb, s);
-        case 15: return column_inst<SRC, OP, HASWM, 15>(a, nb, s);
-        case 21: return column_inst<SRC, OP, HASWM, 21>(a, nb, s);
-        case 31: return column_inst<SRC, OP, HASWM, 31>(a, nb, s);
-        default: return column_inst<SRC, OP, HASWM, 0>(a, nb, s);
-    }
-}
-
-template <int SRC, int OP>
-static hipError_t column_op(bool spec, bool has_wm, const ColArgs &a, int nb,
-                            hipStream_t s) {
-    const int w = spec ? a.w : 1;
-    if (SRC == SRC_P || spec) {
-        if (!has_wm) return hipErrorInvalidValue;
-        return column_width<SRC, OP, true>(w, a, nb, s);
-    }
-    return has_wm ? column_inst<SRC, OP, true, 1>(a, nb, s)
-                  : column_inst<SRC, OP, false, 1>(a, nb, s);
-}
-
-template <int SRC>
-static hipError_t column_src(int op, bool spec, bool has_wm, const ColArgs &a,
-                             int nb, hipStream_t s) {
-    switch (op) {
-        case OP_STD: return column_op<SRC, OP_STD>(spec, has_wm, a, nb, s);
-        case OP_HIST1: return column_op<SRC, OP_HIST1>(spec, has_wm, a, nb, s);
-        case OP_HIST2: return column_op<SRC, OP_HIST2>(spec, has_wm, a, nb, s);
-        case OP_CLIP: return column_op<SRC, OP_CLIP>(spec, has_wm, a, nb, s);
-        case OP_WRITE: return column_op<SRC, OP_WRITE>(spec, has_wm, a, nb, s);
-        case OP_SELECT: return column_op<SRC, OP_SELECT>(spec, has_wm, a, nb, s);
-    }
-    return hipErrorInvalidValue;
-}
+template <int OP>
+hipError_t launch_column_op(int src, bool spec, bool has_wm, const ColArgs &a, int nb,
+                            hipStream_t s);
 
 hipError_t launch_column(int src, int op, bool spectral, bool has_wm,
                          const ColArgs &a, int nblocks, hipStream_t s) {
-    return src == SRC_X ? column_src<SRC_X>(op, spectral, has_wm, a, nblocks, s)
-                        : column_src<SRC_P>(op, spectral, has_wm, a, nblocks, s);
+    switch (op) {
+        case OP_STD: return launch_column_op<OP_STD>(src, spectral, has_wm, a, nblocks, s);
+        case OP_HIST1: return launch_column_op<OP_HIST1>(src, spectral, has_wm, a, nblocks, s);
+        case OP_HIST2: return launch_column_op<OP_HIST2>(src, spectral, has_wm, a, nblocks, s);
+        case OP_CLIP: return launch_column_op<OP_CLIP>(src, spectral, has_wm, a, nblocks, s);
+        case OP_WRITE: return launch_column_op<OP_WRITE>(src, spectral, has_wm, a, nblocks, s);
+        case OP_SELECT: return launch_column_op<OP_SELECT>(src, spectral, has_wm, a, nblocks, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize_std(DevState *st, const double *part_sum,

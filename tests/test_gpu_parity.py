@@ -4,6 +4,7 @@ Tolerances: a mask must equal the oracle's on every voxel outside the
 boundary band (voxels with | |s|/sigma_k - t | <= 1e-5, reported by the
 oracle); noise values must agree to 1e-6 relative.
 """
+import ctypes
 import math
 import sys
 
@@ -222,6 +223,35 @@ def test_bad_arguments_raise_einval(h):
         with pytest.raises(sc.ScError) as e:
             h.run(x, kernels, t, "std", "all")
         assert e.value.code == sc.EINVAL
+
+
+def test_step_ex_f32_equals_step_and_checks_options(h):
+    x = cfg2_like(90, 70, 60, seed=44, n_gal=4)
+    xd = dev(x)
+    s0, _ = oracle.noise(np.where(np.isfinite(x), x, np.nan).astype(np.float64),
+                         "mad", "negative")
+    m1, _ = h.step(xd, (0.0, 0), 3.5, "mad", "negative", 2.0, s0)
+    for kern in [(0.0, 0), (3.0, 7), (6.0, 15)]:
+        a, sa = h.step(xd, kern, 3.5, "mad", "negative", 2.0, s0, mask_in=m1)
+        b, sb = h.step_ex(xd, kern, 3.5, "mad", "negative", mask_in=m1, replacement=2.0,
+                          sigma0=s0)
+        assert sa == sb
+        assert torch.equal(a, b)
+    # 16-bit storage needs the scale; unknown storage and bad struct sizes fail
+    with pytest.raises(sc.ScError) as e:
+        h.step_ex(xd, (3.0, 3), 3.5, "mad", "negative", replacement=-1.0, storage="bf16")
+    assert e.value.code == sc.EINVAL
+    opt = sc.Options()
+    h.lib.sofia_sc_default_options(ctypes.byref(opt))
+    noise = ctypes.c_double()
+    out = torch.empty(xd.shape, dtype=torch.uint8, device=xd.device)
+    k = sc.Kernel(3.0, 3)
+    for field, val in [("struct_size", 8), ("storage", 7), ("reserved", 1)]:
+        bad = sc.Options.from_buffer_copy(opt)
+        setattr(bad, field, val)
+        rc = h.lib.sofia_sc_step_ex(h.h, xd.data_ptr(), 90, 70, 60, k, 3.5, 1, -1, None,
+                                    out.data_ptr(), ctypes.byref(noise), ctypes.byref(bad))
+        assert rc == sc.EINVAL and np.isnan(noise.value), field
 
 
 # ------------------------------------------------------------------ invariants
