@@ -65,6 +65,8 @@ struct sofia_sc {
     size_t cap_cap = 0;
     uint16_t *xq = nullptr;
     size_t xq_cap = 0;
+    uint64_t *det = nullptr;         // packed detection bits (spatial replacement)
+    size_t det_cap = 0;              // in words
     bool prof = false;
     std::vector<LaunchRec> recs;
     std::vector<hipEvent_t> pool;
@@ -202,8 +204,20 @@ int ensure_q16(sofia_sc *h, int64_t N) {
     return SOFIA_SC_OK;
 }
 
-int ensure_workspace(sofia_sc *h, int64_t N, bool need_p, size_t parts) {
+// Packed detection bits: words per plane of nx * ny voxels.
+int64_t det_words_per_plane(int64_t ncol) { return (ncol + 63) / 64; }
+
+int ensure_workspace(sofia_sc *h, int64_t N, bool need_p, size_t parts,
+                     int64_t det_words = 0) {
     hipError_t e;
+    if ((size_t)det_words > h->det_cap) {
+        if (h->det) (void)hipFree(h->det);
+        h->det = nullptr;
+        h->det_cap = 0;
+        if ((e = hipMalloc(&h->det, (size_t)det_words * sizeof(uint64_t))) != hipSuccess)
+            return fail(h, SOFIA_SC_ENOMEM, std::string("detection bits: ") + hipGetErrorString(e));
+        h->det_cap = (size_t)det_words;
+    }
     if (!h->st) {
         if ((e = hipMalloc(&h->st, sizeof(DevState))) != hipSuccess)
             return fail(h, SOFIA_SC_ENOMEM, std::string("state: ") + hipGetErrorString(e));
@@ -328,6 +342,8 @@ struct PairJob {
     bool out_user;
     bool also_sigma0;
     float *write_out;
+    bool det_live = false;  // this call sized h->det for the cube: the clip keeps
+                            // the packed detection bits, the spatial pass reads them
 };
 
 int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
@@ -345,26 +361,26 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
         return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
     if (spatial) {
-        const int ty = spatial_tile_rows(j.pl.n_iter, j.pl.radius);
-        const int64_t tiles = ((d.nx + 63) / 64) * ((d.ny + ty - 1) / ty);
-        if (tiles * d.nz > 0x7fffffffLL)
-            return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
-        SpatialArgs a{};
-        a.x = j.x;
-        a.xq = j.xq;
-        a.xtype = j.xtype;
-        a.wm = j.repl_active ? j.wm_in : nullptr;
+        StripArgs a{};
+        a.x = j.xtype == ST_F32 ? j.x : nullptr;
+        a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
+        a.wpp = det_words_per_plane(d.ncol);
+        a.det = nullptr;
+        if (j.repl_active) {
+            if (!j.det_live || h->det_cap < (size_t)(d.nz * a.wpp))
+                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
+            a.det = h->det;
+        }
         a.p = h->p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
-        a.tiles_x = (int)((d.nx + 63) / 64);
-        a.tiles_y = (int)((d.ny + ty - 1) / ty);
-        spatial_interior(a, j.pl.n_iter, j.pl.radius);
-        a.repl_on = j.repl_active ? 1 : 0;
+        spatial_strips(a, j.pl.n_iter, j.pl.radius);
+        if (a.tiles > 0x7fffffffLL)
+            return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
         a.repl_n = j.repl_n;
         a.st = h->st;
         const double bytes = N * (bx + (j.repl_active ? 1.0 : 0.0) + 4.0);
         rc = launch(h, s, F_SPATIAL, bytes, N, [&] {
-            return launch_spatial(j.pl.n_iter, j.pl.radius, a, s);
+            return launch_spatial(j.pl.n_iter, j.pl.radius, j.xtype, j.repl_active, a, s);
         });
         if (rc) return rc;
     }
@@ -494,7 +510,16 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     if (j.clip_out) {
         c.mask_out = j.clip_out;
         c.out_user = j.out_user ? 1 : 0;
-        if ((rc = col(OP_CLIP, F_COL_CLIP, rd + N))) return rc;
+        // a later spatial kernel replaces detections: keep the packed bits
+        c.wpp = det_words_per_plane(d.ncol);
+        c.det_bits = nullptr;
+        if (j.det_live && !j.out_user) {
+            if (h->det_cap < (size_t)(d.nz * c.wpp))
+                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
+            c.det_bits = h->det;
+        }
+        const double det_bytes = c.det_bits ? N / 8.0 : 0.0;
+        if ((rc = col(OP_CLIP, F_COL_CLIP, rd + N + det_bytes))) return rc;
     }
     return SOFIA_SC_OK;
 }
@@ -566,7 +591,9 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
     const ColGrid g = col_grid(d.ncol, d.nz);
     const bool q16 = storage != SOFIA_SC_STORE_F32;
-    if ((rc = ensure_workspace(h, d.N, any_spatial, (size_t)g.blocks()))) return rc;
+    if ((rc = ensure_workspace(h, d.N, any_spatial, (size_t)g.blocks(),
+                               any_spatial ? d.nz * det_words_per_plane(d.ncol) : 0)))
+        return rc;
     if (q16 && (rc = ensure_q16(h, d.N))) return rc;
 
     const bool repl_on = opt->replacement >= 0.0;
@@ -606,7 +633,8 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
         uint8_t *out = last ? mask : (have_wm ? h->wm[1 - cur] : h->wm[cur]);
         PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, plans[k], k, repl_on && k >= 1,
                   opt->replacement, mode, range, t, have_wm ? h->wm[cur] : nullptr, out, last,
-                  k == 0 && first_identity && repl_on && !given0 && !q16, nullptr};
+                  k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
+                  any_spatial};
         if ((rc = run_pair(h, s, j))) return rc;
         if (!last) {
             if (have_wm) cur = 1 - cur;
@@ -689,6 +717,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->part_cnt) (void)hipFree(h->part_cnt);
         if (h->cap_buf) (void)hipFree(h->cap_buf);
         if (h->xq) (void)hipFree(h->xq);
+        if (h->det) (void)hipFree(h->det);
     }
     delete h;
 }
@@ -746,7 +775,9 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     hipStream_t s = (hipStream_t)stream;
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
     const ColGrid g = col_grid(d.ncol, d.nz);
-    if ((rc = ensure_workspace(h, d.N, pl.spatial(), (size_t)g.blocks()))) return rc;
+    if ((rc = ensure_workspace(h, d.N, pl.spatial(), (size_t)g.blocks(),
+                               pl.spatial() ? d.nz * det_words_per_plane(d.ncol) : 0)))
+        return rc;
     if (q16 && (rc = ensure_q16(h, d.N))) return rc;
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
         return launch_set_sigma0(h->st, (repl || q16) ? sigma0 : NAN, s);
@@ -756,6 +787,13 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
         return launch_init_mask(cube, mask_in, h->wm[0], d.N, s);
     });
     if (rc) return rc;
+    if (pl.spatial() && repl) {
+        rc = launch(h, s, F_INIT, 1.125 * d.N, (double)d.N, [&] {
+            return launch_pack_det(h->wm[0], h->det, d.ncol, d.nz,
+                                   det_words_per_plane(d.ncol), s);
+        });
+        if (rc) return rc;
+    }
     int xtype = ST_F32;
     if (q16) {
         xtype = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
@@ -768,7 +806,8 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     }
     PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, pl, 0, repl, replacement,
               write_out ? 0 : mode, write_out ? 0 : range, write_out ? 1.0 : threshold,
-              h->wm[0], write_out ? nullptr : mask_out, true, false, write_out};
+              h->wm[0], write_out ? nullptr : mask_out, true, false, write_out,
+              pl.spatial()};
     if ((rc = run_pair(h, s, j))) return rc;
     if ((rc = finish(h, s))) return rc;
     if (write_out) return SOFIA_SC_OK;

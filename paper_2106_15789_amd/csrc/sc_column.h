@@ -152,6 +152,11 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             if (a.out_user) out = (uint8_t)((wb & kDet) | det);
             else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
             (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
+            if (a.det_bits) {
+                // the wave's 64 columns start at a multiple of 64: one word
+                const uint64_t bits = __ballot((out & kDet) != 0);
+                if ((tid & 63) == 0) a.det_bits[zo * a.wpp + ((col0 + tid) >> 6)] = bits;
+            }
         } else {  // OP_WRITE
             (a.s_out + (int64_t)zo * ncol + col0)[tid] = blank ? NAN : (float)s;
         }

@@ -11,7 +11,10 @@ namespace sc {
 
 // Working-mask bits. The library keeps its own per-voxel byte: bit 0 = in the
 // detection mask so far, bit 1 = blanked (non-finite input). The caller's
-// mask only ever receives 0/1.
+// mask only ever receives 0/1. Next to it, the detection bits alone are kept
+// packed, 64 voxels of a row-major plane per word, for the spatial kernel:
+// its waves need them across 64 unaligned columns per row, which a byte per
+// lane would fetch several times over.
 constexpr uint8_t kDet = 1;
 constexpr uint8_t kBlank = 2;
 
@@ -92,23 +95,28 @@ struct ColArgs {
     unsigned long long *cap_count;
     unsigned long long cap_capacity;
     unsigned long long *sel_counts;  // OP_SELECT: [selected voxels, keys below klo]
+    uint64_t *det_bits;          // OP_CLIP: packed detection bits out (may be null)
+    int64_t wpp;                 // 64-bit words per plane of det_bits
 };
 
-struct SpatialArgs {
-    const float *x;
-    const uint16_t *xq;          // 16-bit storage of the cube (xtype != ST_F32)
-    int32_t xtype;
-    int32_t pad0;
-    const uint8_t *wm;           // may be null (no replacement)
-    float *p;
+// Arguments of the strip-streaming spatial kernel. A strip is 128 adjacent
+// columns of one plane (128 - 2H of them output columns, H = n r); a wave
+// streams one chunk of `rows` rows of it.
+struct StripArgs {
+    const float *x;              // raw cube (ST_F32)
+    const uint16_t *xq;          // raw cube stored as 16 bits (ST_F16 / ST_BF16)
+    const uint64_t *det;         // packed detection bits (replacement only)
+    int64_t wpp;                 // 64-bit words per plane of det
+    float *p;                    // output: spatially smoothed cube
     int64_t nx, ny, nz;
-    int32_t tiles_x, tiles_y;    // tiles per plane along x and y
-    int32_t tx_begin, ntx;       // interior tiles: region inside the cube
-    int32_t ty_begin, nty;
-    int64_t tiles_per_plane;     // set per launch (interior or edge set)
-    int32_t repl_on;
+    int32_t nstrips;             // strips across x
+    int32_t wpb;                 // strips (waves) per workgroup
+    int32_t ngroups;             // workgroups across x: ceil(nstrips / wpb)
+    int32_t rows;                // output rows per chunk
+    int32_t nchunks;             // chunks per plane
     int32_t pad;
-    double repl_n;
+    int64_t tiles;               // workgroups: ngroups * nchunks * nz
+    double repl_n;               // n of +-n sigma_0
     const DevState *st;
 };
 
@@ -116,8 +124,16 @@ struct SpatialArgs {
 hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
                             int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
-hipError_t launch_spatial(int n_iter, int radius, const SpatialArgs &a,
-                          hipStream_t s);
+// Packed detection bits of a working mask (detected and not blanked); word
+// w of plane z holds columns 64w .. 64w+63 of that plane, bit b = column
+// 64w + b.
+hipError_t launch_pack_det(const uint8_t *wm, uint64_t *det, int64_t ncol, int64_t nz,
+                           int64_t wpp, hipStream_t s);
+// Spatial cascade of n_iter boxcars of radius r per axis into a.p.
+hipError_t launch_spatial(int n_iter, int radius, int xtype, bool repl,
+                          const StripArgs &a, hipStream_t s);
+template <int R, int NIT>
+hipError_t launch_strip(const StripArgs &a, int xtype, bool repl, hipStream_t s);
 hipError_t launch_column(int src, int op, bool spectral, bool has_wm,
                          const ColArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_finalize_std(DevState *st, const double *part_sum,
@@ -154,22 +170,30 @@ hipError_t launch_enter_scaled(DevState *st, hipStream_t s);
 constexpr int kColThreads = 256;
 size_t column_lds_bytes(int src, int op, bool spectral, int w);
 
-// Spatial tile: 64 columns x (64 - 2 n r) rows per one-wave block.
-inline int spatial_tile_rows(int n_iter, int radius) { return 64 - 2 * n_iter * radius; }
+// The spatial kernel's wave covers a strip of kStripCols columns (two per
+// lane); a workgroup holds the waves of up to kStripWaves adjacent strips of
+// the same rows, which stage each row's span once in LDS.
+constexpr int kStripCols = 128;
+constexpr int kStripWaves = 4;
 
-// Interior tile rectangle: tiles whose region (tile plus halo) lies inside
-// the cube, so the cascade needs no edge handling there.
-inline void spatial_interior(SpatialArgs &a, int n_iter, int radius) {
-    const int64_t H = (int64_t)n_iter * radius, TY = spatial_tile_rows(n_iter, radius);
-    int64_t tx0 = (H + 63) / 64, tx1 = a.nx - 64 - H >= 0 ? (a.nx - 64 - H) / 64 + 1 : 0;
-    int64_t ty0 = (H + TY - 1) / TY, ty1 = a.ny - 64 + H >= 0 ? (a.ny - 64 + H) / TY + 1 : 0;
-    if (tx1 > a.tiles_x) tx1 = a.tiles_x;
-    if (ty1 > a.tiles_y) ty1 = a.tiles_y;
-    if (tx1 <= tx0 || ty1 <= ty0) { tx0 = tx1 = ty0 = ty1 = 0; }
-    a.tx_begin = (int32_t)tx0;
-    a.ntx = (int32_t)(tx1 - tx0);
-    a.ty_begin = (int32_t)ty0;
-    a.nty = (int32_t)(ty1 - ty0);
+// Strip geometry of the spatial kernel for a cube of width nx and halo H:
+// strips of kStripCols - 2H output columns, up to kStripWaves adjacent
+// strips per workgroup (spread evenly over the groups a row needs), rows in
+// chunks.
+inline void spatial_strips(StripArgs &a, int n_iter, int radius) {
+    const int64_t H = (int64_t)n_iter * radius, W = kStripCols - 2 * H;
+    a.nstrips = (int32_t)((a.nx + W - 1) / W);
+    const int64_t groups = (a.nstrips + kStripWaves - 1) / kStripWaves;
+    a.wpb = (int32_t)((a.nstrips + groups - 1) / groups);
+    a.ngroups = (int32_t)((a.nstrips + a.wpb - 1) / a.wpb);
+    // rows per chunk: long chunks keep the y halo small; shorter ones when
+    // the cube is too small to give the chip enough waves otherwise
+    int64_t rows = 256;
+    while (rows > 32 && a.nstrips * ((a.ny + rows - 1) / rows) * a.nz < 16384) rows /= 2;
+    if (rows > a.ny) rows = a.ny;
+    a.rows = (int32_t)rows;
+    a.nchunks = (int32_t)((a.ny + rows - 1) / rows);
+    a.tiles = (int64_t)a.ngroups * a.nchunks * a.nz;
 }
 
 }  // namespace sc

@@ -8,11 +8,10 @@
 //
 // Work split, chosen for HBM streaming rather than for the paper's OpenMP
 // loops:
-//  * k_spatial: one wave per 64-column tile of one z-plane. The tile plus
-//    its halo is staged in LDS; each lane then runs the x passes of the
-//    cascade on one row held in registers, the block is transposed through
-//    LDS, and each lane runs the y passes on one column. Output: the
-//    spatially smoothed plane (float32) in a work buffer.
+//  * k_strip (sc_spatial.h): one wave per strip of 64 columns of one
+//    z-plane streams a chunk of rows; x passes across the lanes (DPP wave
+//    shifts), y passes as running sums down the rows. Output: the spatially
+//    smoothed cube (float32) in a work buffer.
 //  * k_column: one thread per (x, y) column streams z with a ring of the
 //    last w inputs in LDS and an FP64 running sum (exact for FP32 inputs),
 //    and performs one per-voxel operation: accumulate sum s^2 (std noise),
@@ -22,8 +21,6 @@
 //  * tiny one-block kernels turn the partial sums / histograms into sigma_k
 //    on the device, so a run never waits on the host between launches.
 #include <math.h>
-
-#include <type_traits>
 
 #include "sc_device.h"
 
@@ -50,6 +47,24 @@ __global__ void k_init_mask(const float *__restrict__ x,
         uint8_t b = isfinite(x[i]) ? 0 : kBlank;
         if (mask_in && mask_in[i]) b |= kDet;
         wm[i] = b;
+    }
+}
+
+// One wave per (plane, word): lane l reads column 64w + l of the working
+// mask. A bit is set for detected voxels that are not blanked (a caller's
+// mask may mark blanked voxels; they are never replaced).
+__global__ void k_pack_det(const uint8_t *__restrict__ wm, uint64_t *__restrict__ det,
+                           int64_t ncol, int64_t nz, int64_t wpp) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = nz * wpp;
+    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nw;
+         w += wstride) {
+        const int64_t z = w / wpp, col = (w - z * wpp) * 64 + lane;
+        const uint8_t b = col < ncol ? wm[z * ncol + col] : (uint8_t)0;
+        const bool d = (b & kDet) && !(b & kBlank);
+        const uint64_t bits = __ballot(d);
+        if (lane == 0) det[w] = bits;
     }
 }
 
@@ -105,218 +120,6 @@ __global__ void k_set_sigma0(DevState *st, double sigma0) {
         st->fallback = 0ull;
         st->scale = 1.0;
         for (int k = 0; k < SOFIA_SC_MAX_KERNELS; ++k) st->sigma[k] = NAN;
-    }
-}
-
-// ------------------------------------------------------ spatial cascade
-
-// One boxcar pass over register array `in`, writing out[i] for i in
-// [LO, HI): the unnormalised sum of in[i-R .. i+R]. The running sum is kept
-// in FP64, which holds sums of FP32 values exactly, so each output carries a
-// single FP32 rounding; it is recomputed directly every kAnchor outputs.
-constexpr int kAnchor = 32;
-template <int N, int R, int LO, int HI>
-__device__ __forceinline__ void box_pass(const float (&in)[N], float (&out)[N]) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = LO; i < HI; ++i) {
-        if ((i - LO) % kAnchor == 0) {
-            s = 0.0;
-#pragma unroll
-            for (int j = -R; j <= R; ++j) s += (double)in[i + j];
-        } else {
-            s += (double)in[i + R] - (double)in[i - R - 1];
-        }
-        out[i] = (float)s;
-    }
-}
-
-// Pass P of NIT. Input valid on [(P-1)R, N-(P-1)R); output on [PR, N-PR).
-// With EDGE set, entries whose global coordinate lies outside the cube
-// (local index outside [lo, hi), the same for every lane) are zeroed after
-// each pass, so every pass sees zeros beyond the cube edge; the zeroing is a
-// multiply by a uniform 0/1 so it stays branch-free.
-template <int N, int R, int P, int NIT, bool EDGE>
-struct Cascade {
-    __device__ __forceinline__ static void run(float (&v)[N], int lo, int hi) {
-        float o[N];
-        box_pass<N, R, P * R, N - P * R>(v, o);
-#pragma unroll
-        for (int i = P * R; i < N - P * R; ++i) {
-            if (EDGE) {
-                const float keep = (i >= lo && i < hi) ? 1.f : 0.f;
-                v[i] = o[i] * keep;
-            } else {
-                v[i] = o[i];
-            }
-        }
-        Cascade<N, R, P + 1, NIT, EDGE>::run(v, lo, hi);
-    }
-};
-template <int N, int R, int NIT, bool EDGE>
-struct Cascade<N, R, NIT + 1, NIT, EDGE> {
-    __device__ __forceinline__ static void run(float (&)[N], int, int) {}
-};
-
-// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
-// b % 8). Remap so that each XCD works through one contiguous range of
-// tiles: neighbouring tiles then share their halo rows and columns through
-// the same L2 instead of fetching them from HBM once per XCD.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
-    const int64_t q = nb / 8, r = nb % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
-}
-
-// Tile of the launch: interior launches cover the rectangle of tiles whose
-// region lies inside the cube; edge launches cover the ring of the others.
-__device__ __forceinline__ void spatial_tile(const SpatialArgs &a, bool edge, int64_t t,
-                                             int &tx, int &ty) {
-    if (!edge) {
-        ty = a.ty_begin + (int)(t / a.ntx);
-        tx = a.tx_begin + (int)(t - (int64_t)(ty - a.ty_begin) * a.ntx);
-        return;
-    }
-    const int64_t T = a.tiles_x;
-    const int64_t above = a.ty_begin, below = a.tiles_y - a.ty_begin - a.nty;
-    const int64_t left = a.tx_begin, right = a.tiles_x - a.tx_begin - a.ntx;
-    if (t < above * T) {
-        ty = (int)(t / T);
-        tx = (int)(t - (int64_t)ty * T);
-    } else if (t < (above + below) * T) {
-        const int64_t j = t - above * T;
-        ty = (int)(a.ty_begin + a.nty + j / T);
-        tx = (int)(j % T);
-    } else {
-        const int64_t j = t - (above + below) * T, per = left + right;
-        const int64_t row = j / per, k = j - row * per;
-        ty = (int)(a.ty_begin + row);
-        tx = (int)(k < left ? k : a.tx_begin + a.ntx + (k - left));
-    }
-}
-
-template <int R, int NIT, bool EDGE>
-__global__ __launch_bounds__(64) void k_spatial(SpatialArgs a) {
-    constexpr int H = R * NIT;          // halo consumed by the cascade
-    constexpr int RW = 64 + 2 * H;      // region width
-    constexpr int P1 = RW + 1;          // odd LDS pitch: conflict-free rows
-    constexpr int P2 = 65;
-    constexpr int TY = 64 - 2 * H;      // output rows per tile
-    static_assert(TY >= 1, "halo too large for a 64-row region");
-    static_assert(2 * H <= 64, "second column strip must fit in one wave");
-    __shared__ float lds[64 * P1];
-
-    const int lane = threadIdx.x;
-    const int64_t tiles = a.tiles_per_plane;
-    const int64_t tile = xcd_remap((int64_t)blockIdx.x, tiles * a.nz);
-    const int64_t z = tile / tiles;
-    int tx, ty;
-    spatial_tile(a, EDGE, tile - z * tiles, tx, ty);
-    const int64_t nx = a.nx, ny = a.ny;
-    const int64_t x0 = (int64_t)tx * 64, y0 = (int64_t)ty * TY;
-    const float *xp = a.x ? a.x + z * nx * ny : nullptr;
-    const uint16_t *xqp = a.xq ? a.xq + z * nx * ny : nullptr;
-    const uint8_t *wp = a.wm ? a.wm + z * nx * ny : nullptr;
-    const bool repl = a.repl_on && wp != nullptr;
-    const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
-    const bool xedge = EDGE && ((x0 - H < 0) || (x0 + 64 + H > nx));
-    const bool yedge = EDGE && ((y0 - H < 0) || (y0 - H + 64 > ny));
-
-    // Stage the region (64 rows x RW columns): lanes take columns lane and
-    // 64 + lane (the latter only for the 2H right-halo columns). Rows are
-    // fetched in batches so many loads are in flight at once. Every lane
-    // loads, from coordinates clamped into the cube, and what lies outside
-    // is zeroed afterwards: a load under a divergent branch makes the
-    // compiler merge or convert its result at once, which waits for it and
-    // serialises the batch. The clamped duplicates hit in cache.
-    constexpr int kRows = 8;
-    const bool has2 = lane < 2 * H;
-    const int64_t gx0 = x0 - H + lane, gx1 = gx0 + 64;
-    const bool in0 = !xedge || (gx0 >= 0 && gx0 < nx);
-    const bool in1 = has2 && (!xedge || gx1 < nx);
-    const int64_t cx0 = xedge ? (gx0 < 0 ? 0 : (gx0 >= nx ? nx - 1 : gx0)) : gx0;
-    const int64_t cx1 = in1 ? gx1 : cx0;
-    // One batch of kRows region rows for a compile-time storage type XT and
-    // replacement flag RP (a run-time flag would put the mask loads under a
-    // branch, with the same effect).
-    auto stage = [&](auto xt, auto rp, int r0) {
-        constexpr int XT = decltype(xt)::value;
-        constexpr bool RP = decltype(rp)::value;
-        auto ld = [&](int64_t i) -> float {
-            if (XT == ST_F16) return f16_bits_to_float(xqp[i]);
-            if (XT == ST_BF16) return bf16_bits_to_float(xqp[i]);
-            return xp[i];
-        };
-        float v0[kRows], v1[kRows];
-        uint32_t m0[kRows], m1[kRows];
-        bool yin[kRows];
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            const int64_t gy = y0 - H + r0 + k;
-            yin[k] = !yedge || (gy >= 0 && gy < ny);
-            const int64_t cy = yedge ? (gy < 0 ? 0 : (gy >= ny ? ny - 1 : gy)) : gy;
-            const int64_t row = cy * nx;
-            v0[k] = ld(row + cx0);
-            v1[k] = ld(row + cx1);
-            m0[k] = RP ? wp[row + cx0] : 0u;
-            m1[k] = RP ? wp[row + cx1] : 0u;
-        }
-#pragma unroll
-        for (int k = 0; k < kRows; ++k) {
-            float *dst = lds + (r0 + k) * P1;
-            const bool f0 = yin[k] && in0 && isfinite(v0[k]);
-            const bool f1 = yin[k] && in1 && isfinite(v1[k]);
-            float y0v = f0 ? v0[k] : 0.f, y1v = f1 ? v1[k] : 0.f;
-            if (RP && f0 && (m0[k] & kDet)) y0v = copysignf(rv, v0[k]);
-            if (RP && f1 && (m1[k] & kDet)) y1v = copysignf(rv, v1[k]);
-            dst[lane] = y0v;
-            if (has2) dst[64 + lane] = y1v;
-        }
-    };
-    auto stage_all = [&](auto xt) {
-        for (int r0 = 0; r0 < 64; r0 += kRows) {
-            if (repl) stage(xt, std::true_type{}, r0);
-            else stage(xt, std::false_type{}, r0);
-        }
-    };
-    if (a.xtype == ST_F16) stage_all(std::integral_constant<int, ST_F16>{});
-    else if (a.xtype == ST_BF16) stage_all(std::integral_constant<int, ST_BF16>{});
-    else stage_all(std::integral_constant<int, ST_F32>{});
-    __syncthreads();
-
-    // x passes: lane = region row.
-    float r[RW];
-#pragma unroll
-    for (int i = 0; i < RW; ++i) r[i] = lds[lane * P1 + i];
-    {
-        const int lo = xedge ? (int)(H - x0) : 0;            // local index of gx = 0
-        const int hi = xedge ? (int)(nx - x0 + H) : RW;      // local index of gx = nx
-        Cascade<RW, R, 1, NIT, EDGE>::run(r, lo, hi);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 64; ++i) lds[lane * P2 + i] = r[H + i];
-    __syncthreads();
-
-    // y passes: lane = tile column.
-    float c[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) c[j] = lds[j * P2 + lane];
-    {
-        const int lo = yedge ? (int)(H - y0) : 0;
-        const int hi = yedge ? (int)(ny - y0 + H) : 64;
-        Cascade<64, R, 1, NIT, EDGE>::run(c, lo, hi);
-    }
-    double norm = 1.0;
-    for (int p = 0; p < 2 * NIT; ++p) norm *= (double)(2 * R + 1);
-    const float scale = (float)(1.0 / norm);
-    const int64_t gx = x0 + lane;
-    if (!EDGE || gx < nx) {
-        float *pp = a.p + z * nx * ny + gx;
-#pragma unroll
-        for (int j = 0; j < TY; ++j) {
-            const int64_t gy = y0 + j;
-            if (!EDGE || gy < ny) pp[gy * nx] = c[H + j] * scale;
-        }
     }
 }
 
@@ -624,6 +427,14 @@ hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
     return hipGetLastError();
 }
 
+hipError_t launch_pack_det(const uint8_t *wm, uint64_t *det, int64_t ncol, int64_t nz,
+                           int64_t wpp, hipStream_t s) {
+    const int64_t waves = nz * wpp;
+    const int blocks = (int)(waves / 4 + 1 < 65536 ? waves / 4 + 1 : 65536);
+    hipLaunchKernelGGL(k_pack_det, dim3(blocks), dim3(256), 0, s, wm, det, ncol, nz, wpp);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n);
     return hipGetLastError();
@@ -651,31 +462,10 @@ hipError_t launch_set_sigma0(DevState *st, double sigma0, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int R, int NIT>
-static hipError_t spatial_inst(const SpatialArgs &a, hipStream_t s) {
-    const int64_t n_int = (int64_t)a.ntx * a.nty;
-    const int64_t n_edge = (int64_t)a.tiles_x * a.tiles_y - n_int;
-    if (n_int > 0) {
-        SpatialArgs b = a;
-        b.tiles_per_plane = n_int;
-        hipLaunchKernelGGL((k_spatial<R, NIT, false>), dim3((unsigned)(n_int * a.nz)),
-                           dim3(64), 0, s, b);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (n_edge > 0) {
-        SpatialArgs b = a;
-        b.tiles_per_plane = n_edge;
-        hipLaunchKernelGGL((k_spatial<R, NIT, true>), dim3((unsigned)(n_edge * a.nz)),
-                           dim3(64), 0, s, b);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_spatial(int n_iter, int radius, const SpatialArgs &a,
-                          hipStream_t s) {
+hipError_t launch_spatial(int n_iter, int radius, int xtype, bool repl,
+                          const StripArgs &a, hipStream_t s) {
 #define SC_SP(N, R) \
-    if (n_iter == N && radius == R) return spatial_inst<R, N>(a, s);
+    if (n_iter == N && radius == R) return launch_strip<R, N>(a, xtype, repl, s);
     SC_SP(3, 1) SC_SP(3, 2) SC_SP(3, 3) SC_SP(3, 4) SC_SP(3, 5)
     SC_SP(4, 1) SC_SP(4, 2) SC_SP(4, 3) SC_SP(4, 4)
     SC_SP(5, 1) SC_SP(5, 2) SC_SP(5, 3)

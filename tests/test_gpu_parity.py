@@ -225,6 +225,26 @@ def test_bad_arguments_raise_einval(h):
         assert e.value.code == sc.EINVAL
 
 
+def test_handle_reuse_across_cube_sizes():
+    """Workspace sized by an earlier, smaller cube: later, larger runs on the
+    same handle (spectral-only, then spatial with replacement) must size
+    everything they touch, including the packed detection bits."""
+    handle = sc.SofiaSC(0)
+    try:
+        small = cfg2_like(70, 50, 40, seed=71, n_gal=2)
+        big = cfg2_like(180, 150, 120, seed=72, n_gal=5)
+        kern_sp = [(0.0, 0), (3.0, 3), (6.0, 0)]
+        kern_spec = [(0.0, 0), (0.0, 3)]
+        for x, kern in [(small, kern_sp), (big, kern_spec), (big, kern_sp)]:
+            say("reuse", x.shape, kern)
+            ref = oracle.run(x, kern, 3.5, "mad", "negative", 2.0)
+            m, noise, _ = handle.run(dev(x), kern, 3.5, "mad", "negative")
+            assert_sigma(noise, ref.sigma, "sigma_k")
+            assert_mask(host(m), ref.mask, ref.band, "mask")
+    finally:
+        handle.close()
+
+
 def test_step_ex_f32_equals_step_and_checks_options(h):
     x = cfg2_like(90, 70, 60, seed=44, n_gal=4)
     xd = dev(x)
