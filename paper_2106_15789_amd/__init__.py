@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsofia_sc.so")
 HEADER = os.path.join(ROOT, "include", "sofia_sc.h")
 SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
     "sc_kernels.hip", "sc_spatial_n3.hip", "sc_spatial_n4.hip", "sc_spatial_n5.hip",
-    "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip",
+    "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip", "sc_col_selclip.hip",
     "sc_col_clip.hip", "sc_col_write.hip", "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4

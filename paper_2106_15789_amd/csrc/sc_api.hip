@@ -20,12 +20,13 @@ namespace {
 enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
-    F_QUANTIZE, F_COUNT
+    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
-    "column_clip", "column_write", "finalize", "quantize"};
+    "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
+    "clip_fixup"};
 
 struct LaunchRec {
     int fam;
@@ -67,6 +68,8 @@ struct sofia_sc {
     size_t xq_cap = 0;
     uint64_t *det = nullptr;         // packed detection bits (spatial replacement)
     size_t det_cap = 0;              // in words
+    AmbEntry *amb = nullptr;         // undecided voxels of the fused clip
+    size_t amb_cap = 0;
     bool prof = false;
     std::vector<LaunchRec> recs;
     std::vector<hipEvent_t> pool;
@@ -76,13 +79,15 @@ struct sofia_sc {
 namespace {
 
 // Histogram workspace, zeroed before every MAD measurement: level 1 |
-// level-2 coarse | level 2 | sampled level 1 | capture count | selection counts.
+// level-2 coarse | level 2 | sampled level 1 | capture count | selection
+// counts | count of voxels the fused clip left undecided.
 constexpr size_t kOffL2c = kL1Bins;
 constexpr size_t kOffL2 = kOffL2c + 2 * (size_t)kL2Coarse;
 constexpr size_t kOffSample = kOffL2 + 2 * (size_t)kL2Bins;
 constexpr size_t kOffCapCount = kOffSample + kL1Bins;
 constexpr size_t kOffSelCounts = kOffCapCount + 2;
-constexpr size_t kHistWords = kOffSelCounts + 2;
+constexpr size_t kOffAmbCount = kOffSelCounts + 2;
+constexpr size_t kHistWords = kOffAmbCount + 2;
 // Columns blocks visited by the sampling pass: every 17th (a stride coprime
 // to the usual blocks-per-row counts spreads the sample over x and y).
 constexpr int kSampleStride = 17;
@@ -93,6 +98,11 @@ unsigned long long *hist2_of(sofia_sc *h) { return h->hist + kOffL2; }
 unsigned long long *hist_s_of(sofia_sc *h) { return h->hist + kOffSample; }
 unsigned long long *cap_count_of(sofia_sc *h) { return h->hist + kOffCapCount; }
 unsigned long long *sel_counts_of(sofia_sc *h) { return h->hist + kOffSelCounts; }
+unsigned long long *amb_count_of(sofia_sc *h) { return h->hist + kOffAmbCount; }
+
+// Undecided-voxel list of the fused clip: up to N/256 entries (at least
+// 2^16); beyond that the plain clip pass runs.
+size_t amb_capacity(int64_t N) { return std::max<size_t>((size_t)N / 256, (size_t)1 << 16); }
 
 // Capture buffer: up to N/8 keys (at least 2^20).
 size_t capture_capacity(int64_t N) { return std::max<size_t>((size_t)N / 8, (size_t)1 << 20); }
@@ -245,6 +255,15 @@ int ensure_workspace(sofia_sc *h, int64_t N, bool need_p, size_t parts,
             return fail(h, SOFIA_SC_ENOMEM, std::string("plane buffer: ") + hipGetErrorString(e));
         h->p_cap = (size_t)N;
     }
+    const size_t acap = amb_capacity(N);
+    if (acap > h->amb_cap) {
+        if (h->amb) (void)hipFree(h->amb);
+        h->amb = nullptr;
+        h->amb_cap = 0;
+        if ((e = hipMalloc(&h->amb, acap * sizeof(AmbEntry))) != hipSuccess)
+            return fail(h, SOFIA_SC_ENOMEM, std::string("undecided list: ") + hipGetErrorString(e));
+        h->amb_cap = acap;
+    }
     const size_t cap = capture_capacity(N);
     if (cap > h->cap_cap) {
         if (h->cap_buf) (void)hipFree(h->cap_buf);
@@ -304,7 +323,12 @@ void collect_profile(sofia_sc *h) {
     for (auto &r : h->recs) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
-            const bool skipped = r.cond >= 0 && !((h->st_host->fallback >> r.cond) & 1ull);
+            // cond k < 64: runs only when kernel k needed the full histogram
+            // passes; cond 64 + k: only when it needed the full clip pass
+            const DevState &hs = *h->st_host;
+            const bool skipped =
+                r.cond >= 0 && !(r.cond < 64 ? (hs.fallback >> r.cond) & 1ull
+                                              : (hs.clip_fallback >> (r.cond - 64)) & 1ull);
             Agg &a = h->agg[skipped ? F_FALLBACK_SKIPPED : r.fam];
             if (skipped) { r.bytes = 0; r.vox = 0; }
             a.launches += 1;
@@ -424,6 +448,26 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         return col(OP_WRITE, F_COL_WRITE, rd + 4.0 * N);
     }
 
+    // Clip target: the next working mask (with the packed detection bits a
+    // later spatial kernel replaces from) or, for the last kernel, the
+    // caller's 0/1 mask.
+    double clip_bytes = 0.0;
+    if (j.clip_out) {
+        c.mask_out = j.clip_out;
+        c.out_user = j.out_user ? 1 : 0;
+        c.wpp = det_words_per_plane(d.ncol);
+        c.det_bits = nullptr;
+        if (j.det_live && !j.out_user) {
+            if (h->det_cap < (size_t)(d.nz * c.wpp))
+                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
+            c.det_bits = h->det;
+        }
+        clip_bytes = N + (c.det_bits ? N / 8.0 : 0.0);
+    }
+    const int cond = j.k >= 0 ? j.k : 63;
+    // With MAD noise the clip rides on the selection pass (see below).
+    const bool fused = j.clip_out && j.mode != SOFIA_SC_NOISE_STD;
+
     if (j.mode == SOFIA_SC_NOISE_STD) {
         if ((rc = col(OP_STD, F_COL_STD, rd))) return rc;
         rc = launch(h, s, F_FINALIZE, 16.0 * g.blocks(), 0, [&] {
@@ -461,16 +505,27 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
             if (rc) return rc;
         }
         rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
-            return launch_finalize_predict(h->st, hist_s_of(h), s);
+            return launch_finalize_predict(h->st, hist_s_of(h), j.t, s);
         });
         if (rc) return rc;
-        if ((rc = col(OP_SELECT, F_COL_SELECT, rd))) return rc;
+        // Fused clip: the predicted median window bounds the threshold, so
+        // the selection pass also clips every voxel whose |s| lies outside
+        // (thr_lo, thr_hi] and lists the others for an exact decision later.
+        if (fused) {
+            c.amb = h->amb;
+            c.amb_count = amb_count_of(h);
+            c.amb_capacity = (unsigned long long)h->amb_cap;
+            if ((rc = col(OP_SELCLIP, F_COL_SELCLIP, rd + clip_bytes))) return rc;
+        } else {
+            if ((rc = col(OP_SELECT, F_COL_SELECT, rd))) return rc;
+        }
         rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
             return launch_finalize_select(h->st, sel_counts_of(h), cap_count_of(h),
-                                          (unsigned long long)h->cap_cap, j.k, s);
+                                          (unsigned long long)h->cap_cap, j.k,
+                                          fused ? amb_count_of(h) : nullptr,
+                                          (unsigned long long)h->amb_cap, s);
         });
         if (rc) return rc;
-        const int cond = j.k >= 0 ? j.k : 63;
         rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
             return launch_capture_l1(h->st, h->cap_buf, cap_count_of(h), hist1_of(h), s);
         });
@@ -507,19 +562,23 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         });
         if (rc) return rc;
     }
-    if (j.clip_out) {
-        c.mask_out = j.clip_out;
-        c.out_user = j.out_user ? 1 : 0;
-        // a later spatial kernel replaces detections: keep the packed bits
-        c.wpp = det_words_per_plane(d.ncol);
-        c.det_bits = nullptr;
-        if (j.det_live && !j.out_user) {
-            if (h->det_cap < (size_t)(d.nz * c.wpp))
-                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
-            c.det_bits = h->det;
-        }
-        const double det_bytes = c.det_bits ? N / 8.0 : 0.0;
-        if ((rc = col(OP_CLIP, F_COL_CLIP, rd + N + det_bytes))) return rc;
+    if (fused) {
+        // decide the listed voxels; the full clip pass below runs only when
+        // the median missed the window or the list overflowed
+        rc = launch(h, s, F_CLIP_FIXUP, 0, 0, [&] {
+            return launch_clip_fixup(h->st, h->amb, amb_count_of(h),
+                                     (unsigned long long)h->amb_cap, c.mask_out, c.out_user,
+                                     c.det_bits, d.ncol, c.wpp, s);
+        });
+        if (rc) return rc;
+        c.skip_if_fused = 1;
+        rc = launch(h, s, F_COL_CLIP, rd + clip_bytes, N, [&] {
+            return launch_column(src, OP_CLIP, spec, has_wm, c, g.blocks(), s);
+        }, 64 + cond);
+        c.skip_if_fused = 0;
+        if (rc) return rc;
+    } else if (j.clip_out) {
+        if ((rc = col(OP_CLIP, F_COL_CLIP, rd + clip_bytes))) return rc;
     }
     return SOFIA_SC_OK;
 }
@@ -718,6 +777,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->cap_buf) (void)hipFree(h->cap_buf);
         if (h->xq) (void)hipFree(h->xq);
         if (h->det) (void)hipFree(h->det);
+        if (h->amb) (void)hipFree(h->amb);
     }
     delete h;
 }

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     constexpr int G = ColGroup<W>::G;
     const int tid = threadIdx.x;
     if ((OP == OP_HIST1 || OP == OP_HIST2) && a.skip_if_captured && a.st->use_capture) return;
+    if (OP == OP_CLIP && a.skip_if_fused && a.st->fused_ok) return;
     const int cb = (int)(blockIdx.x % (unsigned)a.ncb) * a.cb_stride;
     const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
     const int64_t ncol = a.ncol;
@@ -71,7 +72,9 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
 
     const bool repl = SRC == SRC_X && HASWM && a.repl_on;
     const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
+    constexpr bool SELCLIP = OP == OP_SELCLIP;
     const double T = (OP == OP_CLIP) ? a.st->thr : 0.0;
+    const double Tlo = SELCLIP ? a.st->thr_lo : 0.0, Thi = SELCLIP ? a.st->thr_hi : 0.0;
     uint32_t b0 = 0xffffffffu, b1 = 0xffffffffu;
     if (OP == OP_HIST2) { b0 = a.st->bin[0]; b1 = a.st->bin[1]; }
     const int range = a.range;
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // predicted window [klo, khi], and append the keys inside it, per wave, to
     // an LDS buffer that is flushed to the global key list with one atomic
     // per flush.
-    constexpr bool capture = OP == OP_SELECT;
+    constexpr bool capture = OP == OP_SELECT || OP == OP_SELCLIP;
     uint32_t klo = 1, khi = 0;
     if (capture) { klo = a.st->klo; khi = a.st->khi; }
     unsigned n_sel = 0, n_below = 0;
@@ -108,6 +111,50 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         fill = 0;
     };
 
+    // Fused clip: undecided voxels are collected per wave in LDS and appended
+    // to the global list in bulk, once per group of planes (one atomic per
+    // flush: a single shared counter hit once per voxel-plane would serialise
+    // the whole pass). Entries beyond the buffer are dropped and the count is
+    // pushed past the list's capacity, which sends the pass to the full clip.
+    const size_t amb_off =
+        ((size_t)((const char *)(capw + (B / 64 - (tid >> 6)) * kCapPerWave(G)) -
+                  (const char *)dyn_lds) + 15) & ~(size_t)15;
+    AmbEntry *ambw = (AmbEntry *)((char *)dyn_lds + amb_off) + (tid >> 6) * kAmbPerWave;
+    int afill = 0;   // entries in this wave's buffer (same in every lane)
+    auto flush_amb = [&]() {
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long act = __ballot(1);
+        const int leader = __ffsll((long long)act) - 1;
+        const int kept = afill < kAmbPerWave ? afill : kAmbPerWave;
+        const unsigned long long add =
+            (unsigned long long)afill + (afill > kAmbPerWave ? a.amb_capacity + 1 : 0ull);
+        unsigned long long base = 0;
+        if ((tid & 63) == leader) base = atomicAdd(a.amb_count, add);
+        const uint32_t lo32 = __shfl((uint32_t)base, leader);
+        const uint32_t hi32 = __shfl((uint32_t)(base >> 32), leader);
+        base = ((unsigned long long)hi32 << 32) | lo32;
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+        const int nact = __popcll(act);
+        for (int i = rank; i < kept; i += nact)
+            if (base + i < a.amb_capacity) a.amb[base + i] = ambw[i];
+        __builtin_amdgcn_wave_barrier();
+        afill = 0;
+    };
+
+    // Clip output byte of a voxel and, when kept, its packed detection bit.
+    auto clip_out = [&](int zo, bool blank, uint8_t wb, uint8_t det) {
+        uint8_t out;
+        if (a.out_user) out = (uint8_t)((wb & kDet) | det);
+        else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
+        (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
+        if (a.det_bits) {
+            // the wave's 64 columns start at a multiple of 64: one word
+            const uint64_t bits = __ballot((out & kDet) != 0);
+            if ((tid & 63) == 0) a.det_bits[zo * a.wpp + ((col0 + tid) >> 6)] = bits;
+        }
+    };
+
     // Per-voxel operation on the smoothed value s of output plane zo.
     auto consume = [&](int zo, double s, bool blank, uint8_t wb) {
         if (OP == OP_STD) {
@@ -117,7 +164,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
             }
-        } else if (OP == OP_SELECT) {
+        } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
             const bool sel = !blank && in_flux_range(s, range);
             const uint32_t key = __float_as_uint(fabsf((float)s));
             n_sel += sel ? 1u : 0u;
@@ -131,6 +178,24 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                     capw[fill + below] = key;
                 }
                 fill += __popcll(bal);
+            }
+            if (SELCLIP) {
+                // clip now unless |s| lies in (thr_lo, thr_hi], where the
+                // decision waits for the exact threshold
+                const double as = fabs(s);
+                const bool det = !blank && as > Thi;
+                const bool amb = !blank && as > Tlo && !det;
+                clip_out(zo, blank, wb, det ? kDet : 0);
+                const unsigned long long ab = __ballot(amb);
+                if (ab) {
+                    if (amb) {
+                        const int at = afill + (int)__builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(ab >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ab, 0u));
+                        if (at < kAmbPerWave)
+                            ambw[at] = AmbEntry{(uint64_t)((int64_t)zo * ncol + col0 + tid), s};
+                    }
+                    afill += __popcll(ab);
+                }
             }
         } else if (OP == OP_HIST2) {
             if (!blank && in_flux_range(s, range)) {
@@ -147,16 +212,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_CLIP) {
-            const uint8_t det = (!blank && fabs(s) > T) ? kDet : 0;
-            uint8_t out;
-            if (a.out_user) out = (uint8_t)((wb & kDet) | det);
-            else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
-            (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
-            if (a.det_bits) {
-                // the wave's 64 columns start at a multiple of 64: one word
-                const uint64_t bits = __ballot((out & kDet) != 0);
-                if ((tid & 63) == 0) a.det_bits[zo * a.wpp + ((col0 + tid) >> 6)] = bits;
-            }
+            clip_out(zo, blank, wb, (!blank && fabs(s) > T) ? kDet : 0);
         } else {  // OP_WRITE
             (a.s_out + (int64_t)zo * ncol + col0)[tid] = blank ? NAN : (float)s;
         }
@@ -257,6 +313,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         }
         // The buffer holds one more group on top of kCapFlushAt entries.
         if (capture && fill > kCapFlushAt) flush();
+        if (SELCLIP && afill > kAmbFlushAt) flush_amb();
         if (SPEC && (++groups & 7) == 0) {   // re-anchor the running sum
             S = 0.0;
             if (LDSRING) {
@@ -279,6 +336,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             process_group(zb + G, gb);
         }
         if (capture && fill > 0) flush();
+        if (SELCLIP && afill > 0) flush_amb();
     }
 
     if (OP == OP_STD) {
@@ -297,7 +355,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         __syncthreads();
         for (int i = tid; i < kL1Bins; i += B)
             if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
-    } else if (OP == OP_SELECT) {
+    } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
         __shared__ unsigned long long rc[2][B];
         rc[0][tid] = n_sel;
         rc[1][tid] = n_below;
@@ -332,11 +390,12 @@ inline size_t column_lds_bytes(int src, int op, bool spectral, int w) {
     if (lds_ring) b += (size_t)w * kColThreads * sizeof(float);
     if (lds_ring && src == SRC_X) b += ((size_t)w * kColThreads + 3) & ~(size_t)3;
     if (op == OP_HIST1) b += (size_t)kL1Bins * sizeof(unsigned);
-    if (op == OP_SELECT) {
+    if (op == OP_SELECT || op == OP_SELCLIP) {
         const int tw = spectral ? ring_template_width(w) : 1;
         const int group = tw >= 3 ? tw * ((8 + tw - 1) / tw) : 8;
         b += (size_t)(kColThreads / 64) * kCapPerWave(group) * sizeof(uint32_t);
     }
+    if (op == OP_SELCLIP) b += 16 + (size_t)(kColThreads / 64) * kAmbPerWave * sizeof(AmbEntry);
     if (op == OP_HIST2) b += (size_t)2 * kL2Coarse * sizeof(unsigned);
     return b;
 }

@@ -49,7 +49,19 @@ struct DevState {
     unsigned long long crank[2];  // residual ranks inside the coarse bins
     unsigned long long fallback;  // bit k: kernel k needed the full level-2 pass
     double scale;           // 16-bit storage: cube units per stored unit (sigma_0)
+    double thr_lo, thr_hi;  // window the clip threshold t sigma_k lies in when the
+                            // captured window holds the median (fused clip)
+    int32_t fused_ok;       // fused clip valid: median captured, ambiguous list whole
+    int32_t pad1;
+    unsigned long long clip_fallback;  // bit k: kernel k needed the full clip pass
     double sigma[SOFIA_SC_MAX_KERNELS];
+};
+
+// A voxel whose clip decision the fused selection pass could not take yet:
+// |s| lies in (thr_lo, thr_hi]. Decided once sigma_k is exact.
+struct AmbEntry {
+    uint64_t idx;           // voxel index z * nx * ny + y * nx + x
+    double s;               // smoothed value, as the clip compares it
 };
 
 // Keys captured per wave in LDS before one bulk append to global memory:
@@ -57,10 +69,19 @@ struct DevState {
 // of the wave may capture on every plane of a group).
 constexpr int kCapFlushAt = 256;
 constexpr int kCapPerWave(int group) { return kCapFlushAt + 64 * group; }
+// Undecided voxels of the fused clip, per wave in LDS: flushed after a group
+// of planes once more than kAmbFlushAt are held. A group of noise-like data
+// adds well under one; a group that overflows the buffer sends the pass to
+// the full clip.
+constexpr int kAmbFlushAt = 64;
+constexpr int kAmbPerWave = 192;
 
 enum Src { SRC_X = 0, SRC_P = 1 };
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
-enum Op { OP_STD = 0, OP_HIST1 = 1, OP_HIST2 = 2, OP_CLIP = 3, OP_WRITE = 4, OP_SELECT = 5 };
+enum Op {
+    OP_STD = 0, OP_HIST1 = 1, OP_HIST2 = 2, OP_CLIP = 3, OP_WRITE = 4, OP_SELECT = 5,
+    OP_SELCLIP = 6   // OP_SELECT plus the clip for every voxel outside (thr_lo, thr_hi]
+};
 
 // Arguments of the column-streaming kernel (spectral boxcar + one of the
 // per-voxel operations). One thread owns one (x, y) column and streams z.
@@ -95,8 +116,13 @@ struct ColArgs {
     unsigned long long *cap_count;
     unsigned long long cap_capacity;
     unsigned long long *sel_counts;  // OP_SELECT: [selected voxels, keys below klo]
-    uint64_t *det_bits;          // OP_CLIP: packed detection bits out (may be null)
+    uint64_t *det_bits;          // OP_CLIP / OP_SELCLIP: packed detection bits out (may be null)
     int64_t wpp;                 // 64-bit words per plane of det_bits
+    AmbEntry *amb;               // OP_SELCLIP: undecided voxels
+    unsigned long long *amb_count;
+    unsigned long long amb_capacity;
+    int32_t skip_if_fused;       // OP_CLIP: do nothing when st->fused_ok
+    int32_t pad2;
 };
 
 // Arguments of the strip-streaming spatial kernel. A strip is 128 adjacent
@@ -143,12 +169,20 @@ hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
                                 hipStream_t s);
 hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_counts,
                                   const unsigned long long *cap_count,
-                                  unsigned long long cap_capacity, int k, hipStream_t s);
+                                  unsigned long long cap_capacity, int k,
+                                  const unsigned long long *amb_count,
+                                  unsigned long long amb_capacity, hipStream_t s);
 hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
                              const unsigned long long *cap_count,
                              unsigned long long *hist1, hipStream_t s);
 hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_s,
-                                   hipStream_t s);
+                                   double t, hipStream_t s);
+// After sigma_k is exact: decide the voxels the fused selection pass left
+// undecided (when st->fused_ok), into the mask and the packed bits.
+hipError_t launch_clip_fixup(const DevState *st, const AmbEntry *amb,
+                             const unsigned long long *amb_count,
+                             unsigned long long amb_capacity, uint8_t *mask_out, int out_user,
+                             uint64_t *det_bits, int64_t ncol, int64_t wpp, hipStream_t s);
 hipError_t launch_capture_coarse(const DevState *st, const uint32_t *cap_buf,
                                  const unsigned long long *cap_count,
                                  unsigned long long *hist2c, hipStream_t s);

@@ -118,6 +118,10 @@ __global__ void k_set_sigma0(DevState *st, double sigma0) {
         st->khi = 0u;
         st->below = 0ull;
         st->fallback = 0ull;
+        st->clip_fallback = 0ull;
+        st->fused_ok = 0;
+        st->thr_lo = 0.0;
+        st->thr_hi = 0.0;
         st->scale = 1.0;
         for (int k = 0; k < SOFIA_SC_MAX_KERNELS; ++k) st->sigma[k] = NAN;
     }
@@ -206,23 +210,57 @@ __global__ __launch_bounds__(256) void k_finalize_mad1(
 // After the selection pass: the captured keys decide the order statistics
 // when the count below the window and the captured count bracket both ranks
 // (and nothing was dropped); otherwise the full level-1/level-2 passes run.
+// amb_count may be null: no fused clip in this pass (then fused_ok = 0 and
+// the plain clip pass runs).
 __global__ void k_finalize_select(DevState *st, const unsigned long long *sel_counts,
                                   const unsigned long long *cap_count,
-                                  unsigned long long cap_capacity, int k) {
+                                  unsigned long long cap_capacity, int k,
+                                  const unsigned long long *amb_count,
+                                  unsigned long long amb_capacity) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const unsigned long long m = sel_counts[0], below = sel_counts[1], cin = *cap_count;
+    const unsigned long long bit = 1ull << (k >= 0 ? k : 63);
     st->m = m;
     st->below = 0ull;
+    st->fused_ok = 0;
     if (m == 0) {                 // no voxel in the flux range
         st->status |= 1;
         st->use_capture = 1;      // nothing to select: skip every later pass
+        st->clip_fallback |= bit; // (the mask is undefined then)
         return;
     }
     const unsigned long long r_lo = (m - 1) / 2, r_hi = m / 2;
     const bool ok = cin <= cap_capacity && below <= r_lo && r_hi < below + cin;
     st->use_capture = ok ? 1 : 0;
     if (ok) st->below = below;
-    else st->fallback |= 1ull << (k >= 0 ? k : 63);
+    else st->fallback |= bit;
+    // The median lies in the captured window, so the threshold lies in
+    // (thr_lo, thr_hi]: every voxel outside it was clipped exactly.
+    const bool fused = ok && amb_count && *amb_count <= amb_capacity;
+    st->fused_ok = fused ? 1 : 0;
+    if (!fused) st->clip_fallback |= bit;
+}
+
+// Voxels with thr_lo < |s| <= thr_hi, decided with the exact threshold.
+__global__ void k_clip_fixup(const DevState *st, const AmbEntry *amb,
+                             const unsigned long long *amb_count,
+                             unsigned long long amb_capacity, uint8_t *mask_out, int out_user,
+                             uint64_t *det_bits, int64_t ncol, int64_t wpp) {
+    if (!st->fused_ok) return;
+    const unsigned long long n = *amb_count < amb_capacity ? *amb_count : amb_capacity;
+    const double T = st->thr;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         i < n; i += stride) {
+        const AmbEntry e = amb[i];
+        if (!(fabs(e.s) > T)) continue;
+        mask_out[e.idx] |= out_user ? (uint8_t)1 : kDet;
+        if (det_bits) {
+            const int64_t z = (int64_t)(e.idx / (uint64_t)ncol);
+            const int64_t col = (int64_t)e.idx - z * ncol;
+            atomicOr((unsigned long long *)&det_bits[z * wpp + (col >> 6)], 1ull << (col & 63));
+        }
+    }
 }
 
 // Predict the median of |s| from the level-1 histogram of a sample of
@@ -230,7 +268,7 @@ __global__ void k_finalize_select(DevState *st, const unsigned long long *sel_co
 // and set the capture window to that estimate -/+ delta, with
 // delta = 2 % + 3 / sqrt(sample size).
 __global__ __launch_bounds__(256) void k_finalize_predict(
-    DevState *st, const unsigned long long *hist_s) {
+    DevState *st, const unsigned long long *hist_s, double t) {
     __shared__ unsigned long long buf[256];
     __shared__ float est[2];
     constexpr int PER = kL1Bins / 256;
@@ -275,6 +313,11 @@ __global__ __launch_bounds__(256) void k_finalize_predict(
             st->klo = lo > 0.0 ? __float_as_uint((float)lo) : 0u;
             st->khi = hi < 3.0e38 ? __float_as_uint((float)hi) : 0x7f800000u;
         }
+        // If the two central order statistics v0 <= v1 fall in the window,
+        // t * 1.4826 * (v0 + v1) / 2 lies between these bounds (widened far
+        // beyond the three roundings of that product).
+        st->thr_lo = t * (kMadFactor * (double)__uint_as_float(st->klo)) * (1.0 - 1e-12);
+        st->thr_hi = t * (kMadFactor * (double)__uint_as_float(st->khi)) * (1.0 + 1e-12);
     }
 }
 
@@ -487,6 +530,7 @@ hipError_t launch_column(int src, int op, bool spectral, bool has_wm,
         case OP_CLIP: return launch_column_op<OP_CLIP>(src, spectral, has_wm, a, nblocks, s);
         case OP_WRITE: return launch_column_op<OP_WRITE>(src, spectral, has_wm, a, nblocks, s);
         case OP_SELECT: return launch_column_op<OP_SELECT>(src, spectral, has_wm, a, nblocks, s);
+        case OP_SELCLIP: return launch_column_op<OP_SELCLIP>(src, spectral, has_wm, a, nblocks, s);
     }
     return hipErrorInvalidValue;
 }
@@ -507,9 +551,20 @@ hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
 
 hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_counts,
                                   const unsigned long long *cap_count,
-                                  unsigned long long cap_capacity, int k, hipStream_t s) {
+                                  unsigned long long cap_capacity, int k,
+                                  const unsigned long long *amb_count,
+                                  unsigned long long amb_capacity, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(64), 0, s, st, sel_counts,
-                       cap_count, cap_capacity, k);
+                       cap_count, cap_capacity, k, amb_count, amb_capacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_clip_fixup(const DevState *st, const AmbEntry *amb,
+                             const unsigned long long *amb_count,
+                             unsigned long long amb_capacity, uint8_t *mask_out, int out_user,
+                             uint64_t *det_bits, int64_t ncol, int64_t wpp, hipStream_t s) {
+    hipLaunchKernelGGL(k_clip_fixup, dim3(512), dim3(256), 0, s, st, amb, amb_count,
+                       amb_capacity, mask_out, out_user, det_bits, ncol, wpp);
     return hipGetLastError();
 }
 
@@ -522,8 +577,8 @@ hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
 }
 
 hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_s,
-                                   hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_predict, dim3(1), dim3(256), 0, s, st, hist_s);
+                                   double t, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_predict, dim3(1), dim3(256), 0, s, st, hist_s, t);
     return hipGetLastError();
 }
 

@@ -346,6 +346,27 @@ def test_mad_fallback_when_sample_is_unrepresentative(h):
     assert_mask(host(m), ref.mask, ref.band)
 
 
+def test_fused_clip_falls_back_when_undecided_list_overflows(h):
+    """Many voxels within the threshold window (|s| near 3.5 sigma, all
+    positive so the negative-pixel median is untouched): the selection pass
+    cannot clip them and its list of undecided voxels (N/256) overflows, so
+    the exact full clip pass must run."""
+    nz, ny, nx = 64, 128, 128
+    rng = np.random.default_rng(57)
+    x = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    sig, _ = oracle.noise(x.astype(np.float64), "mad", "negative")
+    near = (x > 0) & (rng.random(x.shape) < 0.3)   # ~157k > the 2^16 capacity floor
+    x[near] = (3.5 * sig * (1.0 + rng.uniform(-0.005, 0.005, int(near.sum())))).astype(np.float32)
+    h.profile(True)
+    m, noise, _ = h.run(dev(x), [(0.0, 0)], 3.5, "mad", "negative")
+    h.profile(False)
+    fam = _families(h)
+    assert fam.get("column_clip", {}).get("launches", 0) >= 1, fam.keys()
+    ref = oracle.run(x, [(0.0, 0)], 3.5, "mad", "negative", 2.0)
+    assert_sigma(noise, ref.sigma)
+    assert_mask(host(m), ref.mask, ref.band)
+
+
 def test_mad_fallback_on_capture_overflow(h):
     """Most voxels share one value: the captured keys exceed the buffer
     (N/8) and the full level-2 pass must take over."""
