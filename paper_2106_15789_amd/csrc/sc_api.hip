@@ -368,6 +368,8 @@ struct PairJob {
     float *write_out;
     bool det_live = false;  // this call sized h->det for the cube: the clip keeps
                             // the packed detection bits, the spatial pass reads them
+    bool det_next = false;  // the next kernel is spatial with replacement: the
+                            // clip must write the packed bits
 };
 
 int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
@@ -457,7 +459,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         c.out_user = j.out_user ? 1 : 0;
         c.wpp = det_words_per_plane(d.ncol);
         c.det_bits = nullptr;
-        if (j.det_live && !j.out_user) {
+        if (j.det_live && j.det_next && !j.out_user) {
             if (h->det_cap < (size_t)(d.nz * c.wpp))
                 return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
             c.det_bits = h->det;
@@ -693,7 +695,7 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
         PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, plans[k], k, repl_on && k >= 1,
                   opt->replacement, mode, range, t, have_wm ? h->wm[cur] : nullptr, out, last,
                   k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
-                  any_spatial};
+                  any_spatial, !last && plans[k + 1].spatial() && repl_on};
         if ((rc = run_pair(h, s, j))) return rc;
         if (!last) {
             if (have_wm) cur = 1 - cur;

@@ -77,7 +77,11 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     const double Tlo = SELCLIP ? a.st->thr_lo : 0.0, Thi = SELCLIP ? a.st->thr_hi : 0.0;
     uint32_t b0 = 0xffffffffu, b1 = 0xffffffffu;
     if (OP == OP_HIST2) { b0 = a.st->bin[0]; b1 = a.st->bin[1]; }
-    const int range = a.range;
+    // Flux range as a sign test without branches: all voxels, or those with
+    // s * range > 0 (s < 0 for range -1, s > 0 for range +1).
+    const bool all_range = a.range == 0;
+    const double rsgn = (double)a.range;
+    auto in_range = [&](double s) { return all_range || s * rsgn > 0.0; };
     ColAcc acc{0.0, 0ull};
     const float *src = SRC == SRC_X ? a.x : a.p;
 
@@ -143,29 +147,31 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     };
 
     // Clip output byte of a voxel and, when kept, its packed detection bit.
-    auto clip_out = [&](int zo, bool blank, uint8_t wb, uint8_t det) {
+    auto clip_out = [&](int64_t po, int64_t zw, bool blank, uint8_t wb, uint8_t det) {
         uint8_t out;
         if (a.out_user) out = (uint8_t)((wb & kDet) | det);
         else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
-        (a.mask_out + (int64_t)zo * ncol + col0)[tid] = out;
+        (a.mask_out + po)[tid] = out;
         if (a.det_bits) {
             // the wave's 64 columns start at a multiple of 64: one word
             const uint64_t bits = __ballot((out & kDet) != 0);
-            if ((tid & 63) == 0) a.det_bits[zo * a.wpp + ((col0 + tid) >> 6)] = bits;
+            if ((tid & 63) == 0) a.det_bits[zw + ((col0 + tid) >> 6)] = bits;
         }
     };
 
-    // Per-voxel operation on the smoothed value s of output plane zo.
-    auto consume = [&](int zo, double s, bool blank, uint8_t wb) {
+    // Per-voxel operation on the smoothed value s of output plane zo; po =
+    // zo * ncol + col0 and zw = zo * wpp are kept as running sums by the
+    // caller (no 64-bit multiply per plane).
+    auto consume = [&](int64_t po, int64_t zw, double s, bool blank, uint8_t wb) {
         if (OP == OP_STD) {
-            if (!blank && in_flux_range(s, range)) { acc.sum += s * s; acc.cnt += 1; }
+            if (!blank && in_range(s)) { acc.sum += s * s; acc.cnt += 1; }
         } else if (OP == OP_HIST1) {
-            if (!blank && in_flux_range(s, range)) {
+            if (!blank && in_range(s)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
             }
         } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
-            const bool sel = !blank && in_flux_range(s, range);
+            const bool sel = !blank && in_range(s);
             const uint32_t key = __float_as_uint(fabsf((float)s));
             n_sel += sel ? 1u : 0u;
             n_below += (sel && key < klo) ? 1u : 0u;
@@ -185,20 +191,20 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 const double as = fabs(s);
                 const bool det = !blank && as > Thi;
                 const bool amb = !blank && as > Tlo && !det;
-                clip_out(zo, blank, wb, det ? kDet : 0);
+                clip_out(po, zw, blank, wb, det ? kDet : 0);
                 const unsigned long long ab = __ballot(amb);
                 if (ab) {
                     if (amb) {
                         const int at = afill + (int)__builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(ab >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ab, 0u));
                         if (at < kAmbPerWave)
-                            ambw[at] = AmbEntry{(uint64_t)((int64_t)zo * ncol + col0 + tid), s};
+                            ambw[at] = AmbEntry{(uint64_t)(po + tid), s};
                     }
                     afill += __popcll(ab);
                 }
             }
         } else if (OP == OP_HIST2) {
-            if (!blank && in_flux_range(s, range)) {
+            if (!blank && in_range(s)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 const uint32_t k1 = key >> kL1Shift;
                 const uint32_t lo = key & (kL2Bins - 1);
@@ -212,9 +218,9 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_CLIP) {
-            clip_out(zo, blank, wb, (!blank && fabs(s) > T) ? kDet : 0);
+            clip_out(po, zw, blank, wb, (!blank && fabs(s) > T) ? kDet : 0);
         } else {  // OP_WRITE
-            (a.s_out + (int64_t)zo * ncol + col0)[tid] = blank ? NAN : (float)s;
+            (a.s_out + po)[tid] = blank ? NAN : (float)s;
         }
     };
 
@@ -240,22 +246,23 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     };
     const int zs = SPEC ? z0 - h : z0;
     const int ze = SPEC ? z1 + h : z1;   // exclusive
+    const int64_t hoff = (int64_t)h * ncol;
     auto load_group = [&](int zb, Group &g) {
+        int64_t off = (int64_t)zb * ncol + col0;   // running: plane zb + j
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
+        for (int j = 0; j < G; ++j, off += ncol) {
             const int zi = zb + j;
             g.v[j] = 0.f;
             g.q[j] = 0;
             g.b[j] = 0;
             if (zi < ze && zi >= 0 && zi < nz) {
-                const int64_t off = (int64_t)zi * ncol + col0;
                 if (Q16) g.q[j] = (a.xq + off)[tid];
                 else g.v[j] = (src + off)[tid];
                 if (SRC == SRC_X && HASWM) g.b[j] = (a.wm_in + off)[tid];
             }
             if (SRC == SRC_P) {
                 const int zo = zi - h;
-                if (zi < ze && zo >= z0) g.b[j] = (a.wm_in + (int64_t)zo * ncol + col0)[tid];
+                if (zi < ze && zo >= z0) g.b[j] = (a.wm_in + (off - hoff))[tid];
             }
         }
     };
@@ -270,17 +277,20 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     int groups = 0;
 
     auto process_group = [&](int zb, const Group &g) {
+        // output plane of step j: zb + j (no spectral smoothing) or zb + j - h
+        const int zo0 = SPEC ? zb - h : zb;
+        int64_t po = (int64_t)zo0 * ncol + col0, zw = (int64_t)zo0 * a.wpp;
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
+        for (int j = 0; j < G; ++j, po += ncol, zw += a.wpp) {
             const int zi = zb + j;
             if (zi >= ze) break;
             if (!SPEC) {
                 const float xv = in_value(g, j);
                 if (SRC == SRC_X) {
                     const bool blank = !isfinite(xv);
-                    consume(zi, (double)raw_value(xv, g.b[j]), blank, g.b[j]);
+                    consume(po, zw, (double)raw_value(xv, g.b[j]), blank, g.b[j]);
                 } else {
-                    consume(zi, (double)xv, (g.b[j] & kBlank) != 0, g.b[j]);
+                    consume(po, zw, (double)xv, (g.b[j] & kBlank) != 0, g.b[j]);
                 }
                 continue;
             }
@@ -309,7 +319,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             }
             S += (double)vn - (double)vo;
             const int zo = zi - h;
-            if (zo >= z0) consume(zo, S * inv_w, (wb_out & kBlank) != 0, wb_out);
+            if (zo >= z0) consume(po, zw, S * inv_w, (wb_out & kBlank) != 0, wb_out);
         }
         // The buffer holds one more group on top of kCapFlushAt entries.
         if (capture && fill > kCapFlushAt) flush();
