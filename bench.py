@@ -28,10 +28,14 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 
 
 def kernel_source_sha() -> str:
+    """Hash of every kernel and host source of the library."""
     h = hashlib.sha256()
-    for name in ("sc_kernels.hip", "sc_api.hip", "sc_internal.h"):
-        with open(os.path.join(ROOT, "paper_2106_15789_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_2106_15789_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 
