@@ -8,6 +8,12 @@ sigma varies 0.8-1.5 across the field, a 13-px NaN border (5 % of voxels) and
 2000 mock galaxies; kernels spatial {0, 3, 6} px x spectral {0, 3, 7, 15} ch;
 MAD noise on negative voxels; threshold 3.5; replacement n = 2.
 
+--workload batch96: 96 cubes of seeded uneven shapes (spatial 96-512 px,
+128-1024 channels, sigma 0.5-2 per cube, same kernels and settings); one step
+runs all of them, by default as one batched run (a single graph launch),
+with --batch-mode loop as one run call per cube. --storage f16/bf16 stores
+the cube noise-scaled in 16 bits inside each run.
+
 Prints one JSON line. `value` is voxels per second of whole runs; `roofline`
 describes the kernel family with the largest share of device time, timed with
 HIP events on the launch stream; `cpu_baseline` times the FP64 oracle on a
@@ -85,6 +91,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
                     help="cube storage inside the run (16-bit: noise-scaled copy)")
+    ap.add_argument("--batch-mode", default="graph", choices=["graph", "loop"],
+                    help="many-cube workloads: one sofia_sc_run_batch graph launch per "
+                         "step, or one sofia_sc_run call per cube")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the cube (4 B/voxel "
                          "read + write), the calibration kernel for HBM counters")
@@ -101,18 +110,30 @@ def main():
 
     wl = synth.workload(args.workload)
     spec = wl.cubes[0]
-    print(f"[bench] generating {args.workload} {spec.nx}x{spec.ny}x{spec.nz}",
-          file=sys.stderr, flush=True)
-    x_host = synth.generate(spec)
-    x = torch.from_numpy(x_host).cuda()
-    mask = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    batch = len(wl.cubes) > 1
+    print(f"[bench] generating {args.workload}: {len(wl.cubes)} cube(s), "
+          f"{sum(c.n_vox for c in wl.cubes)} voxels", file=sys.stderr, flush=True)
+    xs = []
+    for i, c in enumerate(wl.cubes):
+        xs.append(torch.from_numpy(synth.generate(c)).cuda())
+        if batch and (i + 1) % 16 == 0:
+            print(f"[bench] {i + 1} cubes generated", file=sys.stderr, flush=True)
+    masks = [torch.empty(x.shape, dtype=torch.uint8, device=x.device) for x in xs]
+    x, mask = xs[0], masks[0]
     torch.cuda.synchronize()
     h = sc.SofiaSC(0)
     stream = torch.cuda.current_stream()
 
     def step():
-        return h.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
-                     wl.replacement, mask=mask, stream=stream, storage=args.storage)
+        if batch and args.batch_mode == "graph":
+            _, noise, s0 = h.run_batch(xs, wl.kernels, wl.threshold, wl.noise_mode,
+                                       wl.flux_range, wl.replacement, masks=masks,
+                                       stream=stream, storage=args.storage)
+            return None, noise[0], s0[0]
+        for xi, mi in zip(xs, masks):
+            out = h.run(xi, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
+                        wl.replacement, mask=mi, stream=stream, storage=args.storage)
+        return out
 
     for _ in range(args.warmup):
         step()
@@ -133,7 +154,7 @@ def main():
     stats = h.profile_read()
     print("[bench] timed steps done", file=sys.stderr, flush=True)
 
-    n_vox = spec.n_vox
+    n_vox = sum(c.n_vox for c in wl.cubes)
     value = n_vox * args.steps / dt
     gpu_ms = sum(s["total_ms"] for s in stats)
     dom = max(stats, key=lambda s: s["total_ms"])
@@ -157,10 +178,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded Philox noise + Gaussian mock galaxies)",
         "config": {
-            "workload": args.workload, "nx": spec.nx, "ny": spec.ny, "nz": spec.nz,
+            "workload": args.workload, "n_cubes": len(wl.cubes),
+            "nx": spec.nx, "ny": spec.ny, "nz": spec.nz,
             "kernels": [list(k) for k in wl.kernels], "noise": wl.noise_mode,
             "flux_range": wl.flux_range, "threshold": wl.threshold,
             "replacement": wl.replacement, "storage": args.storage,
+            "batch_mode": args.batch_mode if batch else None,
         },
         "roofline": {
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved,
@@ -175,11 +198,11 @@ def main():
                        for s in stats if s["bytes"] > 0 and s["total_ms"] > 0},
         "noise": [float(v) for v in noise],
         "sigma0": float(sigma0),
-        "mask_voxels": int(mask.sum().item()),
+        "mask_voxels": int(sum(int(m.sum().item()) for m in masks)),
         "kernel_src_sha": kernel_source_sha(),
     }
     h.close()
-    del x, mask
+    del x, mask, xs, masks
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_planes, spec.nz))

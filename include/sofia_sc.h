@@ -71,6 +71,7 @@ enum {
 #define SOFIA_SC_MAX_KERNELS 64
 #define SOFIA_SC_MAX_HALO 16        /* n * r of the spatial cascade */
 #define SOFIA_SC_MAX_WIDTH 63       /* spectral boxcar width */
+#define SOFIA_SC_MAX_CUBES 4096     /* cubes of one batch */
 
 typedef struct {
     uint32_t struct_size;   /* = sizeof(sofia_sc_options) */
@@ -123,6 +124,35 @@ int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     int32_t n_kernels, double threshold, int32_t noise_mode,
                     int32_t flux_range, uint8_t *mask, double *noise,
                     const sofia_sc_options *opt, double *sigma0);
+
+/* One cube of a batch: device pointers, owned by the caller. */
+typedef struct {
+    const float *cube;      /* float32 [nz][ny][nx], read only */
+    int64_t nx, ny, nz;
+    uint8_t *mask;          /* uint8 [nz][ny][nx], fully overwritten with 0/1 */
+} sofia_sc_cube;
+
+/* Independent S+C runs (Sect. 4.2) of many cubes with one kernel list,
+ * threshold, noise mode, flux range and options: the result for each cube is
+ * the one sofia_sc_run_ex gives for it alone (every cube measures its own
+ * sigma_0 and noise; a given opt->sigma0 applies to every cube). The cubes
+ * are spread over a few workspaces whose launch chains run concurrently;
+ * the whole batch is captured once into a HIP graph and launched as one
+ * graph on opt->stream. An identical later call (same cube and mask
+ * pointers, shapes, kernels and settings) launches the same graph again
+ * without capturing. Inputs must be ready on opt->stream.
+ *  cubes    host array of n_cubes (1..SOFIA_SC_MAX_CUBES) descriptors; the
+ *           masks must be distinct and must not overlap any cube.
+ *  noise    host, double[n_cubes][n_kernels] (cube-major).
+ *  sigma0   host, double[n_cubes] or NULL: as sofia_sc_run_ex per cube.
+ * Returns after the work has completed. EINVAL as sofia_sc_run_ex (the
+ * message names the cube), and for n_cubes out of range or two cubes with
+ * one mask. ENOSTAT when any cube has a noise without voxels: every other
+ * value is still filled in. */
+int sofia_sc_run_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
+                       const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
+                       int32_t noise_mode, int32_t flux_range, double *noise,
+                       const sofia_sc_options *opt, double *sigma0);
 
 /* One S+C iteration with the previous state given (Sect. 4.2 and 6.2.4):
  * smooth the cube after replacing the voxels set in mask_in by

@@ -30,7 +30,8 @@ RANGE = {"negative": -1, "all": 0, "positive": 1}
 # Every symbol include/sofia_sc.h declares.
 EXPORTS = [
     "sofia_sc_default_options", "sofia_sc_create", "sofia_sc_destroy",
-    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step", "sofia_sc_step_ex", "sofia_sc_smooth",
+    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch", "sofia_sc_step", "sofia_sc_step_ex",
+    "sofia_sc_smooth",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
 ]
@@ -91,6 +92,11 @@ class Options(ctypes.Structure):
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 
+class Cube(ctypes.Structure):
+    _fields_ = [("cube", ctypes.c_void_p), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("mask", ctypes.c_void_p)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
@@ -121,6 +127,9 @@ def load():
     lib.sofia_sc_run_ex.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(Kernel), i32,
                                     dbl, i32, i32, vp, ctypes.POINTER(dbl),
                                     ctypes.POINTER(Options), ctypes.POINTER(dbl)]
+    lib.sofia_sc_run_batch.argtypes = [vp, ctypes.POINTER(Cube), i32, ctypes.POINTER(Kernel),
+                                       i32, dbl, i32, i32, ctypes.POINTER(dbl),
+                                       ctypes.POINTER(Options), ctypes.POINTER(dbl)]
     lib.sofia_sc_step.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, dbl,
                                   dbl, vp, vp, ctypes.POINTER(dbl), vp]
     lib.sofia_sc_step_ex.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, vp, vp,
@@ -135,7 +144,8 @@ def load():
     lib.sofia_sc_last_error.restype = ctypes.c_char_p
     lib.sofia_sc_strerror.argtypes = [ctypes.c_int]
     lib.sofia_sc_strerror.restype = ctypes.c_char_p
-    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_step",
+    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch",
+                 "sofia_sc_step",
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
                  "sofia_sc_profile_read"):
@@ -247,6 +257,42 @@ class SofiaSC:
         if rc != OK and not (allow_nostat and rc == ENOSTAT):
             self._raise(rc, "sofia_sc_run_ex")
         return mask, np.array(noise[:], dtype=np.float64), s0.value
+
+    def run_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
+                  flux_range: str = "negative", replacement: float = 2.0, masks=None,
+                  stream=None, allow_nostat: bool = False, storage: str = "f32",
+                  sigma0: float = float("nan")):
+        """Independent S+C runs of many cubes in one graph launch.
+
+        Returns (list of mask tensors, noise[n_cubes, K] ndarray, sigma0[n_cubes])."""
+        import torch
+        n = len(cubes)
+        if masks is None:
+            masks = [torch.empty(c.shape, dtype=torch.uint8, device=c.device) for c in cubes]
+        if len(masks) != n:
+            raise ValueError("one mask per cube")
+        desc = (Cube * n)()
+        for i, (c, m) in enumerate(zip(cubes, masks)):
+            nx, ny, nz = _check_cube(c)
+            _check_like(m, c, torch.uint8, "mask")
+            desc[i].cube, desc[i].nx, desc[i].ny, desc[i].nz = c.data_ptr(), nx, ny, nz
+            desc[i].mask = m.data_ptr()
+        K = len(kernels)
+        noise = (ctypes.c_double * (n * K))()
+        s0 = (ctypes.c_double * n)()
+        opt = Options()
+        self.lib.sofia_sc_default_options(ctypes.byref(opt))
+        opt.replacement = float(replacement)
+        opt.sigma0 = float(sigma0)
+        opt.storage = STORAGE[storage]
+        opt.stream = _stream_ptr(stream)
+        rc = self.lib.sofia_sc_run_batch(self.h, desc, n, _kernels(kernels), K,
+                                         float(threshold), NOISE[noise_mode],
+                                         RANGE[flux_range], noise, ctypes.byref(opt), s0)
+        if rc != OK and not (allow_nostat and rc == ENOSTAT):
+            self._raise(rc, "sofia_sc_run_batch")
+        return (masks, np.array(noise[:], dtype=np.float64).reshape(n, K),
+                np.array(s0[:], dtype=np.float64))
 
     def step(self, cube, kernel, threshold: float, noise_mode: str, flux_range: str,
              replacement: float = 2.0, sigma0: float = float("nan"), mask_in=None,

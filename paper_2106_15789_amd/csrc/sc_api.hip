@@ -20,13 +20,13 @@ namespace {
 enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
-    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_COUNT
+    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
-    "clip_fixup"};
+    "clip_fixup", "batch_graph"};
 
 struct LaunchRec {
     int fam;
@@ -47,17 +47,17 @@ struct Plan {
     bool identity() const { return !spatial() && !spectral(); }
 };
 
-}  // namespace
-
-struct sofia_sc {
-    int device = 0;
-    std::string err;
+// Device workspace of one S+C run at a time: working masks, the smoothed
+// plane buffer, histograms, partials, the capture and undecided-voxel lists,
+// the 16-bit cube and the packed detection bits. Grown on demand, never
+// shrunk. `st` is the run's device state; a batch points it at the state of
+// the cube being enqueued.
+struct Work {
     uint8_t *wm[2] = {nullptr, nullptr};
     size_t wm_cap = 0;
     float *p = nullptr;
     size_t p_cap = 0;
     DevState *st = nullptr;
-    DevState *st_host = nullptr;     // pinned
     unsigned long long *hist = nullptr;
     double *part_sum = nullptr;
     unsigned long long *part_cnt = nullptr;
@@ -70,35 +70,73 @@ struct sofia_sc {
     size_t det_cap = 0;              // in words
     AmbEntry *amb = nullptr;         // undecided voxels of the fused clip
     size_t amb_cap = 0;
+};
+
+// Lanes of a batch: cubes are spread over this many workspaces whose
+// launch chains run side by side (one per hardware queue HIP opens by
+// default).
+constexpr int kBatchLanes = 4;
+
+// Everything a captured batch graph depends on; an identical call replays
+// the instantiated graph.
+struct BatchKey {
+    std::vector<sofia_sc_cube> cubes;
+    std::vector<sofia_sc_kernel> kernels;
+    double t = 0, repl = 0;
+    uint64_t sigma0_bits = 0;
+    int mode = 0, range = 0, storage = 0;
+    uint64_t work_gen = 0;
+};
+
+}  // namespace
+
+struct sofia_sc {
+    int device = 0;
+    std::string err;
+    Work w;                          // workspace of run / step / smooth
+    DevState *st_host = nullptr;     // pinned
     bool prof = false;
     std::vector<LaunchRec> recs;
     std::vector<hipEvent_t> pool;
     Agg agg[F_COUNT];
+    // batch
+    Work lanes[kBatchLanes];
+    hipStream_t lane_s[kBatchLanes] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kBatchLanes] = {};
+    DevState *bst = nullptr;         // per-cube device states
+    DevState *bst_host = nullptr;    // pinned copy
+    size_t bst_cap = 0;
+    uint64_t work_gen = 0;           // bumped whenever a lane workspace moves
+    hipGraphExec_t gexec = nullptr;
+    BatchKey gkey;
+    bool gvalid = false;
+    double graph_bytes = 0;          // algorithmic bytes of the captured launches
+    bool capturing = false;          // launches are being captured: no events
+    double capture_bytes = 0;
 };
 
 namespace {
 
 // Histogram workspace, zeroed before every MAD measurement: level 1 |
-// level-2 coarse | level 2 | sampled level 1 | capture count | selection
-// counts | count of voxels the fused clip left undecided.
+// level-2 coarse | level 2 | sampled level 1 | capture count | count of
+// voxels the fused clip left undecided.
 constexpr size_t kOffL2c = kL1Bins;
 constexpr size_t kOffL2 = kOffL2c + 2 * (size_t)kL2Coarse;
 constexpr size_t kOffSample = kOffL2 + 2 * (size_t)kL2Bins;
 constexpr size_t kOffCapCount = kOffSample + kL1Bins;
-constexpr size_t kOffSelCounts = kOffCapCount + 2;
-constexpr size_t kOffAmbCount = kOffSelCounts + 2;
+constexpr size_t kOffAmbCount = kOffCapCount + 2;
 constexpr size_t kHistWords = kOffAmbCount + 2;
-// Columns blocks visited by the sampling pass: every 17th (a stride coprime
-// to the usual blocks-per-row counts spreads the sample over x and y).
+// 64-column segments visited by the sampling pass: every 17th (a stride
+// coprime to the usual row lengths in segments spreads the sample over x and
+// y).
 constexpr int kSampleStride = 17;
 
-unsigned long long *hist1_of(sofia_sc *h) { return h->hist; }
-unsigned long long *hist2c_of(sofia_sc *h) { return h->hist + kOffL2c; }
-unsigned long long *hist2_of(sofia_sc *h) { return h->hist + kOffL2; }
-unsigned long long *hist_s_of(sofia_sc *h) { return h->hist + kOffSample; }
-unsigned long long *cap_count_of(sofia_sc *h) { return h->hist + kOffCapCount; }
-unsigned long long *sel_counts_of(sofia_sc *h) { return h->hist + kOffSelCounts; }
-unsigned long long *amb_count_of(sofia_sc *h) { return h->hist + kOffAmbCount; }
+unsigned long long *hist1_of(const Work &w) { return w.hist; }
+unsigned long long *hist2c_of(const Work &w) { return w.hist + kOffL2c; }
+unsigned long long *hist2_of(const Work &w) { return w.hist + kOffL2; }
+unsigned long long *hist_s_of(const Work &w) { return w.hist + kOffSample; }
+unsigned long long *cap_count_of(const Work &w) { return w.hist + kOffCapCount; }
+unsigned long long *amb_count_of(const Work &w) { return w.hist + kOffAmbCount; }
 
 // Undecided-voxel list of the fused clip: up to N/256 entries (at least
 // 2^16); beyond that the plain clip pass runs.
@@ -201,89 +239,68 @@ ColGrid col_grid(int64_t ncol, int64_t nz) {
     return g;
 }
 
-// 16-bit copy of the cube for F16/BF16 storage.
-int ensure_q16(sofia_sc *h, int64_t N) {
-    if ((size_t)N <= h->xq_cap) return SOFIA_SC_OK;
-    if (h->xq) (void)hipFree(h->xq);
-    h->xq = nullptr;
-    h->xq_cap = 0;
-    const hipError_t e = hipMalloc(&h->xq, (size_t)N * sizeof(uint16_t));
+// Grow a device buffer to at least `need` elements (contents are not kept).
+template <typename T>
+int grow(sofia_sc *h, T *&ptr, size_t &cap, size_t need, const char *what, bool *moved) {
+    if (need <= cap) return SOFIA_SC_OK;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    const hipError_t e = hipMalloc(&ptr, need * sizeof(T));
     if (e != hipSuccess)
-        return fail(h, SOFIA_SC_ENOMEM, std::string("16-bit cube: ") + hipGetErrorString(e));
-    h->xq_cap = (size_t)N;
+        return fail(h, SOFIA_SC_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    cap = need;
+    if (moved) *moved = true;
     return SOFIA_SC_OK;
 }
 
 // Packed detection bits: words per plane of nx * ny voxels.
 int64_t det_words_per_plane(int64_t ncol) { return (ncol + 63) / 64; }
 
-int ensure_workspace(sofia_sc *h, int64_t N, bool need_p, size_t parts,
-                     int64_t det_words = 0) {
+// Workspace for cubes of up to N voxels: `parts` column blocks, the
+// smoothed-plane buffer when a kernel is spatial, det_words packed words and
+// a 16-bit cube when q16. *moved is set when any buffer was reallocated.
+int ensure_work(sofia_sc *h, Work &w, int64_t N, bool need_p, size_t parts,
+                int64_t det_words, bool q16, bool *moved = nullptr) {
+    int rc;
+    size_t one = w.hist ? kHistWords : 0;
+    if ((rc = grow(h, w.hist, one, kHistWords, "histograms", moved))) return rc;
+    if ((rc = grow(h, w.det, w.det_cap, (size_t)det_words, "detection bits", moved))) return rc;
+    for (int i = 0; i < 2; ++i) {
+        size_t cap = w.wm_cap;
+        if ((rc = grow(h, w.wm[i], cap, (size_t)N, "working mask", moved))) return rc;
+    }
+    w.wm_cap = std::max(w.wm_cap, (size_t)N);
+    if (need_p && (rc = grow(h, w.p, w.p_cap, (size_t)N, "plane buffer", moved))) return rc;
+    if ((rc = grow(h, w.amb, w.amb_cap, amb_capacity(N), "undecided list", moved))) return rc;
+    if ((rc = grow(h, w.cap_buf, w.cap_cap, capture_capacity(N), "capture buffer", moved)))
+        return rc;
+    // partial sums: one per block; partial counts: two per block (the
+    // selection pass keeps two counts)
+    size_t pc = w.part_cap, pc2 = 2 * w.part_cap;
+    if ((rc = grow(h, w.part_sum, pc, parts, "partials", moved))) return rc;
+    if ((rc = grow(h, w.part_cnt, pc2, 2 * parts, "partials", moved))) return rc;
+    w.part_cap = std::max(w.part_cap, parts);
+    if (q16 && (rc = grow(h, w.xq, w.xq_cap, (size_t)N, "16-bit cube", moved))) return rc;
+    return SOFIA_SC_OK;
+}
+
+void free_work(Work &w) {
+    void *ps[] = {w.wm[0], w.wm[1], w.p, w.st, w.hist, w.part_sum, w.part_cnt, w.cap_buf,
+                  w.xq, w.det, w.amb};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    w = Work{};
+}
+
+// The handle's own device state and its pinned host copy.
+int ensure_state(sofia_sc *h) {
     hipError_t e;
-    if ((size_t)det_words > h->det_cap) {
-        if (h->det) (void)hipFree(h->det);
-        h->det = nullptr;
-        h->det_cap = 0;
-        if ((e = hipMalloc(&h->det, (size_t)det_words * sizeof(uint64_t))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("detection bits: ") + hipGetErrorString(e));
-        h->det_cap = (size_t)det_words;
-    }
-    if (!h->st) {
-        if ((e = hipMalloc(&h->st, sizeof(DevState))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("state: ") + hipGetErrorString(e));
-        if ((e = hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault)) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("host state: ") + hipGetErrorString(e));
-        if ((e = hipMalloc(&h->hist, kHistWords * sizeof(unsigned long long))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("histograms: ") + hipGetErrorString(e));
-    }
-    if ((size_t)N > h->wm_cap) {
-        for (int i = 0; i < 2; ++i) {
-            if (h->wm[i]) (void)hipFree(h->wm[i]);
-            h->wm[i] = nullptr;
-        }
-        h->wm_cap = 0;
-        for (int i = 0; i < 2; ++i)
-            if ((e = hipMalloc(&h->wm[i], (size_t)N)) != hipSuccess)
-                return fail(h, SOFIA_SC_ENOMEM, std::string("working mask: ") + hipGetErrorString(e));
-        h->wm_cap = (size_t)N;
-    }
-    if (need_p && (size_t)N > h->p_cap) {
-        if (h->p) (void)hipFree(h->p);
-        h->p = nullptr;
-        h->p_cap = 0;
-        if ((e = hipMalloc(&h->p, (size_t)N * sizeof(float))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("plane buffer: ") + hipGetErrorString(e));
-        h->p_cap = (size_t)N;
-    }
-    const size_t acap = amb_capacity(N);
-    if (acap > h->amb_cap) {
-        if (h->amb) (void)hipFree(h->amb);
-        h->amb = nullptr;
-        h->amb_cap = 0;
-        if ((e = hipMalloc(&h->amb, acap * sizeof(AmbEntry))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("undecided list: ") + hipGetErrorString(e));
-        h->amb_cap = acap;
-    }
-    const size_t cap = capture_capacity(N);
-    if (cap > h->cap_cap) {
-        if (h->cap_buf) (void)hipFree(h->cap_buf);
-        h->cap_buf = nullptr;
-        h->cap_cap = 0;
-        if ((e = hipMalloc(&h->cap_buf, cap * sizeof(uint32_t))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("capture buffer: ") + hipGetErrorString(e));
-        h->cap_cap = cap;
-    }
-    if (parts > h->part_cap) {
-        if (h->part_sum) (void)hipFree(h->part_sum);
-        if (h->part_cnt) (void)hipFree(h->part_cnt);
-        h->part_sum = nullptr;
-        h->part_cnt = nullptr;
-        h->part_cap = 0;
-        if ((e = hipMalloc(&h->part_sum, parts * sizeof(double))) != hipSuccess ||
-            (e = hipMalloc(&h->part_cnt, parts * sizeof(unsigned long long))) != hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("partials: ") + hipGetErrorString(e));
-        h->part_cap = parts;
-    }
+    if (!h->w.st && (e = hipMalloc(&h->w.st, sizeof(DevState))) != hipSuccess)
+        return fail(h, SOFIA_SC_ENOMEM, std::string("state: ") + hipGetErrorString(e));
+    if (!h->st_host &&
+        (e = hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault)) != hipSuccess)
+        return fail(h, SOFIA_SC_ENOMEM, std::string("host state: ") + hipGetErrorString(e));
     return SOFIA_SC_OK;
 }
 
@@ -304,6 +321,13 @@ template <typename F>
 int launch(sofia_sc *h, hipStream_t s, int fam, double bytes, double vox, F &&f,
            int cond = -1) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->capturing) {
+        // inside a graph capture: no per-launch events; the algorithmic bytes
+        // of the launches that always work are summed for the whole graph
+        if (cond < 0) h->capture_bytes += bytes;
+        const hipError_t e = f();
+        return e == hipSuccess ? SOFIA_SC_OK : hip_fail(h, e, kFamilyName[fam]);
+    }
     if (h->prof) {
         e0 = take_event(h);
         e1 = take_event(h);
@@ -372,7 +396,7 @@ struct PairJob {
                             // clip must write the packed bits
 };
 
-int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
+int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     const Dims &d = j.d;
     const double N = (double)d.N;
     int rc;
@@ -393,17 +417,17 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         a.wpp = det_words_per_plane(d.ncol);
         a.det = nullptr;
         if (j.repl_active) {
-            if (!j.det_live || h->det_cap < (size_t)(d.nz * a.wpp))
+            if (!j.det_live || w.det_cap < (size_t)(d.nz * a.wpp))
                 return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
-            a.det = h->det;
+            a.det = w.det;
         }
-        a.p = h->p;
+        a.p = w.p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
         spatial_strips(a, j.pl.n_iter, j.pl.radius);
         if (a.tiles > 0x7fffffffLL)
             return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
         a.repl_n = j.repl_n;
-        a.st = h->st;
+        a.st = w.st;
         const double bytes = N * (bx + (j.repl_active ? 1.0 : 0.0) + 4.0);
         rc = launch(h, s, F_SPATIAL, bytes, N, [&] {
             return launch_spatial(j.pl.n_iter, j.pl.radius, j.xtype, j.repl_active, a, s);
@@ -415,7 +439,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     c.x = j.x;
     c.xq = j.xq;
     c.xtype = j.xtype;
-    c.p = h->p;
+    c.p = w.p;
     c.wm_in = j.wm_in;
     c.ncol = d.ncol;
     c.nz = d.nz;
@@ -426,17 +450,17 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     c.range = j.range;
     c.repl_on = (!spatial && j.repl_active) ? 1 : 0;
     c.repl_n = j.repl_n;
-    c.st = h->st;
-    c.part_sum = h->part_sum;
-    c.part_cnt = h->part_cnt;
-    c.hist1 = hist1_of(h);
-    c.hist2 = hist2_of(h);
-    c.hist2c = hist2c_of(h);
+    c.st = w.st;
+    c.part_sum = w.part_sum;
+    c.part_cnt = w.part_cnt;
+    c.hist1 = hist1_of(w);
+    c.hist2 = hist2_of(w);
+    c.hist2c = hist2c_of(w);
     c.cb_stride = 1;
-    c.cap_buf = h->cap_buf;
-    c.cap_count = cap_count_of(h);
-    c.cap_capacity = (unsigned long long)h->cap_cap;
-    c.sel_counts = sel_counts_of(h);
+    c.cap_buf = w.cap_buf;
+    c.cap_count = cap_count_of(w);
+    c.cap_capacity = (unsigned long long)w.cap_cap;
+    c.sel_part = w.part_cnt;
     const int src = spatial ? SRC_P : SRC_X;
     const double rd = N * ((spatial ? 4.0 : bx) + (has_wm ? 1.0 : 0.0));
     auto col = [&](int op, int fam, double bytes) {
@@ -460,9 +484,9 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         c.wpp = det_words_per_plane(d.ncol);
         c.det_bits = nullptr;
         if (j.det_live && j.det_next && !j.out_user) {
-            if (h->det_cap < (size_t)(d.nz * c.wpp))
+            if (w.det_cap < (size_t)(d.nz * c.wpp))
                 return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
-            c.det_bits = h->det;
+            c.det_bits = w.det;
         }
         clip_bytes = N + (c.det_bits ? N / 8.0 : 0.0);
     }
@@ -473,7 +497,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
     if (j.mode == SOFIA_SC_NOISE_STD) {
         if ((rc = col(OP_STD, F_COL_STD, rd))) return rc;
         rc = launch(h, s, F_FINALIZE, 16.0 * g.blocks(), 0, [&] {
-            return launch_finalize_std(h->st, h->part_sum, h->part_cnt, g.blocks(),
+            return launch_finalize_std(w.st, w.part_sum, w.part_cnt, g.blocks(),
                                        j.k, j.t, j.also_sigma0 ? 1 : 0, s);
         });
         if (rc) return rc;
@@ -485,7 +509,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         // If the window missed them, full level-1 and level-2 passes over the
         // cube run instead (each launch checks the flag and exits otherwise).
         rc = launch(h, s, F_FILL, 8.0 * kHistWords, 0, [&] {
-            return launch_fill_u64(h->hist, (int64_t)kHistWords, s);
+            return launch_fill_u64(w.hist, (int64_t)kHistWords, s);
         });
         if (rc) return rc;
         {
@@ -493,43 +517,46 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
             // launch still has a few blocks per CU.
             ColArgs cs = c;
             cs.cb_stride = kSampleStride;
-            cs.ncb = (g.ncb + kSampleStride - 1) / kSampleStride;
-            cs.hist1 = hist_s_of(h);
+            const int64_t nseg = (d.ncol + 63) / 64;   // 64-column segments
+            const int64_t sampled = (nseg + kSampleStride - 1) / kSampleStride;
+            cs.ncb = (int)((sampled + kColThreads / 64 - 1) / (kColThreads / 64));
+            cs.hist1 = hist_s_of(w);
             int nzc = (int)std::min<int64_t>((2048 + cs.ncb - 1) / cs.ncb,
                                              std::max<int64_t>(1, d.nz / 32));
             nzc = std::max(nzc, 1);
             cs.zchunk = (int)((d.nz + nzc - 1) / nzc);
             nzc = (int)((d.nz + cs.zchunk - 1) / cs.zchunk);
             const int nb = cs.ncb * nzc;
-            rc = launch(h, s, F_COL_SAMPLE, rd * cs.ncb / g.ncb, N * cs.ncb / g.ncb, [&] {
+            const double frac = (double)sampled / (double)nseg;
+            rc = launch(h, s, F_COL_SAMPLE, rd * frac, N * frac, [&] {
                 return launch_column(src, OP_HIST1, spec, has_wm, cs, nb, s);
             });
             if (rc) return rc;
         }
         rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
-            return launch_finalize_predict(h->st, hist_s_of(h), j.t, s);
+            return launch_finalize_predict(w.st, hist_s_of(w), j.t, s);
         });
         if (rc) return rc;
         // Fused clip: the predicted median window bounds the threshold, so
         // the selection pass also clips every voxel whose |s| lies outside
         // (thr_lo, thr_hi] and lists the others for an exact decision later.
         if (fused) {
-            c.amb = h->amb;
-            c.amb_count = amb_count_of(h);
-            c.amb_capacity = (unsigned long long)h->amb_cap;
+            c.amb = w.amb;
+            c.amb_count = amb_count_of(w);
+            c.amb_capacity = (unsigned long long)w.amb_cap;
             if ((rc = col(OP_SELCLIP, F_COL_SELCLIP, rd + clip_bytes))) return rc;
         } else {
             if ((rc = col(OP_SELECT, F_COL_SELECT, rd))) return rc;
         }
         rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
-            return launch_finalize_select(h->st, sel_counts_of(h), cap_count_of(h),
-                                          (unsigned long long)h->cap_cap, j.k,
-                                          fused ? amb_count_of(h) : nullptr,
-                                          (unsigned long long)h->amb_cap, s);
+            return launch_finalize_select(w.st, w.part_cnt, g.blocks(), cap_count_of(w),
+                                          (unsigned long long)w.cap_cap, j.k,
+                                          fused ? amb_count_of(w) : nullptr,
+                                          (unsigned long long)w.amb_cap, s);
         });
         if (rc) return rc;
         rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
-            return launch_capture_l1(h->st, h->cap_buf, cap_count_of(h), hist1_of(h), s);
+            return launch_capture_l1(w.st, w.cap_buf, cap_count_of(w), hist1_of(w), s);
         });
         if (rc) return rc;
         c.skip_if_captured = 1;
@@ -538,11 +565,11 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         }, cond);
         if (rc) return rc;
         rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
-            return launch_finalize_mad1(h->st, hist1_of(h), s);
+            return launch_finalize_mad1(w.st, hist1_of(w), s);
         });
         if (rc) return rc;
         rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
-            return launch_capture_coarse(h->st, h->cap_buf, cap_count_of(h), hist2c_of(h), s);
+            return launch_capture_coarse(w.st, w.cap_buf, cap_count_of(w), hist2c_of(w), s);
         });
         if (rc) return rc;
         rc = launch(h, s, F_COL_HIST2, rd, N, [&] {
@@ -551,15 +578,15 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         c.skip_if_captured = 0;
         if (rc) return rc;
         rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Coarse, 0, [&] {
-            return launch_finalize_mad2a(h->st, hist2c_of(h), s);
+            return launch_finalize_mad2a(w.st, hist2c_of(w), s);
         });
         if (rc) return rc;
         rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
-            return launch_capture_fine(h->st, h->cap_buf, cap_count_of(h), hist2_of(h), s);
+            return launch_capture_fine(w.st, w.cap_buf, cap_count_of(w), hist2_of(w), s);
         });
         if (rc) return rc;
         rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Fine, 0, [&] {
-            return launch_finalize_mad2b(h->st, hist2_of(h), j.k, j.t,
+            return launch_finalize_mad2b(w.st, hist2_of(w), j.k, j.t,
                                          j.also_sigma0 ? 1 : 0, s);
         });
         if (rc) return rc;
@@ -568,8 +595,8 @@ int run_pair(sofia_sc *h, hipStream_t s, const PairJob &j) {
         // decide the listed voxels; the full clip pass below runs only when
         // the median missed the window or the list overflowed
         rc = launch(h, s, F_CLIP_FIXUP, 0, 0, [&] {
-            return launch_clip_fixup(h->st, h->amb, amb_count_of(h),
-                                     (unsigned long long)h->amb_cap, c.mask_out, c.out_user,
+            return launch_clip_fixup(w.st, w.amb, amb_count_of(w),
+                                     (unsigned long long)w.amb_cap, c.mask_out, c.out_user,
                                      c.det_bits, d.ncol, c.wpp, s);
         });
         if (rc) return rc;
@@ -599,9 +626,9 @@ struct DeviceGuard {
     }
 };
 
-int finish(sofia_sc *h, hipStream_t s) {
-    hipError_t e = hipMemcpyAsync(h->st_host, h->st, sizeof(DevState),
-                                  hipMemcpyDeviceToHost, s);
+// Copy n device states to the host and wait for the stream.
+int finish(sofia_sc *h, hipStream_t s, DevState *host, const DevState *dev, size_t n = 1) {
+    hipError_t e = hipMemcpyAsync(host, dev, n * sizeof(DevState), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(h, e, "copy of noise values");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "stream");
     if (h->prof) collect_profile(h);
@@ -611,6 +638,120 @@ int finish(sofia_sc *h, hipStream_t s) {
 void nan_fill(double *v, int n) {
     if (v)
         for (int i = 0; i < n; ++i) v[i] = NAN;
+}
+
+// A validated whole run: one cube, its kernel plans and options.
+struct RunSpec {
+    const float *cube;
+    Dims d;
+    const Plan *plans;
+    int K;
+    double t;
+    int mode, range;
+    uint8_t *mask;
+    double repl;          // < 0: no replacement
+    double sigma0;        // NaN: measure
+    int storage;
+    bool any_spatial() const {
+        for (int k = 0; k < K; ++k)
+            if (plans[k].spatial()) return true;
+        return false;
+    }
+};
+
+int check_options(sofia_sc *h, const sofia_sc_options *opt) {
+    if (!opt || opt->struct_size != sizeof(sofia_sc_options))
+        return fail(h, SOFIA_SC_EINVAL, "options missing or struct_size mismatch");
+    if (std::isnan(opt->replacement) || opt->replacement == INFINITY)
+        return fail(h, SOFIA_SC_EINVAL, "replacement must be finite");
+    const int storage = opt->storage;
+    if (storage != SOFIA_SC_STORE_F32 && storage != SOFIA_SC_STORE_F16 &&
+        storage != SOFIA_SC_STORE_BF16)
+        return fail(h, SOFIA_SC_EINVAL, "unknown storage");
+    if (opt->reserved != 0) return fail(h, SOFIA_SC_EINVAL, "reserved option field must be 0");
+    if (!std::isnan(opt->sigma0) && !(std::isfinite(opt->sigma0) && opt->sigma0 > 0.0))
+        return fail(h, SOFIA_SC_EINVAL, "sigma0 must be NaN (measure) or finite and > 0");
+    return SOFIA_SC_OK;
+}
+
+// Workspace a run of this cube and kernel list needs.
+int ensure_for(sofia_sc *h, Work &w, const RunSpec &r, bool *moved = nullptr) {
+    const bool sp = r.any_spatial();
+    const ColGrid g = col_grid(r.d.ncol, r.d.nz);
+    return ensure_work(h, w, r.d.N, sp, (size_t)g.blocks(),
+                       sp ? r.d.nz * det_words_per_plane(r.d.ncol) : 0,
+                       r.storage != SOFIA_SC_STORE_F32, moved);
+}
+
+// Enqueue a whole S+C run (Sect. 4.2) on stream s, with workspace w and the
+// run's state w.st. Makes no host round trip: every later launch reads what
+// it needs from the device state.
+int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
+    int rc;
+    const Dims &d = r.d;
+    const int K = r.K;
+    const bool given0 = !std::isnan(r.sigma0);
+    const bool q16 = r.storage != SOFIA_SC_STORE_F32;
+    const bool any_spatial = r.any_spatial();
+    const bool repl_on = r.repl >= 0.0;
+    const bool first_identity = r.plans[0].identity();
+    rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
+        return launch_set_sigma0(w.st, given0 ? r.sigma0 : NAN, s);
+    });
+    if (rc) return rc;
+    int cur = 0;
+    bool have_wm = false;
+    if (!first_identity) {
+        rc = launch(h, s, F_INIT, 5.0 * d.N, (double)d.N, [&] {
+            return launch_init_mask(r.cube, nullptr, w.wm[0], d.N, s);
+        });
+        if (rc) return rc;
+        have_wm = true;
+    }
+    // sigma_0 on the FP32 cube when replacement or 16-bit scaling needs it and
+    // it cannot come from kernel 1 (a (0, 0) kernel measured on FP32 data).
+    if (!given0 && (q16 || (repl_on && !first_identity))) {
+        PairJob j{r.cube, nullptr, ST_F32, d, Plan{0, 0, 1}, -1, false, 0.0, r.mode, r.range,
+                  r.t, have_wm ? w.wm[cur] : nullptr, nullptr, false, false, nullptr};
+        if ((rc = run_pair(h, s, w, j))) return rc;
+    }
+    int xtype = ST_F32;
+    if (q16) {
+        xtype = r.storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
+        rc = launch(h, s, F_QUANTIZE, 6.0 * d.N, (double)d.N, [&] {
+            return launch_quantize(r.cube, w.st, 0.0, xtype, w.xq, d.N, s);
+        });
+        if (rc) return rc;
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(w.st, s); });
+        if (rc) return rc;
+    }
+    for (int k = 0; k < K; ++k) {
+        const bool last = k == K - 1;
+        uint8_t *out = last ? r.mask : (have_wm ? w.wm[1 - cur] : w.wm[cur]);
+        PairJob j{r.cube, q16 ? w.xq : nullptr, xtype, d, r.plans[k], k, repl_on && k >= 1,
+                  r.repl, r.mode, r.range, r.t, have_wm ? w.wm[cur] : nullptr, out, last,
+                  k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
+                  any_spatial, !last && r.plans[k + 1].spatial() && repl_on};
+        if ((rc = run_pair(h, s, w, j))) return rc;
+        if (!last) {
+            if (have_wm) cur = 1 - cur;
+            have_wm = true;
+        }
+    }
+    return SOFIA_SC_OK;
+}
+
+// Noise values of a finished run in cube units, and its sigma_0 output.
+int read_run(sofia_sc *h, const DevState &hs, const RunSpec &r, double *noise,
+             double *sigma0_out) {
+    const bool q16 = r.storage != SOFIA_SC_STORE_F32;
+    const double scale = q16 ? hs.scale : 1.0;   // stored units -> cube units
+    for (int k = 0; k < r.K; ++k) noise[k] = hs.sigma[k] * scale;
+    if (sigma0_out)
+        *sigma0_out = q16 ? hs.scale
+                          : (r.repl >= 0.0 || !std::isnan(r.sigma0) ? hs.sigma0 : NAN);
+    if (hs.status) return fail(h, SOFIA_SC_ENOSTAT, "no finite voxel in the flux range for some kernel");
+    return SOFIA_SC_OK;
 }
 
 int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
@@ -625,90 +766,220 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
         return fail(h, SOFIA_SC_EINVAL, "NULL argument");
     if (K < 1 || K > SOFIA_SC_MAX_KERNELS)
         return fail(h, SOFIA_SC_EINVAL, "number of kernels must be 1..64");
-    if (!opt || opt->struct_size != sizeof(sofia_sc_options))
-        return fail(h, SOFIA_SC_EINVAL, "options missing or struct_size mismatch");
     int rc;
+    if ((rc = check_options(h, opt))) return rc;
     if ((rc = check_dims(h, nx, ny, nz))) return rc;
     if ((rc = check_modes(h, t, mode, range))) return rc;
-    if (std::isnan(opt->replacement) || opt->replacement == INFINITY)
-        return fail(h, SOFIA_SC_EINVAL, "replacement must be finite");
-    const int storage = opt->storage;
-    if (storage != SOFIA_SC_STORE_F32 && storage != SOFIA_SC_STORE_F16 &&
-        storage != SOFIA_SC_STORE_BF16)
-        return fail(h, SOFIA_SC_EINVAL, "unknown storage");
-    if (opt->reserved != 0) return fail(h, SOFIA_SC_EINVAL, "reserved option field must be 0");
-    const bool given0 = !std::isnan(opt->sigma0);
-    if (given0 && !(std::isfinite(opt->sigma0) && opt->sigma0 > 0.0))
-        return fail(h, SOFIA_SC_EINVAL, "sigma0 must be NaN (measure) or finite and > 0");
     std::vector<Plan> plans((size_t)K);
-    bool any_spatial = false;
-    for (int k = 0; k < K; ++k) {
+    for (int k = 0; k < K; ++k)
         if ((rc = make_plan(h, kernels[k], &plans[k]))) return rc;
-        any_spatial |= plans[k].spatial();
-    }
     DeviceGuard dg(h->device);
     if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)opt->stream;
-    Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
-    const ColGrid g = col_grid(d.ncol, d.nz);
-    const bool q16 = storage != SOFIA_SC_STORE_F32;
-    if ((rc = ensure_workspace(h, d.N, any_spatial, (size_t)g.blocks(),
-                               any_spatial ? d.nz * det_words_per_plane(d.ncol) : 0)))
-        return rc;
-    if (q16 && (rc = ensure_q16(h, d.N))) return rc;
+    const RunSpec r{cube, Dims{nx, ny, nz, nx * ny, nx * ny * nz}, plans.data(), K, t, mode,
+                    range, mask, opt->replacement, opt->sigma0, opt->storage};
+    if ((rc = ensure_state(h))) return rc;
+    if ((rc = ensure_for(h, h->w, r))) return rc;
+    if ((rc = enqueue_run(h, s, h->w, r))) return rc;
+    if ((rc = finish(h, s, h->st_host, h->w.st))) return rc;
+    return read_run(h, *h->st_host, r, noise, sigma0_out);
+}
 
-    const bool repl_on = opt->replacement >= 0.0;
-    const bool first_identity = plans[0].identity();
-    rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
-        return launch_set_sigma0(h->st, given0 ? opt->sigma0 : NAN, s);
-    });
-    if (rc) return rc;
-    int cur = 0;
-    bool have_wm = false;
-    if (!first_identity) {
-        rc = launch(h, s, F_INIT, 5.0 * d.N, (double)d.N, [&] {
-            return launch_init_mask(cube, nullptr, h->wm[0], d.N, s);
-        });
-        if (rc) return rc;
-        have_wm = true;
+// ---- batches: many independent cubes, one graph launch
+
+bool same_key(const BatchKey &a, const BatchKey &b) {
+    if (a.cubes.size() != b.cubes.size() || a.kernels.size() != b.kernels.size()) return false;
+    for (size_t i = 0; i < a.cubes.size(); ++i) {
+        const sofia_sc_cube &x = a.cubes[i], &y = b.cubes[i];
+        if (x.cube != y.cube || x.mask != y.mask || x.nx != y.nx || x.ny != y.ny || x.nz != y.nz)
+            return false;
     }
-    // sigma_0 on the FP32 cube when replacement or 16-bit scaling needs it and
-    // it cannot come from kernel 1 (a (0, 0) kernel measured on FP32 data).
-    if (!given0 && (q16 || (repl_on && !first_identity))) {
-        PairJob j{cube, nullptr, ST_F32, d, Plan{0, 0, 1}, -1, false, 0.0, mode, range, t,
-                  have_wm ? h->wm[cur] : nullptr, nullptr, false, false, nullptr};
-        if ((rc = run_pair(h, s, j))) return rc;
+    for (size_t k = 0; k < a.kernels.size(); ++k)
+        if (std::memcmp(&a.kernels[k].spatial_fwhm_px, &b.kernels[k].spatial_fwhm_px,
+                        sizeof(double)) != 0 ||
+            a.kernels[k].spectral_width_ch != b.kernels[k].spectral_width_ch)
+            return false;
+    return a.t == b.t && a.repl == b.repl && a.sigma0_bits == b.sigma0_bits &&
+           a.mode == b.mode && a.range == b.range && a.storage == b.storage &&
+           a.work_gen == b.work_gen;
+}
+
+void drop_graph(sofia_sc *h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gvalid = false;
+}
+
+// Lane streams, fork/join events and the per-cube device states.
+int ensure_batch_infra(sofia_sc *h, size_t n, bool *moved) {
+    hipError_t e;
+    for (int l = 0; l < kBatchLanes; ++l) {
+        if (!h->lane_s[l] &&
+            (e = hipStreamCreateWithFlags(&h->lane_s[l], hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(h, e, "lane stream");
+        if (!h->join_ev[l] &&
+            (e = hipEventCreateWithFlags(&h->join_ev[l], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(h, e, "lane event");
     }
-    int xtype = ST_F32;
-    if (q16) {
-        xtype = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
-        rc = launch(h, s, F_QUANTIZE, 6.0 * d.N, (double)d.N, [&] {
-            return launch_quantize(cube, h->st, 0.0, xtype, h->xq, d.N, s);
-        });
-        if (rc) return rc;
-        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(h->st, s); });
-        if (rc) return rc;
+    if (!h->fork_ev &&
+        (e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(h, e, "fork event");
+    if (n > h->bst_cap) {
+        if (h->bst) (void)hipFree(h->bst);
+        if (h->bst_host) (void)hipHostFree(h->bst_host);
+        h->bst = nullptr;
+        h->bst_host = nullptr;
+        h->bst_cap = 0;
+        if ((e = hipMalloc(&h->bst, n * sizeof(DevState))) != hipSuccess)
+            return fail(h, SOFIA_SC_ENOMEM, std::string("batch states: ") + hipGetErrorString(e));
+        if ((e = hipHostMalloc(&h->bst_host, n * sizeof(DevState), hipHostMallocDefault)) !=
+            hipSuccess)
+            return fail(h, SOFIA_SC_ENOMEM, std::string("batch host states: ") + hipGetErrorString(e));
+        h->bst_cap = n;
+        *moved = true;
     }
-    for (int k = 0; k < K; ++k) {
-        const bool last = k == K - 1;
-        uint8_t *out = last ? mask : (have_wm ? h->wm[1 - cur] : h->wm[cur]);
-        PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, plans[k], k, repl_on && k >= 1,
-                  opt->replacement, mode, range, t, have_wm ? h->wm[cur] : nullptr, out, last,
-                  k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
-                  any_spatial, !last && plans[k + 1].spatial() && repl_on};
-        if ((rc = run_pair(h, s, j))) return rc;
-        if (!last) {
-            if (have_wm) cur = 1 - cur;
-            have_wm = true;
+    return SOFIA_SC_OK;
+}
+
+// Capture every cube's launch chain into one graph: lane l's cubes run one
+// after another on lane stream l, the lanes side by side (forked from and
+// joined back into lane 0, the capture's origin).
+int capture_batch(sofia_sc *h, const std::vector<RunSpec> &runs,
+                  const std::vector<std::vector<int>> &lane_cubes) {
+    const int L = (int)lane_cubes.size();
+    hipStream_t s0 = h->lane_s[0];
+    hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(h, e, "graph capture");
+    h->capturing = true;
+    h->capture_bytes = 0;
+    int rc = SOFIA_SC_OK;
+    e = hipEventRecord(h->fork_ev, s0);
+    for (int l = 1; l < L && e == hipSuccess; ++l) e = hipStreamWaitEvent(h->lane_s[l], h->fork_ev, 0);
+    if (e != hipSuccess) rc = hip_fail(h, e, "graph fork");
+    for (int l = 0; l < L && rc == SOFIA_SC_OK; ++l) {
+        for (int i : lane_cubes[l]) {
+            Work w = h->lanes[l];
+            w.st = h->bst + i;
+            if ((rc = enqueue_run(h, h->lane_s[l], w, runs[(size_t)i]))) break;
         }
     }
-    if ((rc = finish(h, s))) return rc;
-    const DevState &hs = *h->st_host;
-    const double scale = q16 ? hs.scale : 1.0;   // stored units -> cube units
-    for (int k = 0; k < K; ++k) noise[k] = hs.sigma[k] * scale;
-    if (sigma0_out) *sigma0_out = q16 ? hs.scale : (repl_on || given0 ? hs.sigma0 : NAN);
-    if (hs.status) return fail(h, SOFIA_SC_ENOSTAT, "no finite voxel in the flux range for some kernel");
-    return SOFIA_SC_OK;
+    // join every forked lane, also after an error, so no stream stays in capture
+    for (int l = 1; l < L; ++l) {
+        hipError_t ej = hipEventRecord(h->join_ev[l], h->lane_s[l]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(s0, h->join_ev[l], 0);
+        if (ej != hipSuccess && rc == SOFIA_SC_OK) rc = hip_fail(h, ej, "graph join");
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s0, &g);
+    h->capturing = false;
+    if (rc == SOFIA_SC_OK && e != hipSuccess) rc = hip_fail(h, e, "graph capture end");
+    if (rc == SOFIA_SC_OK) {
+        e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            h->gexec = nullptr;
+            rc = hip_fail(h, e, "graph instantiate");
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (rc == SOFIA_SC_OK) h->graph_bytes = h->capture_bytes;
+    return rc;
+}
+
+int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
+               const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
+               int32_t range, double *noise, const sofia_sc_options *opt,
+               double *sigma0_out) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err.clear();
+    const bool sizes_ok = n >= 1 && n <= SOFIA_SC_MAX_CUBES && K >= 1 && K <= SOFIA_SC_MAX_KERNELS;
+    if (sizes_ok) {
+        nan_fill(noise, n * K);
+        nan_fill(sigma0_out, n);
+    }
+    if (!cubes || !kernels || !noise) return fail(h, SOFIA_SC_EINVAL, "NULL argument");
+    if (!sizes_ok)
+        return fail(h, SOFIA_SC_EINVAL, "number of cubes must be 1..4096 and of kernels 1..64");
+    int rc;
+    if ((rc = check_options(h, opt))) return rc;
+    if ((rc = check_modes(h, t, mode, range))) return rc;
+    std::vector<Plan> plans((size_t)K);
+    for (int k = 0; k < K; ++k)
+        if ((rc = make_plan(h, kernels[k], &plans[k]))) return rc;
+    std::vector<RunSpec> runs;
+    runs.reserve((size_t)n);
+    std::vector<const uint8_t *> masks;
+    for (int i = 0; i < n; ++i) {
+        const sofia_sc_cube &c = cubes[i];
+        if (!c.cube || !c.mask)
+            return fail(h, SOFIA_SC_EINVAL, "NULL cube or mask in cube " + std::to_string(i));
+        if ((rc = check_dims(h, c.nx, c.ny, c.nz))) {
+            h->err += " (cube " + std::to_string(i) + ")";
+            return rc;
+        }
+        runs.push_back(RunSpec{c.cube, Dims{c.nx, c.ny, c.nz, c.nx * c.ny, c.nx * c.ny * c.nz},
+                               plans.data(), K, t, mode, range, c.mask, opt->replacement,
+                               opt->sigma0, opt->storage});
+        masks.push_back(c.mask);
+    }
+    std::sort(masks.begin(), masks.end());
+    if (std::adjacent_find(masks.begin(), masks.end()) != masks.end())
+        return fail(h, SOFIA_SC_EINVAL, "two cubes share one mask");
+    DeviceGuard dg(h->device);
+    if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
+
+    // Longest first onto the least loaded lane.
+    const int L = std::min<int>(kBatchLanes, n);
+    std::vector<int> order((size_t)n);
+    for (int i = 0; i < n; ++i) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return runs[(size_t)a].d.N > runs[(size_t)b].d.N; });
+    std::vector<std::vector<int>> lane_cubes((size_t)L);
+    std::vector<double> load((size_t)L, 0.0);
+    for (int i : order) {
+        const size_t l = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane_cubes[l].push_back(i);
+        load[l] += (double)runs[(size_t)i].d.N;
+    }
+    bool moved = false;
+    for (int l = 0; l < L; ++l)
+        for (int i : lane_cubes[(size_t)l])
+            if ((rc = ensure_for(h, h->lanes[l], runs[(size_t)i], &moved))) return rc;
+    if ((rc = ensure_batch_infra(h, (size_t)n, &moved))) return rc;
+    if (moved) {
+        ++h->work_gen;
+        drop_graph(h);
+    }
+
+    BatchKey key;
+    key.cubes.assign(cubes, cubes + n);
+    key.kernels.assign(kernels, kernels + K);
+    key.t = t;
+    key.repl = opt->replacement;
+    std::memcpy(&key.sigma0_bits, &opt->sigma0, sizeof(double));
+    key.mode = mode;
+    key.range = range;
+    key.storage = opt->storage;
+    key.work_gen = h->work_gen;
+    if (!h->gvalid || !same_key(key, h->gkey)) {
+        drop_graph(h);
+        if ((rc = capture_batch(h, runs, lane_cubes))) return rc;
+        h->gkey = std::move(key);
+        h->gvalid = true;
+    }
+
+    hipStream_t s = (hipStream_t)opt->stream;
+    double vox = 0;
+    for (const RunSpec &r : runs) vox += (double)r.d.N;
+    rc = launch(h, s, F_BATCH, h->graph_bytes, vox, [&] { return hipGraphLaunch(h->gexec, s); });
+    if (rc) return rc;
+    if ((rc = finish(h, s, h->bst_host, h->bst, (size_t)n))) return rc;
+    for (int i = 0; i < n; ++i) {
+        const int ri = read_run(h, h->bst_host[i], runs[(size_t)i], noise + (size_t)i * K,
+                                sigma0_out ? sigma0_out + i : nullptr);
+        if (ri) rc = ri;
+    }
+    if (rc == SOFIA_SC_ENOSTAT) h->err = "no finite voxel in the flux range for some kernel of some cube";
+    return rc;
 }
 
 }  // namespace
@@ -766,20 +1037,22 @@ void sofia_sc_destroy(sofia_sc *h) {
     if (!h) return;
     {
         DeviceGuard dg(h->device);
+        drop_graph(h);
         for (auto &r : h->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
         for (auto e : h->pool) (void)hipEventDestroy(e);
-        if (h->wm[0]) (void)hipFree(h->wm[0]);
-        if (h->wm[1]) (void)hipFree(h->wm[1]);
-        if (h->p) (void)hipFree(h->p);
-        if (h->st) (void)hipFree(h->st);
+        free_work(h->w);   // also frees h->w.st
+        for (auto &w : h->lanes) {
+            w.st = nullptr;    // lanes borrow the per-cube states
+            free_work(w);
+        }
         if (h->st_host) (void)hipHostFree(h->st_host);
-        if (h->hist) (void)hipFree(h->hist);
-        if (h->part_sum) (void)hipFree(h->part_sum);
-        if (h->part_cnt) (void)hipFree(h->part_cnt);
-        if (h->cap_buf) (void)hipFree(h->cap_buf);
-        if (h->xq) (void)hipFree(h->xq);
-        if (h->det) (void)hipFree(h->det);
-        if (h->amb) (void)hipFree(h->amb);
+        if (h->bst) (void)hipFree(h->bst);
+        if (h->bst_host) (void)hipHostFree(h->bst_host);
+        for (int l = 0; l < kBatchLanes; ++l) {
+            if (h->lane_s[l]) (void)hipStreamDestroy(h->lane_s[l]);
+            if (h->join_ev[l]) (void)hipEventDestroy(h->join_ev[l]);
+        }
+        if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     }
     delete h;
 }
@@ -801,6 +1074,14 @@ int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     const sofia_sc_options *opt, double *sigma0) {
     return run_impl(h, cube, nx, ny, nz, kernels, n_kernels, threshold, noise_mode,
                     flux_range, mask, noise, opt, sigma0);
+}
+
+int sofia_sc_run_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
+                       const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
+                       int32_t noise_mode, int32_t flux_range, double *noise,
+                       const sofia_sc_options *opt, double *sigma0) {
+    return batch_impl(h, cubes, n_cubes, kernels, n_kernels, threshold, noise_mode, flux_range,
+                      noise, opt, sigma0);
 }
 
 static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
@@ -837,21 +1118,22 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     hipStream_t s = (hipStream_t)stream;
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
     const ColGrid g = col_grid(d.ncol, d.nz);
-    if ((rc = ensure_workspace(h, d.N, pl.spatial(), (size_t)g.blocks(),
-                               pl.spatial() ? d.nz * det_words_per_plane(d.ncol) : 0)))
+    if ((rc = ensure_state(h))) return rc;
+    if ((rc = ensure_work(h, h->w, d.N, pl.spatial(), (size_t)g.blocks(),
+                          pl.spatial() ? d.nz * det_words_per_plane(d.ncol) : 0, q16)))
         return rc;
-    if (q16 && (rc = ensure_q16(h, d.N))) return rc;
+    const Work &w = h->w;
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
-        return launch_set_sigma0(h->st, (repl || q16) ? sigma0 : NAN, s);
+        return launch_set_sigma0(w.st, (repl || q16) ? sigma0 : NAN, s);
     });
     if (rc) return rc;
     rc = launch(h, s, F_INIT, (mask_in ? 6.0 : 5.0) * d.N, (double)d.N, [&] {
-        return launch_init_mask(cube, mask_in, h->wm[0], d.N, s);
+        return launch_init_mask(cube, mask_in, w.wm[0], d.N, s);
     });
     if (rc) return rc;
     if (pl.spatial() && repl) {
         rc = launch(h, s, F_INIT, 1.125 * d.N, (double)d.N, [&] {
-            return launch_pack_det(h->wm[0], h->det, d.ncol, d.nz,
+            return launch_pack_det(w.wm[0], w.det, d.ncol, d.nz,
                                    det_words_per_plane(d.ncol), s);
         });
         if (rc) return rc;
@@ -860,18 +1142,18 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     if (q16) {
         xtype = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
         rc = launch(h, s, F_QUANTIZE, 6.0 * d.N, (double)d.N, [&] {
-            return launch_quantize(cube, h->st, 0.0, xtype, h->xq, d.N, s);
+            return launch_quantize(cube, w.st, 0.0, xtype, w.xq, d.N, s);
         });
         if (rc) return rc;
-        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(h->st, s); });
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(w.st, s); });
         if (rc) return rc;
     }
-    PairJob j{cube, q16 ? h->xq : nullptr, xtype, d, pl, 0, repl, replacement,
+    PairJob j{cube, q16 ? w.xq : nullptr, xtype, d, pl, 0, repl, replacement,
               write_out ? 0 : mode, write_out ? 0 : range, write_out ? 1.0 : threshold,
-              h->wm[0], write_out ? nullptr : mask_out, true, false, write_out,
+              w.wm[0], write_out ? nullptr : mask_out, true, false, write_out,
               pl.spatial()};
-    if ((rc = run_pair(h, s, j))) return rc;
-    if ((rc = finish(h, s))) return rc;
+    if ((rc = run_pair(h, s, w, j))) return rc;
+    if ((rc = finish(h, s, h->st_host, w.st))) return rc;
     if (write_out) return SOFIA_SC_OK;
     *noise = h->st_host->sigma[0] * (q16 ? h->st_host->scale : 1.0);
     if (h->st_host->status)

@@ -43,10 +43,18 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     const int tid = threadIdx.x;
     if ((OP == OP_HIST1 || OP == OP_HIST2) && a.skip_if_captured && a.st->use_capture) return;
     if (OP == OP_CLIP && a.skip_if_fused && a.st->fused_ok) return;
-    const int cb = (int)(blockIdx.x % (unsigned)a.ncb) * a.cb_stride;
+    const int cb = (int)(blockIdx.x % (unsigned)a.ncb);
     const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
     const int64_t ncol = a.ncol;
-    const int64_t col0 = (int64_t)cb * B;
+    // A sampling pass (cb_stride > 1) gives each wave its own 64-column
+    // segment, every cb_stride-th of the plane, so that the sample spreads
+    // evenly over x and y; the other passes take B adjacent columns per block.
+    // Either way thread tid owns column col0 + tid.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t col0 =
+        a.cb_stride > 1
+            ? (((int64_t)cb * (B / 64) + wave) * a.cb_stride - wave) * 64
+            : (int64_t)cb * B;
     const bool active = col0 + tid < ncol;
     const int nz = (int)a.nz;
     const int z0 = zc * a.zchunk;
@@ -345,8 +353,46 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             if (zb + 2 * G < ze) load_group(zb + 2 * G, ga);
             process_group(zb + G, gb);
         }
-        if (capture && fill > 0) flush();
-        if (SELCLIP && afill > 0) flush_amb();
+    }
+    if (capture) {
+        // End of the block: what the waves still hold goes to the global lists
+        // with one atomic per list for the whole block (a counter shared by
+        // the whole grid serialises its atomics, so they are kept few).
+        __shared__ unsigned wfill[2][B / 64];
+        __shared__ unsigned long long wbase[2];
+        const int lane = tid & 63;
+        if (lane == 0) {
+            wfill[0][wave] = (unsigned)fill;
+            wfill[1][wave] = (unsigned)afill;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long nk = 0, na = 0;
+            bool over = false;
+            for (int v = 0; v < B / 64; ++v) {
+                nk += wfill[0][v];
+                na += min(wfill[1][v], (unsigned)kAmbPerWave);
+                over |= wfill[1][v] > (unsigned)kAmbPerWave;
+            }
+            wbase[0] = nk ? atomicAdd(a.cap_count, nk) : 0ull;
+            wbase[1] = 0ull;
+            if (SELCLIP && (na || over))
+                wbase[1] = atomicAdd(a.amb_count, na + (over ? a.amb_capacity + 1 : 0ull));
+        }
+        __syncthreads();
+        unsigned long long bk = wbase[0], ba = wbase[1];
+        for (int v = 0; v < wave; ++v) {
+            bk += wfill[0][v];
+            ba += min(wfill[1][v], (unsigned)kAmbPerWave);
+        }
+        const int nk = (int)wfill[0][wave];
+        for (int i = lane; i < nk; i += 64)
+            if (bk + i < a.cap_capacity) a.cap_buf[bk + i] = capw[i];
+        if (SELCLIP) {
+            const int na = (int)min(wfill[1][wave], (unsigned)kAmbPerWave);
+            for (int i = lane; i < na; i += 64)
+                if (ba + i < a.amb_capacity) a.amb[ba + i] = ambw[i];
+        }
     }
 
     if (OP == OP_STD) {
@@ -374,9 +420,9 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             if (tid < off) { rc[0][tid] += rc[0][tid + off]; rc[1][tid] += rc[1][tid + off]; }
             __syncthreads();
         }
-        if (tid == 0) {
-            if (rc[0][0]) atomicAdd(&a.sel_counts[0], rc[0][0]);
-            if (rc[1][0]) atomicAdd(&a.sel_counts[1], rc[1][0]);
+        if (tid == 0) {   // per-block partials, summed by the finalize kernel
+            a.sel_part[2 * blockIdx.x] = rc[0][0];
+            a.sel_part[2 * blockIdx.x + 1] = rc[1][0];
         }
     } else if (OP == OP_HIST2) {
         __syncthreads();

@@ -115,7 +115,8 @@ struct ColArgs {
     uint32_t *cap_buf;           // OP_SELECT: captured keys
     unsigned long long *cap_count;
     unsigned long long cap_capacity;
-    unsigned long long *sel_counts;  // OP_SELECT: [selected voxels, keys below klo]
+    unsigned long long *sel_part;    // OP_SELECT / OP_SELCLIP: per block [selected voxels,
+                                     // keys below klo], 2 per block
     uint64_t *det_bits;          // OP_CLIP / OP_SELCLIP: packed detection bits out (may be null)
     int64_t wpp;                 // 64-bit words per plane of det_bits
     AmbEntry *amb;               // OP_SELCLIP: undecided voxels
@@ -167,7 +168,7 @@ hipError_t launch_finalize_std(DevState *st, const double *part_sum,
                                int k, double t, int also_sigma0, hipStream_t s);
 hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
                                 hipStream_t s);
-hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_counts,
+hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_part, int nparts,
                                   const unsigned long long *cap_count,
                                   unsigned long long cap_capacity, int k,
                                   const unsigned long long *amb_count,

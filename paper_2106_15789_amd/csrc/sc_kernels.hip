@@ -212,13 +212,30 @@ __global__ __launch_bounds__(256) void k_finalize_mad1(
 // (and nothing was dropped); otherwise the full level-1/level-2 passes run.
 // amb_count may be null: no fused clip in this pass (then fused_ok = 0 and
 // the plain clip pass runs).
-__global__ void k_finalize_select(DevState *st, const unsigned long long *sel_counts,
-                                  const unsigned long long *cap_count,
-                                  unsigned long long cap_capacity, int k,
-                                  const unsigned long long *amb_count,
-                                  unsigned long long amb_capacity) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long m = sel_counts[0], below = sel_counts[1], cin = *cap_count;
+__global__ __launch_bounds__(256) void k_finalize_select(
+    DevState *st, const unsigned long long *sel_part, int nparts,
+    const unsigned long long *cap_count, unsigned long long cap_capacity, int k,
+    const unsigned long long *amb_count, unsigned long long amb_capacity) {
+    // sum the selection pass's per-block counts (fixed order)
+    __shared__ unsigned long long rs[2][256];
+    const int tid = threadIdx.x;
+    unsigned long long c0 = 0, c1 = 0;
+    for (int b = tid; b < nparts; b += 256) {
+        c0 += sel_part[2 * b];
+        c1 += sel_part[2 * b + 1];
+    }
+    rs[0][tid] = c0;
+    rs[1][tid] = c1;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+            rs[0][tid] += rs[0][tid + off];
+            rs[1][tid] += rs[1][tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const unsigned long long m = rs[0][0], below = rs[1][0], cin = *cap_count;
     const unsigned long long bit = 1ull << (k >= 0 ? k : 63);
     st->m = m;
     st->below = 0ull;
@@ -549,12 +566,12 @@ hipError_t launch_finalize_mad1(DevState *st, const unsigned long long *hist1,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_counts,
+hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_part, int nparts,
                                   const unsigned long long *cap_count,
                                   unsigned long long cap_capacity, int k,
                                   const unsigned long long *amb_count,
                                   unsigned long long amb_capacity, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(64), 0, s, st, sel_counts,
+    hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(256), 0, s, st, sel_part, nparts,
                        cap_count, cap_capacity, k, amb_count, amb_capacity);
     return hipGetLastError();
 }

@@ -156,6 +156,26 @@ def _pairs(spatial, spectral):
     return [(float(f), int(w)) for f in spatial for w in spectral]
 
 
+def batch_specs(n: int, seed: int, xy: Tuple[int, int], z: Tuple[int, int],
+                sigma: Tuple[float, float] = (0.5, 2.0),
+                gal_per_gvox: float = 2000.0) -> List[CubeSpec]:
+    """n cubes of seeded uneven shapes: nx, ny uniform in xy, nz uniform in z
+    (inclusive), one constant noise sigma per cube uniform in `sigma`, mock
+    galaxies at the density of the 1024^3 workload (at least one per cube).
+    Shapes and sigmas come from numpy's PCG64 stream for `seed`; the voxels
+    from the cube generator with cube_id = index."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        nx, ny = (int(v) for v in rng.integers(xy[0], xy[1] + 1, size=2))
+        nz = int(rng.integers(z[0], z[1] + 1))
+        sig = float(rng.uniform(sigma[0], sigma[1]))
+        n_gal = max(1, int(round(gal_per_gvox * nx * ny * nz / float(1 << 30))))
+        out.append(CubeSpec(nx, ny, nz, seed=seed, cube_id=i, sigma_lo=sig, sigma_hi=sig,
+                            n_gal=n_gal))
+    return out
+
+
 def workload(name: str) -> Workload:
     """Named workloads (shapes and settings of the benchmark configurations)."""
     if name == "plain_64x64x128":
@@ -174,6 +194,17 @@ def workload(name: str) -> Workload:
         return Workload(
             name, [CubeSpec(256, 256, 256, seed=2, radial=True, sigma_lo=0.8,
                             sigma_hi=1.5, n_gal=31, nan_border=4)],
+            _pairs([0, 3, 6], [0, 3, 7, 15]), 3.5, "mad", "negative")
+    if name == "batch96":
+        return Workload(
+            name, batch_specs(96, seed=3, xy=(96, 512), z=(128, 1024)),
+            _pairs([0, 3, 6], [0, 3, 7, 15]), 3.5, "mad", "negative",
+            notes="96 independent cubes, spatial 96-512 px, 128-1024 channels, "
+                  "sigma 0.5-2 per cube")
+    if name == "batch_small":
+        # Same recipe at sizes the oracle runs in seconds; ragged shapes.
+        return Workload(
+            name, batch_specs(7, seed=5, xy=(17, 75), z=(24, 90)),
             _pairs([0, 3, 6], [0, 3, 7, 15]), 3.5, "mad", "negative")
     if name == "paper_360x360x1464":
         return Workload(

@@ -49,6 +49,20 @@ def test_strerror_and_null_handle_paths():
     noise = (ctypes.c_double * 1)()
     k = (sc.Kernel * 1)()
     assert lib.sofia_sc_run(None, None, 1, 1, 1, k, 1, 3.0, 0, 0, None, noise) == sc.EINVAL
+    cubes = (sc.Cube * 1)()
+    assert lib.sofia_sc_run_batch(None, cubes, 1, k, 1, 3.0, 0, 0, noise, None,
+                                  None) == sc.EINVAL
+
+
+def test_cube_descriptor_layout_matches_header():
+    """sofia_sc_cube: pointer, three int64 dimensions, pointer (40 bytes)."""
+    assert ctypes.sizeof(sc.Cube) == 40
+    assert [f for f, _ in sc.Cube._fields_] == ["cube", "nx", "ny", "nz", "mask"]
+    text = open(sc.HEADER).read()
+    body = text[text.index("typedef struct {\n    const float *cube;"):]
+    body = body[:body.index("} sofia_sc_cube;")]
+    assert re.findall(r"\b(cube|nx|ny|nz|mask)\b[,;]", body) == ["cube", "nx", "ny", "nz",
+                                                                   "mask"]
 
 
 def test_default_options():
