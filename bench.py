@@ -8,6 +8,10 @@ sigma varies 0.8-1.5 across the field, a 13-px NaN border (5 % of voxels) and
 2000 mock galaxies; kernels spatial {0, 3, 6} px x spectral {0, 3, 7, 15} ch;
 MAD noise on negative voxels; threshold 3.5; replacement n = 2.
 
+--workload large_2048x2048x4096: one 2048 x 2048 x 4096 cube (64 GiB, sigma
+0.8-1.5 across the field, 20000 galaxies), kernels spatial {0, 3, 6, 9} x
+spectral {0, 3, 7, 15, 31}, generated slab by slab straight into HBM.
+
 --workload batch96: 96 cubes of seeded uneven shapes (spatial 96-512 px,
 128-1024 channels, sigma 0.5-2 per cube, same kernels and settings); one step
 runs all of them, by default as one batched run (a single graph launch),
@@ -65,6 +69,26 @@ def read_traffic(family: str, workload: str):
         return None
 
 
+def upload(spec, torch, synth):
+    """Generate a cube slab by slab (about 1 GiB each) straight into HBM."""
+    x = torch.empty(spec.shape, dtype=torch.float32, device="cuda")
+    slab = max(1, (1 << 28) // (spec.nx * spec.ny))
+    for z0 in range(0, spec.nz, slab):
+        z1 = min(spec.nz, z0 + slab)
+        x[z0:z1].copy_(torch.from_numpy(synth.generate(spec, z0=z0, z1=z1)))
+        if spec.nz > 8 * slab and (z0 // slab) % 16 == 15:
+            print(f"[bench] planes 0-{z1 - 1} generated", file=sys.stderr, flush=True)
+    return x
+
+
+def count_set(m, torch) -> int:
+    """Nonzero voxels of a uint8 mask, a slab at a time (a whole-cube reduction
+    would materialise a wider copy)."""
+    slab = max(1, (1 << 28) // (m.shape[1] * m.shape[2]))
+    return sum(int(torch.count_nonzero(m[z0:z0 + slab]).item())
+               for z0 in range(0, m.shape[0], slab))
+
+
 def cpu_baseline(wl, planes: int):
     """The FP64 oracle on planes [0, planes) of the same workload."""
     import oracle
@@ -87,13 +111,15 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain_1024cube")
-    ap.add_argument("--cpu-planes", type=int, default=64)
+    ap.add_argument("--cpu-planes", type=int, default=0,
+                    help="planes of the oracle's sample (0: sized to the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
                     help="cube storage inside the run (16-bit: noise-scaled copy)")
-    ap.add_argument("--batch-mode", default="graph", choices=["graph", "loop"],
-                    help="many-cube workloads: one sofia_sc_run_batch graph launch per "
-                         "step, or one sofia_sc_run call per cube")
+    ap.add_argument("--batch-mode", default="auto", choices=["auto", "graph", "loop"],
+                    help="graph: one sofia_sc_run_batch graph launch per step (all "
+                         "cubes); loop: one sofia_sc_run call per cube; auto: graph for "
+                         "many-cube workloads, loop otherwise")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the cube (4 B/voxel "
                          "read + write), the calibration kernel for HBM counters")
@@ -115,7 +141,7 @@ def main():
           f"{sum(c.n_vox for c in wl.cubes)} voxels", file=sys.stderr, flush=True)
     xs = []
     for i, c in enumerate(wl.cubes):
-        xs.append(torch.from_numpy(synth.generate(c)).cuda())
+        xs.append(upload(c, torch, synth))
         if batch and (i + 1) % 16 == 0:
             print(f"[bench] {i + 1} cubes generated", file=sys.stderr, flush=True)
     masks = [torch.empty(x.shape, dtype=torch.uint8, device=x.device) for x in xs]
@@ -124,8 +150,10 @@ def main():
     h = sc.SofiaSC(0)
     stream = torch.cuda.current_stream()
 
+    graph = args.batch_mode == "graph" or (batch and args.batch_mode == "auto")
+
     def step():
-        if batch and args.batch_mode == "graph":
+        if graph:
             _, noise, s0 = h.run_batch(xs, wl.kernels, wl.threshold, wl.noise_mode,
                                        wl.flux_range, wl.replacement, masks=masks,
                                        stream=stream, storage=args.storage)
@@ -152,7 +180,8 @@ def main():
     dt = time.perf_counter() - t0
     h.profile(False)
     stats = h.profile_read()
-    print("[bench] timed steps done", file=sys.stderr, flush=True)
+    print(f"[bench] timed steps done: {dt * 1e3 / args.steps:.1f} ms/step", file=sys.stderr,
+          flush=True)
 
     n_vox = sum(c.n_vox for c in wl.cubes)
     value = n_vox * args.steps / dt
@@ -183,7 +212,7 @@ def main():
             "kernels": [list(k) for k in wl.kernels], "noise": wl.noise_mode,
             "flux_range": wl.flux_range, "threshold": wl.threshold,
             "replacement": wl.replacement, "storage": args.storage,
-            "batch_mode": args.batch_mode if batch else None,
+            "batch_mode": "graph" if graph else "loop",
         },
         "roofline": {
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved,
@@ -198,14 +227,18 @@ def main():
                        for s in stats if s["bytes"] > 0 and s["total_ms"] > 0},
         "noise": [float(v) for v in noise],
         "sigma0": float(sigma0),
-        "mask_voxels": int(sum(int(m.sum().item()) for m in masks)),
+        "mask_voxels": sum(count_set(m, torch) for m in masks),
         "kernel_src_sha": kernel_source_sha(),
     }
     h.close()
     del x, mask, xs, masks
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_planes, spec.nz))
+        # the sample is sized to about the same oracle work for every workload:
+        # 64 planes of 1024^2 with 12 kernels
+        planes = args.cpu_planes or max(8, -(-64 * (1 << 20) * 12 //
+                                              (spec.nx * spec.ny * len(wl.kernels))))
+        result["cpu_baseline"] = cpu_baseline(wl, min(planes, spec.nz))
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)

@@ -72,6 +72,7 @@ enum {
 #define SOFIA_SC_MAX_HALO 16        /* n * r of the spatial cascade */
 #define SOFIA_SC_MAX_WIDTH 63       /* spectral boxcar width */
 #define SOFIA_SC_MAX_CUBES 4096     /* cubes of one batch */
+#define SOFIA_SC_MAX_PLANE (1LL << 28)  /* nx * ny */
 
 typedef struct {
     uint32_t struct_size;   /* = sizeof(sofia_sc_options) */
@@ -107,7 +108,7 @@ void sofia_sc_destroy(sofia_sc *h);
  *  mask       device, uint8 [nz][ny][nx], fully overwritten with 0/1.
  *  noise      host, double[n_kernels]: the noise of each smoothed cube.
  * Uses the default options. EINVAL: NULL pointer, a dimension < 1,
- * nx*ny*nz > 2^40, bad kernel (FWHM < 0 or non-finite, halo above
+ * nx*ny*nz > 2^40, nx*ny > SOFIA_SC_MAX_PLANE, bad kernel (FWHM < 0 or non-finite, halo above
  * SOFIA_SC_MAX_HALO, even or too large width), bad threshold or enum. */
 int sofia_sc_run(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                  int64_t nz, const sofia_sc_kernel *kernels, int32_t n_kernels,

@@ -204,8 +204,9 @@ int check_dims(sofia_sc *h, int64_t nx, int64_t ny, int64_t nz) {
         return fail(h, SOFIA_SC_EINVAL, "cube dimensions must be >= 1");
     const double n = (double)nx * (double)ny * (double)nz;
     if (n > 1099511627776.0) return fail(h, SOFIA_SC_EINVAL, "cube larger than 2^40 voxels");
-    if (nx * ny > 0x7fffffffLL * 256LL)
-        return fail(h, SOFIA_SC_EINVAL, "plane too large");
+    // the spatial kernel addresses a plane with 32-bit byte offsets
+    if (nx * ny > SOFIA_SC_MAX_PLANE)
+        return fail(h, SOFIA_SC_EINVAL, "plane larger than 2^28 voxels");
     return SOFIA_SC_OK;
 }
 

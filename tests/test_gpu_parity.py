@@ -225,6 +225,23 @@ def test_bad_arguments_raise_einval(h):
         assert e.value.code == sc.EINVAL
 
 
+def test_plane_limit_is_einval_before_any_device_work(h):
+    """nx * ny above SOFIA_SC_MAX_PLANE is refused by the argument checks,
+    which run before any allocation or launch (the tiny buffer is never
+    touched)."""
+    x = dev(np.zeros(16, np.float32))
+    m = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    noise = (ctypes.c_double * 1)()
+    opt = sc.Options()
+    h.lib.sofia_sc_default_options(ctypes.byref(opt))
+    k = sc._kernels([(0.0, 0)])
+    rc = h.lib.sofia_sc_run_ex(h.h, x.data_ptr(), 16385, 16385, 1, k, 1, 3.0, 0, 0,
+                               m.data_ptr(), noise, ctypes.byref(opt), None)
+    assert rc == sc.EINVAL
+    assert "plane" in h.lib.sofia_sc_last_error(h.h).decode()
+    assert math.isnan(noise[0])
+
+
 def test_handle_reuse_across_cube_sizes():
     """Workspace sized by an earlier, smaller cube: later, larger runs on the
     same handle (spectral-only, then spatial with replacement) must size
