@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // s * range > 0 (s < 0 for range -1, s > 0 for range +1).
     const bool all_range = a.range == 0;
     const double rsgn = (double)a.range;
-    auto in_range = [&](double s) { return all_range || s * rsgn > 0.0; };
+    auto in_range = [&](double s) { return all_range | (s * rsgn > 0.0); };
     ColAcc acc{0.0, 0ull};
     const float *src = SRC == SRC_X ? a.x : a.p;
 
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     uint32_t klo = 1, khi = 0;
     if (capture) { klo = a.st->klo; khi = a.st->khi; }
     unsigned n_sel = 0, n_below = 0;
-    uint32_t *capw = (uint32_t *)(hist + kHistWords) + (tid >> 6) * kCapPerWave(G);
+    uint32_t *capw = (uint32_t *)(hist + kHistWords) + (tid >> 6) * kCapStride(G);
     int fill = 0;   // entries in this wave's buffer (same in every lane)
     auto flush = [&]() {
         __builtin_amdgcn_wave_barrier();
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // the whole pass). Entries beyond the buffer are dropped and the count is
     // pushed past the list's capacity, which sends the pass to the full clip.
     const size_t amb_off =
-        ((size_t)((const char *)(capw + (B / 64 - (tid >> 6)) * kCapPerWave(G)) -
+        ((size_t)((const char *)(capw + (B / 64 - (tid >> 6)) * kCapStride(G)) -
                   (const char *)dyn_lds) + 15) & ~(size_t)15;
     AmbEntry *ambw = (AmbEntry *)((char *)dyn_lds + amb_off) + (tid >> 6) * kAmbPerWave;
     int afill = 0;   // entries in this wave's buffer (same in every lane)
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         uint8_t out;
         if (a.out_user) out = (uint8_t)((wb & kDet) | det);
         else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
-        (a.mask_out + po)[tid] = out;
+        buf_st_u8(out, plane_rsrc(a.mask_out + po), (uint32_t)tid, 0u);
         if (a.det_bits) {
             // the wave's 64 columns start at a multiple of 64: one word
             const uint64_t bits = __ballot((out & kDet) != 0);
@@ -172,33 +172,34 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // caller (no 64-bit multiply per plane).
     auto consume = [&](int64_t po, int64_t zw, double s, bool blank, uint8_t wb) {
         if (OP == OP_STD) {
-            if (!blank && in_range(s)) { acc.sum += s * s; acc.cnt += 1; }
+            const bool sel = !blank & in_range(s);
+            acc.sum += sel ? s * s : 0.0;
+            acc.cnt += sel ? 1ull : 0ull;
         } else if (OP == OP_HIST1) {
-            if (!blank && in_range(s)) {
+            if (!blank & in_range(s)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
             }
         } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
-            const bool sel = !blank && in_range(s);
+            // predicates combine bitwise: no branch per voxel
+            const bool sel = !blank & in_range(s);
             const uint32_t key = __float_as_uint(fabsf((float)s));
             n_sel += sel ? 1u : 0u;
-            n_below += (sel && key < klo) ? 1u : 0u;
-            const bool want = sel && key >= klo && key <= khi;
+            n_below += (sel & (key < klo)) ? 1u : 0u;
+            const bool want = sel & (key >= klo) & (key <= khi);
             const unsigned long long bal = __ballot(want);
-            if (bal) {
-                if (want) {
-                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    capw[fill + below] = key;
-                }
-                fill += __popcll(bal);
-            }
+            // every lane writes: a capturing lane to its place in the list,
+            // the others to a slot of their own past the list's end
+            const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            capw[want ? fill + below : kCapPerWave(G) + (tid & 63)] = key;
+            fill += __popcll(bal);
             if (SELCLIP) {
                 // clip now unless |s| lies in (thr_lo, thr_hi], where the
                 // decision waits for the exact threshold
                 const double as = fabs(s);
-                const bool det = !blank && as > Thi;
-                const bool amb = !blank && as > Tlo && !det;
+                const bool det = !blank & (as > Thi);
+                const bool amb = !blank & (as > Tlo) & !det;
                 clip_out(po, zw, blank, wb, det ? kDet : 0);
                 const unsigned long long ab = __ballot(amb);
                 if (ab) {
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_HIST2) {
-            if (!blank && in_range(s)) {
+            if (!blank & in_range(s)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 const uint32_t k1 = key >> kL1Shift;
                 const uint32_t lo = key & (kL2Bins - 1);
@@ -226,16 +227,16 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_CLIP) {
-            clip_out(po, zw, blank, wb, (!blank && fabs(s) > T) ? kDet : 0);
+            clip_out(po, zw, blank, wb, (!blank & (fabs(s) > T)) ? kDet : 0);
         } else {  // OP_WRITE
-            (a.s_out + po)[tid] = blank ? NAN : (float)s;
+            buf_st_f32(blank ? NAN : (float)s, plane_rsrc(a.s_out + po), 4u * (uint32_t)tid, 0u);
         }
     };
 
     // Spectral input of a raw voxel: blanked -> 0, detected -> +-n sigma_0.
     auto raw_value = [&](float xv, uint8_t wb) -> float {
         if (!isfinite(xv)) return 0.f;
-        if (repl && (wb & kDet)) return copysignf(rv, xv);
+        if (repl & ((wb & kDet) != 0)) return copysignf(rv, xv);
         return xv;
     };
 
@@ -264,13 +265,15 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             g.q[j] = 0;
             g.b[j] = 0;
             if (zi < ze && zi >= 0 && zi < nz) {
-                if (Q16) g.q[j] = (a.xq + off)[tid];
-                else g.v[j] = (src + off)[tid];
-                if (SRC == SRC_X && HASWM) g.b[j] = (a.wm_in + off)[tid];
+                if (Q16) g.q[j] = buf_u16(plane_rsrc(a.xq + off), 2u * (uint32_t)tid, 0u);
+                else g.v[j] = buf_f32(plane_rsrc(src + off), 4u * (uint32_t)tid, 0u);
+                if (SRC == SRC_X && HASWM)
+                    g.b[j] = buf_u8(plane_rsrc(a.wm_in + off), (uint32_t)tid, 0u);
             }
             if (SRC == SRC_P) {
                 const int zo = zi - h;
-                if (zi < ze && zo >= z0) g.b[j] = (a.wm_in + (off - hoff))[tid];
+                if (zi < ze && zo >= z0)
+                    g.b[j] = buf_u8(plane_rsrc(a.wm_in + (off - hoff)), (uint32_t)tid, 0u);
             }
         }
     };
@@ -449,7 +452,7 @@ inline size_t column_lds_bytes(int src, int op, bool spectral, int w) {
     if (op == OP_SELECT || op == OP_SELCLIP) {
         const int tw = spectral ? ring_template_width(w) : 1;
         const int group = tw >= 3 ? tw * ((8 + tw - 1) / tw) : 8;
-        b += (size_t)(kColThreads / 64) * kCapPerWave(group) * sizeof(uint32_t);
+        b += (size_t)(kColThreads / 64) * kCapStride(group) * sizeof(uint32_t);
     }
     if (op == OP_SELCLIP) b += 16 + (size_t)(kColThreads / 64) * kAmbPerWave * sizeof(AmbEntry);
     if (op == OP_HIST2) b += (size_t)2 * kL2Coarse * sizeof(unsigned);

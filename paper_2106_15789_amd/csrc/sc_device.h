@@ -21,6 +21,32 @@ __device__ __forceinline__ float load_raw(const float *x, const uint16_t *xq, in
     return type == ST_F16 ? f16_bits_to_float(q) : bf16_bits_to_float(q);
 }
 
+// Buffer access: the resource (a uniform base pointer) lives in scalar
+// registers, a uniform byte offset goes in the scalar offset and the lane's
+// byte offset in the vector offset, so no lane computes a 64-bit address.
+// Offsets from one base stay below 2^32 (callers rebase per plane).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xffffffff,
+                                             0x00020000);
+}
+__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ uint16_t buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                           uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ uint8_t buf_u8(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return (uint8_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st_u8(uint8_t v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                          uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)voff, (int)soff, 0);
+}
+
 __device__ __forceinline__ bool in_flux_range(double s, int range) {
     return range < 0 ? (s < 0.0) : (range > 0 ? (s > 0.0) : true);
 }

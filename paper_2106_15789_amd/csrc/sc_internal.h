@@ -69,6 +69,9 @@ struct AmbEntry {
 // of the wave may capture on every plane of a group).
 constexpr int kCapFlushAt = 256;
 constexpr int kCapPerWave(int group) { return kCapFlushAt + 64 * group; }
+// Per-wave stride of that buffer: 64 more slots, one per lane, where lanes
+// that capture nothing write (so the append needs no branch).
+constexpr int kCapStride(int group) { return kCapPerWave(group) + 64; }
 // Undecided voxels of the fused clip, per wave in LDS: flushed after a group
 // of planes once more than kAmbFlushAt are held. A group of noise-like data
 // adds well under one; a group that overflows the buffer sends the pass to

@@ -29,25 +29,6 @@
 
 namespace sc {
 
-// Buffer access to one plane: the resource (plane base) is uniform, the
-// row offset goes in the scalar offset and the lane's column in the vector
-// offset, so no lane computes a 64-bit address. Offsets stay below 2^32
-// (a plane of the largest supported cube is far smaller).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xffffffff,
-                                             0x00020000);
-}
-__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-__device__ __forceinline__ uint16_t buf_u16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
-}
-__device__ __forceinline__ void buf_st_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                           uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
-}
-
 // Lane i receives lane i-K's value (shr) or lane i+K's (shl); lanes without
 // a source receive 0.
 template <int K>
