@@ -176,9 +176,11 @@ hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_pa
                                   unsigned long long cap_capacity, int k,
                                   const unsigned long long *amb_count,
                                   unsigned long long amb_capacity, hipStream_t s);
+// Walks over the captured keys run on `blocks` workgroups (grid-stride).
 hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
                              const unsigned long long *cap_count,
-                             unsigned long long *hist1, hipStream_t s);
+                             unsigned long long *hist1, int blocks,
+                             hipStream_t s);
 hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_s,
                                    double t, hipStream_t s);
 // After sigma_k is exact: decide the voxels the fused selection pass left
@@ -189,10 +191,12 @@ hipError_t launch_clip_fixup(const DevState *st, const AmbEntry *amb,
                              uint64_t *det_bits, int64_t ncol, int64_t wpp, hipStream_t s);
 hipError_t launch_capture_coarse(const DevState *st, const uint32_t *cap_buf,
                                  const unsigned long long *cap_count,
-                                 unsigned long long *hist2c, hipStream_t s);
+                                 unsigned long long *hist2c, int blocks,
+                             hipStream_t s);
 hipError_t launch_capture_fine(const DevState *st, const uint32_t *cap_buf,
                                const unsigned long long *cap_count,
-                               unsigned long long *hist2, hipStream_t s);
+                               unsigned long long *hist2, int blocks,
+                             hipStream_t s);
 hipError_t launch_finalize_mad2a(DevState *st, const unsigned long long *hist2c,
                                  hipStream_t s);
 hipError_t launch_finalize_mad2b(DevState *st, const unsigned long long *hist2, int k,

@@ -587,8 +587,8 @@ hipError_t launch_clip_fixup(const DevState *st, const AmbEntry *amb,
 
 hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
                              const unsigned long long *cap_count,
-                             unsigned long long *hist1, hipStream_t s) {
-    hipLaunchKernelGGL(k_capture_l1, dim3(512), dim3(256), 0, s, st, cap_buf, cap_count,
+                             unsigned long long *hist1, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_capture_l1, dim3(blocks), dim3(256), 0, s, st, cap_buf, cap_count,
                        hist1);
     return hipGetLastError();
 }
@@ -601,16 +601,16 @@ hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_
 
 hipError_t launch_capture_coarse(const DevState *st, const uint32_t *cap_buf,
                                  const unsigned long long *cap_count,
-                                 unsigned long long *hist2c, hipStream_t s) {
-    hipLaunchKernelGGL(k_capture_coarse, dim3(1024), dim3(256), 0, s, st, cap_buf,
+                                 unsigned long long *hist2c, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_capture_coarse, dim3(blocks), dim3(256), 0, s, st, cap_buf,
                        cap_count, hist2c);
     return hipGetLastError();
 }
 
 hipError_t launch_capture_fine(const DevState *st, const uint32_t *cap_buf,
                                const unsigned long long *cap_count,
-                               unsigned long long *hist2, hipStream_t s) {
-    hipLaunchKernelGGL(k_capture_fine, dim3(1024), dim3(256), 0, s, st, cap_buf,
+                               unsigned long long *hist2, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_capture_fine, dim3(blocks), dim3(256), 0, s, st, cap_buf,
                        cap_count, hist2);
     return hipGetLastError();
 }
