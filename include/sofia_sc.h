@@ -155,6 +155,34 @@ int sofia_sc_run_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
                        int32_t noise_mode, int32_t flux_range, double *noise,
                        const sofia_sc_options *opt, double *sigma0);
 
+/* Launch shapes of batched runs. */
+typedef struct {
+    int32_t lanes;          /* workspaces whose launch chains run side by side:
+                               4, 8 or 16 (default 8) */
+    int32_t col_blocks;     /* column passes: blocks a launch aims at, by
+                               splitting z into chunks of >= 64 planes: 3072,
+                               6144 or 12288 (default 6144) */
+    int32_t strip_rows;     /* spatial pass: most rows per chunk of a strip:
+                               64, 128 or 256 (default 256) */
+    int32_t reserved;
+    double ms;              /* time of one batched run with these shapes as
+                               measured by the tuning (NaN if not tuned) */
+} sofia_sc_batch_tuning;
+
+/* Autotune the launch shapes of sofia_sc_run_batch on a batch: times
+ * candidate shapes one parameter at a time (lanes, then col_blocks, then
+ * strip_rows; each candidate's graph is captured, launched once untimed and
+ * then timed over two launches) and keeps the fastest in the handle; every
+ * later sofia_sc_run_batch call of the handle uses it. Results do not depend
+ * on the shapes except for the last bits of std noise (summation order of
+ * the per-block partials). Arguments as sofia_sc_run_batch; the masks are
+ * written with the batch's result. best (host, may be NULL) receives the
+ * chosen shapes. Returns as sofia_sc_run_batch. */
+int sofia_sc_tune_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
+                        const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
+                        int32_t noise_mode, int32_t flux_range, const sofia_sc_options *opt,
+                        sofia_sc_batch_tuning *best);
+
 /* One S+C iteration with the previous state given (Sect. 4.2 and 6.2.4):
  * smooth the cube after replacing the voxels set in mask_in by
  * copysign(replacement * sigma0, x) (skipped when replacement < 0), measure

@@ -30,7 +30,8 @@ RANGE = {"negative": -1, "all": 0, "positive": 1}
 # Every symbol include/sofia_sc.h declares.
 EXPORTS = [
     "sofia_sc_default_options", "sofia_sc_create", "sofia_sc_destroy",
-    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch", "sofia_sc_step", "sofia_sc_step_ex",
+    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch", "sofia_sc_tune_batch",
+    "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
@@ -92,6 +93,12 @@ class Options(ctypes.Structure):
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("col_blocks", ctypes.c_int32),
+                ("strip_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 class Cube(ctypes.Structure):
     _fields_ = [("cube", ctypes.c_void_p), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("nz", ctypes.c_int64), ("mask", ctypes.c_void_p)]
@@ -130,6 +137,9 @@ def load():
     lib.sofia_sc_run_batch.argtypes = [vp, ctypes.POINTER(Cube), i32, ctypes.POINTER(Kernel),
                                        i32, dbl, i32, i32, ctypes.POINTER(dbl),
                                        ctypes.POINTER(Options), ctypes.POINTER(dbl)]
+    lib.sofia_sc_tune_batch.argtypes = [vp, ctypes.POINTER(Cube), i32, ctypes.POINTER(Kernel),
+                                        i32, dbl, i32, i32, ctypes.POINTER(Options),
+                                        ctypes.POINTER(BatchTuning)]
     lib.sofia_sc_step.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, dbl,
                                   dbl, vp, vp, ctypes.POINTER(dbl), vp]
     lib.sofia_sc_step_ex.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, vp, vp,
@@ -145,6 +155,7 @@ def load():
     lib.sofia_sc_strerror.argtypes = [ctypes.c_int]
     lib.sofia_sc_strerror.restype = ctypes.c_char_p
     for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch",
+                 "sofia_sc_tune_batch",
                  "sofia_sc_step",
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
@@ -258,13 +269,7 @@ class SofiaSC:
             self._raise(rc, "sofia_sc_run_ex")
         return mask, np.array(noise[:], dtype=np.float64), s0.value
 
-    def run_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
-                  flux_range: str = "negative", replacement: float = 2.0, masks=None,
-                  stream=None, allow_nostat: bool = False, storage: str = "f32",
-                  sigma0: float = float("nan")):
-        """Independent S+C runs of many cubes in one graph launch.
-
-        Returns (list of mask tensors, noise[n_cubes, K] ndarray, sigma0[n_cubes])."""
+    def _batch_args(self, cubes, masks):
         import torch
         n = len(cubes)
         if masks is None:
@@ -277,15 +282,47 @@ class SofiaSC:
             _check_like(m, c, torch.uint8, "mask")
             desc[i].cube, desc[i].nx, desc[i].ny, desc[i].nz = c.data_ptr(), nx, ny, nz
             desc[i].mask = m.data_ptr()
-        K = len(kernels)
-        noise = (ctypes.c_double * (n * K))()
-        s0 = (ctypes.c_double * n)()
+        return desc, masks
+
+    def _options(self, replacement, sigma0, storage, stream):
         opt = Options()
         self.lib.sofia_sc_default_options(ctypes.byref(opt))
         opt.replacement = float(replacement)
         opt.sigma0 = float(sigma0)
         opt.storage = STORAGE[storage]
         opt.stream = _stream_ptr(stream)
+        return opt
+
+    def tune_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
+                   flux_range: str = "negative", replacement: float = 2.0, masks=None,
+                   stream=None, storage: str = "f32", sigma0: float = float("nan")):
+        """Autotune the batch launch shapes on this batch; returns the chosen
+        {lanes, col_blocks, strip_rows, ms}, kept for later batches."""
+        desc, masks = self._batch_args(cubes, masks)
+        opt = self._options(replacement, sigma0, storage, stream)
+        best = BatchTuning()
+        rc = self.lib.sofia_sc_tune_batch(self.h, desc, len(cubes), _kernels(kernels),
+                                          len(kernels), float(threshold), NOISE[noise_mode],
+                                          RANGE[flux_range], ctypes.byref(opt),
+                                          ctypes.byref(best))
+        if rc != OK and rc != ENOSTAT:
+            self._raise(rc, "sofia_sc_tune_batch")
+        return {"lanes": best.lanes, "col_blocks": best.col_blocks,
+                "strip_rows": best.strip_rows, "ms": best.ms}
+
+    def run_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
+                  flux_range: str = "negative", replacement: float = 2.0, masks=None,
+                  stream=None, allow_nostat: bool = False, storage: str = "f32",
+                  sigma0: float = float("nan")):
+        """Independent S+C runs of many cubes in one graph launch.
+
+        Returns (list of mask tensors, noise[n_cubes, K] ndarray, sigma0[n_cubes])."""
+        n = len(cubes)
+        desc, masks = self._batch_args(cubes, masks)
+        K = len(kernels)
+        noise = (ctypes.c_double * (n * K))()
+        s0 = (ctypes.c_double * n)()
+        opt = self._options(replacement, sigma0, storage, stream)
         rc = self.lib.sofia_sc_run_batch(self.h, desc, n, _kernels(kernels), K,
                                          float(threshold), NOISE[noise_mode],
                                          RANGE[flux_range], noise, ctypes.byref(opt), s0)

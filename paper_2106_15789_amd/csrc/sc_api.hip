@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -70,13 +71,15 @@ struct Work {
     size_t det_cap = 0;              // in words
     AmbEntry *amb = nullptr;         // undecided voxels of the fused clip
     size_t amb_cap = 0;
+    Shapes sh;                       // launch shapes of the runs on this workspace
 };
 
 // Lanes of a batch: cubes are spread over this many workspaces whose
 // launch chains run side by side in the graph. Measured on a batch of 96
 // uneven cubes: 2, 4, 8 and 16 lanes give 14.0, 16.3, 19.7 and 19.9e9
 // voxels/s; 8 keeps nearly all of the gain at half the workspace of 16.
-constexpr int kBatchLanes = 8;
+constexpr int kDefaultLanes = 8;
+constexpr int kBatchLanes = 16;      // most lanes a tuning may choose
 
 // Everything a captured batch graph depends on; an identical call replays
 // the instantiated graph.
@@ -86,6 +89,7 @@ struct BatchKey {
     double t = 0, repl = 0;
     uint64_t sigma0_bits = 0;
     int mode = 0, range = 0, storage = 0;
+    int lanes = 0, col_blocks = 0, strip_rows = 0;
     uint64_t work_gen = 0;
 };
 
@@ -114,6 +118,7 @@ struct sofia_sc {
     double graph_bytes = 0;          // algorithmic bytes of the captured launches
     bool capturing = false;          // launches are being captured: no events
     double capture_bytes = 0;
+    sofia_sc_batch_tuning tune = {kDefaultLanes, 6144, 256, 0, NAN};
 };
 
 namespace {
@@ -229,10 +234,9 @@ struct ColGrid {
     int blocks() const { return ncb * nzc; }
 };
 
-ColGrid col_grid(int64_t ncol, int64_t nz) {
+ColGrid col_grid(int64_t ncol, int64_t nz, int target) {
     ColGrid g;
     g.ncb = (int)((ncol + kColThreads - 1) / kColThreads);
-    const int64_t target = 6144;
     int64_t nzc = (target + g.ncb - 1) / g.ncb;
     const int64_t max_nzc = std::max<int64_t>(1, nz / 64);
     nzc = std::max<int64_t>(1, std::min(nzc, max_nzc));
@@ -409,7 +413,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     if ((spatial || spec) && !has_wm)
         return fail(h, SOFIA_SC_EINVAL, "internal: smoothing without working mask");
 
-    const ColGrid g = col_grid(d.ncol, d.nz);
+    const ColGrid g = col_grid(d.ncol, d.nz, w.sh.col_blocks);
     if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
         return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
     if (spatial) {
@@ -425,12 +429,14 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         }
         a.p = w.p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
-        spatial_strips(a, j.pl.n_iter, j.pl.radius);
+        spatial_strips(a, j.pl.n_iter, j.pl.radius, w.sh.strip_rows);
         if (a.tiles > 0x7fffffffLL)
             return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
         a.repl_n = j.repl_n;
         a.st = w.st;
-        const double bytes = N * (bx + (j.repl_active ? 1.0 : 0.0) + 4.0);
+        // raw cube in, smoothed plane out, and with replacement the packed
+        // detection bits (one bit per voxel)
+        const double bytes = N * (bx + (j.repl_active ? 0.125 : 0.0) + 4.0);
         rc = launch(h, s, F_SPATIAL, bytes, N, [&] {
             return launch_spatial(j.pl.n_iter, j.pl.radius, j.xtype, j.repl_active, a, s);
         });
@@ -687,7 +693,7 @@ int check_options(sofia_sc *h, const sofia_sc_options *opt) {
 // Workspace a run of this cube and kernel list needs.
 int ensure_for(sofia_sc *h, Work &w, const RunSpec &r, bool *moved = nullptr) {
     const bool sp = r.any_spatial();
-    const ColGrid g = col_grid(r.d.ncol, r.d.nz);
+    const ColGrid g = col_grid(r.d.ncol, r.d.nz, w.sh.col_blocks);
     return ensure_work(h, w, r.d.N, sp, (size_t)g.blocks(),
                        sp ? r.d.nz * det_words_per_plane(r.d.ncol) : 0,
                        r.storage != SOFIA_SC_STORE_F32, moved);
@@ -811,7 +817,8 @@ bool same_key(const BatchKey &a, const BatchKey &b) {
             return false;
     return a.t == b.t && a.repl == b.repl && a.sigma0_bits == b.sigma0_bits &&
            a.mode == b.mode && a.range == b.range && a.storage == b.storage &&
-           a.work_gen == b.work_gen;
+           a.lanes == b.lanes && a.col_blocks == b.col_blocks &&
+           a.strip_rows == b.strip_rows && a.work_gen == b.work_gen;
 }
 
 void drop_graph(sofia_sc *h) {
@@ -938,7 +945,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
 
     // Longest first onto the least loaded lane.
-    const int L = std::min<int>(kBatchLanes, n);
+    const int L = std::min<int>(h->tune.lanes, n);
     std::vector<int> order((size_t)n);
     for (int i = 0; i < n; ++i) order[(size_t)i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -951,9 +958,11 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         load[l] += (double)runs[(size_t)i].d.N;
     }
     bool moved = false;
-    for (int l = 0; l < L; ++l)
+    for (int l = 0; l < L; ++l) {
+        h->lanes[l].sh = Shapes{h->tune.col_blocks, h->tune.strip_rows};
         for (int i : lane_cubes[(size_t)l])
             if ((rc = ensure_for(h, h->lanes[l], runs[(size_t)i], &moved))) return rc;
+    }
     if ((rc = ensure_batch_infra(h, (size_t)n, &moved))) return rc;
     if (moved) {
         ++h->work_gen;
@@ -969,6 +978,9 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     key.mode = mode;
     key.range = range;
     key.storage = opt->storage;
+    key.lanes = L;
+    key.col_blocks = h->tune.col_blocks;
+    key.strip_rows = h->tune.strip_rows;
     key.work_gen = h->work_gen;
     if (!h->gvalid || !same_key(key, h->gkey)) {
         drop_graph(h);
@@ -989,6 +1001,61 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         if (ri) rc = ri;
     }
     if (rc == SOFIA_SC_ENOSTAT) h->err = "no finite voxel in the flux range for some kernel of some cube";
+    return rc;
+}
+
+// Autotuning of the batch launch shapes: coordinate search, each candidate
+// timed as the faster of two graph launches after an untimed one (which
+// also captures its graph).
+int tune_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
+              const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
+              int32_t range, const sofia_sc_options *opt, sofia_sc_batch_tuning *best) {
+    if (!h) return SOFIA_SC_EINVAL;
+    if (n < 1 || n > SOFIA_SC_MAX_CUBES || K < 1 || K > SOFIA_SC_MAX_KERNELS)
+        return fail(h, SOFIA_SC_EINVAL, "number of cubes must be 1..4096 and of kernels 1..64");
+    std::vector<double> noise((size_t)n * K);
+    const sofia_sc_batch_tuning start = h->tune;
+    auto time_it = [&](const sofia_sc_batch_tuning &c, double *ms) -> int {
+        h->tune = c;
+        int rc = batch_impl(h, cubes, n, kernels, K, t, mode, range, noise.data(), opt, nullptr);
+        if (rc != SOFIA_SC_OK && rc != SOFIA_SC_ENOSTAT) return rc;
+        double bestms = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = batch_impl(h, cubes, n, kernels, K, t, mode, range, noise.data(), opt, nullptr);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (rc != SOFIA_SC_OK && rc != SOFIA_SC_ENOSTAT) return rc;
+            bestms = std::min(bestms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        *ms = bestms;
+        return SOFIA_SC_OK;
+    };
+    sofia_sc_batch_tuning cur{kDefaultLanes, 6144, 256, 0, NAN};
+    int rc = time_it(cur, &cur.ms);
+    if (rc) { h->tune = start; return rc; }
+    const int lanes[] = {4, 16}, blocks[] = {3072, 12288}, rows[] = {128, 64};
+    for (int v : lanes) {
+        sofia_sc_batch_tuning c = cur;
+        c.lanes = v;
+        if ((rc = time_it(c, &c.ms))) { h->tune = start; return rc; }
+        if (c.ms < cur.ms) cur = c;
+    }
+    for (int v : blocks) {
+        sofia_sc_batch_tuning c = cur;
+        c.col_blocks = v;
+        if ((rc = time_it(c, &c.ms))) { h->tune = start; return rc; }
+        if (c.ms < cur.ms) cur = c;
+    }
+    for (int v : rows) {
+        sofia_sc_batch_tuning c = cur;
+        c.strip_rows = v;
+        if ((rc = time_it(c, &c.ms))) { h->tune = start; return rc; }
+        if (c.ms < cur.ms) cur = c;
+    }
+    h->tune = cur;
+    if (best) *best = cur;
+    // leave the masks with the chosen shapes' result
+    rc = batch_impl(h, cubes, n, kernels, K, t, mode, range, noise.data(), opt, nullptr);
     return rc;
 }
 
@@ -1094,6 +1161,14 @@ int sofia_sc_run_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
                       noise, opt, sigma0);
 }
 
+int sofia_sc_tune_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
+                        const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
+                        int32_t noise_mode, int32_t flux_range, const sofia_sc_options *opt,
+                        sofia_sc_batch_tuning *best) {
+    return tune_impl(h, cubes, n_cubes, kernels, n_kernels, threshold, noise_mode, flux_range,
+                     opt, best);
+}
+
 static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                          int64_t nz, sofia_sc_kernel kernel, double threshold,
                          int32_t mode, int32_t range, double replacement,
@@ -1127,7 +1202,7 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
-    const ColGrid g = col_grid(d.ncol, d.nz);
+    const ColGrid g = col_grid(d.ncol, d.nz, h->w.sh.col_blocks);
     if ((rc = ensure_state(h))) return rc;
     if ((rc = ensure_work(h, h->w, d.N, pl.spatial(), (size_t)g.blocks(),
                           pl.spatial() ? d.nz * det_words_per_plane(d.ncol) : 0, q16)))

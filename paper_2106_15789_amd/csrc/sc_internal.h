@@ -218,11 +218,19 @@ size_t column_lds_bytes(int src, int op, bool spectral, int w);
 constexpr int kStripCols = 128;
 constexpr int kStripWaves = 4;
 
+// Launch shapes of a run: the column kernel's grid aims at col_blocks
+// blocks (z split into chunks of at least 64 planes); the spatial kernel's
+// row chunks hold at most strip_rows rows.
+struct Shapes {
+    int col_blocks = 6144;
+    int strip_rows = 256;
+};
+
 // Strip geometry of the spatial kernel for a cube of width nx and halo H:
 // strips of kStripCols - 2H output columns, up to kStripWaves adjacent
 // strips per workgroup (spread evenly over the groups a row needs), rows in
-// chunks.
-inline void spatial_strips(StripArgs &a, int n_iter, int radius) {
+// chunks of at most rows_max (>= 32).
+inline void spatial_strips(StripArgs &a, int n_iter, int radius, int rows_max) {
     const int64_t H = (int64_t)n_iter * radius, W = kStripCols - 2 * H;
     a.nstrips = (int32_t)((a.nx + W - 1) / W);
     const int64_t groups = (a.nstrips + kStripWaves - 1) / kStripWaves;
@@ -230,7 +238,7 @@ inline void spatial_strips(StripArgs &a, int n_iter, int radius) {
     a.ngroups = (int32_t)((a.nstrips + a.wpb - 1) / a.wpb);
     // rows per chunk: long chunks keep the y halo small; shorter ones when
     // the cube is too small to give the chip enough waves otherwise
-    int64_t rows = 256;
+    int64_t rows = rows_max;
     while (rows > 32 && a.nstrips * ((a.ny + rows - 1) / rows) * a.nz < 16384) rows /= 2;
     if (rows > a.ny) rows = a.ny;
     a.rows = (int32_t)rows;

@@ -54,6 +54,17 @@ def test_strerror_and_null_handle_paths():
                                   None) == sc.EINVAL
 
 
+def test_batch_tuning_layout_matches_header():
+    """sofia_sc_batch_tuning: four int32 fields, then a double (24 bytes)."""
+    assert ctypes.sizeof(sc.BatchTuning) == 24
+    assert [f for f, _ in sc.BatchTuning._fields_] == ["lanes", "col_blocks", "strip_rows",
+                                                       "reserved", "ms"]
+    lib = sc.load()
+    cubes = (sc.Cube * 1)()
+    k = (sc.Kernel * 1)()
+    assert lib.sofia_sc_tune_batch(None, cubes, 1, k, 1, 3.0, 0, 0, None, None) == sc.EINVAL
+
+
 def test_cube_descriptor_layout_matches_header():
     """sofia_sc_cube: pointer, three int64 dimensions, pointer (40 bytes)."""
     assert ctypes.sizeof(sc.Cube) == 40
