@@ -25,6 +25,8 @@
 // it by a per-column select.
 #pragma once
 
+#include <type_traits>
+
 #include "sc_device.h"
 
 namespace sc {
@@ -161,6 +163,8 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
     const int64_t gx = span0 + lx;
     const bool xin0 = gx >= 0 && gx < nx, xin1 = gx + 1 >= 0 && gx + 1 < nx;
     const uint32_t vo0 = clamp_col(gx) * 4u, vo1 = clamp_col(gx + 1) * 4u;   // P offsets
+    // the whole strip (positions 0 .. kStripCols - 1) inside the plane in x
+    const bool x_interior = span0 + wave * W >= 0 && span0 + wave * W + kStripCols - 1 < nx;
     const bool out0 = 2 * lane >= H && 2 * lane < kStripCols - H && xin0;
     const bool out1 = 2 * lane + 1 >= H && 2 * lane + 1 < kStripCols - H && xin1;
     const float rv = RP ? (float)(a.repl_n * a.st->sigma0) : 0.f;
@@ -222,7 +226,11 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
             for (int j = 0; j < Q; ++j) ring[c][p][j] = 0.0;
         }
 
-    auto compute = [&](int buf, int blk) {
+    // EDGE = false: this wave's strip lies inside the plane in x and every
+    // row and pass of the block inside it in y, so no zeroing is needed (the
+    // selects and multiplies by 1 it skips are exact no-ops there).
+    auto compute = [&](int buf, int blk, auto edge_c) {
+        constexpr bool EDGE = decltype(edge_c)::value;
         const int base = blk * U;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -240,15 +248,19 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
                 if (bits & 1u) c0 = copysignf(rv, vx);
                 if (bits & 2u) c1 = copysignf(rv, vy);
             }
-            const bool yin = yi >= 0 && yi < ny;   // uniform
-            c0 = (xin0 && yin) ? c0 : 0.f;
-            c1 = (xin1 && yin) ? c1 : 0.f;
+            if (EDGE) {
+                const bool yin = yi >= 0 && yi < ny;   // uniform
+                c0 = (xin0 && yin) ? c0 : 0.f;
+                c1 = (xin1 && yin) ? c1 : 0.f;
+            }
 
 #pragma unroll
             for (int p = 0; p < NIT; ++p) {
                 box_pairs<R>(c0, c1);
-                c0 = xin0 ? c0 : 0.f;               // no-op away from the x edges
-                c1 = xin1 ? c1 : 0.f;
+                if (EDGE) {
+                    c0 = xin0 ? c0 : 0.f;           // no-op away from the x edges
+                    c1 = xin1 ? c1 : 0.f;
+                }
             }
 
             // y passes; ring slot j % Q held the input of Q steps ago
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
                     const double old = ring[c][p][sl];
                     ring[c][p][sl] = d[c];
                     S[c][p] = (S[c][p] + d[c]) - old;
-                    d[c] = (p + 1 < NIT) ? S[c][p] * keep : S[c][p];
+                    d[c] = (EDGE && p + 1 < NIT) ? S[c][p] * keep : S[c][p];
                 }
             }
             const int yo = yi - H;
@@ -294,7 +306,13 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
     if (nblk > 1) stage_load(1);
     for (int blk = 0; blk < nblk; ++blk) {
         const int buf = blk & 1;
-        if (active) compute(buf, blk);
+        if (active) {
+            const int yb0 = y_first + blk * U;
+            if (x_interior && yb0 - (NIT - 1) * R >= 0 && yb0 + U - 1 < ny)
+                compute(buf, blk, std::integral_constant<bool, false>{});
+            else
+                compute(buf, blk, std::integral_constant<bool, true>{});
+        }
         if (blk + 1 < nblk) {
             stage_store(buf ^ 1);
             if (blk + 2 < nblk) stage_load(blk + 2);
