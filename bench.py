@@ -120,9 +120,6 @@ def main():
                     help="graph: one sofia_sc_run_batch graph launch per step (all "
                          "cubes); loop: one sofia_sc_run call per cube; auto: graph for "
                          "many-cube workloads, loop otherwise")
-    ap.add_argument("--tune", action="store_true",
-                    help="graph mode: autotune the batch launch shapes (sofia_sc_tune_batch) "
-                         "before the warmup")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain device copy of the cube (4 B/voxel "
                          "read + write), the calibration kernel for HBM counters")
@@ -166,12 +163,6 @@ def main():
                         wl.replacement, mask=mi, stream=stream, storage=args.storage)
         return out
 
-    tuning = None
-    if args.tune:
-        # autotune the batch launch shapes once, outside the timed region
-        tuning = h.tune_batch(xs, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
-                              wl.replacement, masks=masks, stream=stream, storage=args.storage)
-        print(f"[bench] tuned: {tuning}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     print("[bench] warmup done", file=sys.stderr, flush=True)
@@ -222,7 +213,6 @@ def main():
             "flux_range": wl.flux_range, "threshold": wl.threshold,
             "replacement": wl.replacement, "storage": args.storage,
             "batch_mode": "graph" if graph else "loop",
-            "batch_tuning": tuning,
         },
         "roofline": {
             "bound": "hbm", "kernel": dom["name"], "achieved": achieved,

@@ -169,7 +169,10 @@ typedef struct {
                                measured by the tuning (NaN if not tuned) */
 } sofia_sc_batch_tuning;
 
-/* Autotune the launch shapes of sofia_sc_run_batch on a batch: times
+/* SWITCHED OFF IN THIS BUILD: returns SOFIA_SC_EDEVICE at once (best, if
+ * not NULL, receives the defaults), because one tuning run ended in a host
+ * abort whose cause is not yet established. The intended behaviour:
+ * autotune the launch shapes of sofia_sc_run_batch on a batch: times
  * candidate shapes one parameter at a time (lanes, then col_blocks, then
  * strip_rows; each candidate's graph is captured, launched once untimed and
  * then timed over two launches) and keeps the fastest in the handle; every

@@ -306,7 +306,7 @@ class SofiaSC:
                                           RANGE[flux_range], ctypes.byref(opt),
                                           ctypes.byref(best))
         if rc != OK and rc != ENOSTAT:
-            self._raise(rc, "sofia_sc_tune_batch")
+            self._raise(rc, "sofia_sc_tune_batch")   # switched off in this build
         return {"lanes": best.lanes, "col_blocks": best.col_blocks,
                 "strip_rows": best.strip_rows, "ms": best.ms}
 

@@ -134,7 +134,7 @@ constexpr size_t kOffAmbCount = kOffCapCount + 2;
 constexpr size_t kHistWords = kOffAmbCount + 2;
 // 64-column segments visited by the sampling pass: every 17th (a stride
 // coprime to the usual row lengths in segments spreads the sample over x and
-// y).
+// y); planes of more than 17 x 1024 segments use a wider odd stride.
 constexpr int kSampleStride = 17;
 
 unsigned long long *hist1_of(const Work &w) { return w.hist; }
@@ -524,9 +524,13 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
             // The sample touches 1/17 of the columns: split z finer so the
             // launch still has a few blocks per CU.
             ColArgs cs = c;
-            cs.cb_stride = kSampleStride;
             const int64_t nseg = (d.ncol + 63) / 64;   // 64-column segments
-            const int64_t sampled = (nseg + kSampleStride - 1) / kSampleStride;
+            // every 17th segment; on large planes an odd stride that still
+            // samples about 1024 segments per plane
+            const int64_t stride =
+                nseg >= (int64_t)kSampleStride * 1024 ? (nseg / 1024) | 1 : kSampleStride;
+            cs.cb_stride = (int)stride;
+            const int64_t sampled = (nseg + stride - 1) / stride;
             cs.ncb = (int)((sampled + kColThreads / 64 - 1) / (kColThreads / 64));
             cs.hist1 = hist_s_of(w);
             int nzc = (int)std::min<int64_t>((2048 + cs.ncb - 1) / cs.ncb,
@@ -1007,7 +1011,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
 // Autotuning of the batch launch shapes: coordinate search, each candidate
 // timed as the faster of two graph launches after an untimed one (which
 // also captures its graph).
-int tune_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
+[[maybe_unused]] int tune_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
               const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
               int32_t range, const sofia_sc_options *opt, sofia_sc_batch_tuning *best) {
     if (!h) return SOFIA_SC_EINVAL;
@@ -1165,8 +1169,13 @@ int sofia_sc_tune_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes
                         const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
                         int32_t noise_mode, int32_t flux_range, const sofia_sc_options *opt,
                         sofia_sc_batch_tuning *best) {
-    return tune_impl(h, cubes, n_cubes, kernels, n_kernels, threshold, noise_mode, flux_range,
-                     opt, best);
+    // Switched off: one tuning run ended in a host-side abort whose cause is
+    // not established, so the search (tune_impl) is not reachable until it is.
+    (void)cubes; (void)n_cubes; (void)kernels; (void)n_kernels; (void)threshold;
+    (void)noise_mode; (void)flux_range; (void)opt;
+    if (!h) return SOFIA_SC_EINVAL;
+    if (best) *best = sofia_sc_batch_tuning{kDefaultLanes, 6144, 256, 0, NAN};
+    return fail(h, SOFIA_SC_EDEVICE, "batch autotuning is switched off in this build");
 }
 
 static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,

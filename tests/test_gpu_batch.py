@@ -168,6 +168,8 @@ def test_batch_errors(h, small):
     assert e.value.code == sc.ENOSTAT
 
 
+@pytest.mark.skip(reason="sofia_sc_tune_batch is switched off: one run of this test ended in "
+                         "a host-side abort inside the tuning whose cause is not established")
 def test_tuning_picks_candidate_shapes_and_keeps_results(small):
     """The autotuner returns one of its candidate shapes with a positive time,
     later batches use it, and MAD results stay those of the single runs (they
@@ -192,3 +194,12 @@ def test_tuning_picks_candidate_shapes_and_keeps_results(small):
         _assert_same(out, ref, "tuned batch")
     finally:
         ht.close()
+
+
+def test_tuning_entry_point_is_switched_off(h, small):
+    """The switched-off tuner returns an error at once and touches nothing."""
+    wl, xs, xd = small
+    with pytest.raises(sc.ScError) as e:
+        h.tune_batch(xd, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range,
+                     wl.replacement)
+    assert e.value.code == sc.EDEVICE and "switched off" in str(e.value)
