@@ -307,11 +307,17 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
     for (int blk = 0; blk < nblk; ++blk) {
         const int buf = blk & 1;
         if (active) {
-            const int yb0 = y_first + blk * U;
-            if (x_interior && yb0 - (NIT - 1) * R >= 0 && yb0 + U - 1 < ny)
-                compute(buf, blk, std::integral_constant<bool, false>{});
-            else
+            // The interior copy of the row loop costs registers: only the
+            // narrow cascades (halo <= 6) keep their waves per SIMD with it.
+            if constexpr (H <= 6) {
+                const int yb0 = y_first + blk * U;
+                if (x_interior && yb0 - (NIT - 1) * R >= 0 && yb0 + U - 1 < ny)
+                    compute(buf, blk, std::integral_constant<bool, false>{});
+                else
+                    compute(buf, blk, std::integral_constant<bool, true>{});
+            } else {
                 compute(buf, blk, std::integral_constant<bool, true>{});
+            }
         }
         if (blk + 1 < nblk) {
             stage_store(buf ^ 1);
