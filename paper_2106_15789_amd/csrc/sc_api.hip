@@ -134,7 +134,7 @@ constexpr size_t kOffAmbCount = kOffCapCount + 2;
 constexpr size_t kHistWords = kOffAmbCount + 2;
 // 64-column segments visited by the sampling pass: every 17th (a stride
 // coprime to the usual row lengths in segments spreads the sample over x and
-// y); planes of more than 17 x 1024 segments use a wider odd stride.
+// y); planes of more than 17 x 512 segments use a wider odd stride.
 constexpr int kSampleStride = 17;
 
 unsigned long long *hist1_of(const Work &w) { return w.hist; }
@@ -526,9 +526,9 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
             ColArgs cs = c;
             const int64_t nseg = (d.ncol + 63) / 64;   // 64-column segments
             // every 17th segment; on large planes an odd stride that still
-            // samples about 1024 segments per plane
+            // samples about 512 segments per plane
             const int64_t stride =
-                nseg >= (int64_t)kSampleStride * 1024 ? (nseg / 1024) | 1 : kSampleStride;
+                nseg >= (int64_t)kSampleStride * 512 ? (nseg / 512) | 1 : kSampleStride;
             cs.cb_stride = (int)stride;
             const int64_t sampled = (nseg + stride - 1) / stride;
             cs.ncb = (int)((sampled + kColThreads / 64 - 1) / (kColThreads / 64));
