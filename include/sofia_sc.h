@@ -141,7 +141,10 @@ typedef struct {
  * the whole batch is captured once into a HIP graph and launched as one
  * graph on opt->stream. An identical later call (same cube and mask
  * pointers, shapes, kernels and settings) launches the same graph again
- * without capturing. Inputs must be ready on opt->stream.
+ * without capturing. Inputs must be ready on opt->stream. The cached graph
+ * refers to the cube and mask pointers of the call that captured it; it is
+ * destroyed by the next batch call with other arguments and by
+ * sofia_sc_destroy, and is never launched again with freed buffers.
  *  cubes    host array of n_cubes (1..SOFIA_SC_MAX_CUBES) descriptors; the
  *           masks must be distinct and must not overlap any cube.
  *  noise    host, double[n_cubes][n_kernels] (cube-major).

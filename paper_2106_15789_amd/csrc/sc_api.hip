@@ -245,11 +245,24 @@ ColGrid col_grid(int64_t ncol, int64_t nz, int target) {
     return g;
 }
 
+// Destroy the cached batch graph (it is captured again when next needed).
+void drop_graph(sofia_sc *h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gvalid = false;
+}
+
 // Grow a device buffer to at least `need` elements (contents are not kept).
+// moved != null marks a batch lane's buffer: the cached batch graph may hold
+// it in its kernel arguments, so the graph is destroyed before the buffer is
+// freed, never after.
 template <typename T>
 int grow(sofia_sc *h, T *&ptr, size_t &cap, size_t need, const char *what, bool *moved) {
     if (need <= cap) return SOFIA_SC_OK;
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        if (moved) drop_graph(h);
+        (void)hipFree(ptr);
+    }
     ptr = nullptr;
     cap = 0;
     const hipError_t e = hipMalloc(&ptr, need * sizeof(T));
@@ -825,12 +838,6 @@ bool same_key(const BatchKey &a, const BatchKey &b) {
            a.strip_rows == b.strip_rows && a.work_gen == b.work_gen;
 }
 
-void drop_graph(sofia_sc *h) {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-    h->gvalid = false;
-}
-
 // Lane streams, fork/join events and the per-cube device states.
 int ensure_batch_infra(sofia_sc *h, size_t n, bool *moved) {
     hipError_t e;
@@ -846,6 +853,7 @@ int ensure_batch_infra(sofia_sc *h, size_t n, bool *moved) {
         (e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(h, e, "fork event");
     if (n > h->bst_cap) {
+        drop_graph(h);   // the graph holds the per-cube state pointers
         if (h->bst) (void)hipFree(h->bst);
         if (h->bst_host) (void)hipHostFree(h->bst_host);
         h->bst = nullptr;
