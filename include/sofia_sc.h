@@ -82,12 +82,15 @@ typedef struct {
                                replacement and 16-bit scaling: NaN = measure
                                it (default); finite > 0 = use as given */
     int32_t storage;        /* SOFIA_SC_STORE_*; default F32 */
-    int32_t reserved;       /* must be 0 */
+    int32_t keep_input_mask;  /* 0: the mask is fully overwritten with 0/1
+                               (default); 1: mask[i] |= 1 where the run
+                               detects, every other byte keeps its value (the
+                               caller's mask takes no part in the run) */
     void *stream;           /* hipStream_t to run on; NULL = null stream */
 } sofia_sc_options;
 
 /* Fill opt with defaults (replacement 2.0, sigma0 measured, F32 storage,
- * null stream). */
+ * mask overwritten, null stream). */
 void sofia_sc_default_options(sofia_sc_options *opt);
 
 /* Create a handle on a HIP device. The handle owns all device workspace
@@ -118,8 +121,8 @@ int sofia_sc_run(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
 /* sofia_sc_run with options. sigma0 (host, may be NULL) receives the noise
  * of the unsmoothed input that replacement and 16-bit scaling use (NaN when
  * neither needs it). Noise values are always in the cube's own units.
- * EINVAL also for opt == NULL, a struct_size mismatch, an unknown storage or
- * a given sigma0 that is not finite and > 0. */
+ * EINVAL also for opt == NULL, a struct_size mismatch, an unknown storage,
+ * keep_input_mask not 0 or 1, or a given sigma0 that is not finite and > 0. */
 int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     int64_t nz, const sofia_sc_kernel *kernels,
                     int32_t n_kernels, double threshold, int32_t noise_mode,
@@ -209,7 +212,8 @@ int sofia_sc_step(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
  * cube is stored as a run stores it, scaled by opt->sigma0, which must then
  * be given (finite and > 0); the noise is returned in the cube's own units.
  * EINVAL as sofia_sc_step, and for opt == NULL, a struct_size mismatch, an
- * unknown storage or a nonzero reserved field. */
+ * unknown storage or a nonzero keep_input_mask (mask_in / mask_out give a
+ * step its state explicitly). */
 int sofia_sc_step_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                      int64_t nz, sofia_sc_kernel kernel, double threshold,
                      int32_t noise_mode, int32_t flux_range, const uint8_t *mask_in,

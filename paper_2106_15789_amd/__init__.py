@@ -86,7 +86,7 @@ class Options(ctypes.Structure):
                 ("replacement", ctypes.c_double),
                 ("sigma0", ctypes.c_double),
                 ("storage", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("keep_input_mask", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -244,8 +244,11 @@ class SofiaSC:
     def run(self, cube, kernels, threshold: float, noise_mode: str = "mad",
             flux_range: str = "negative", replacement: float = 2.0, mask=None,
             stream=None, allow_nostat: bool = False, storage: str = "f32",
-            sigma0: float = float("nan")):
-        """Whole S+C run. Returns (mask uint8 tensor, noise[K] ndarray, sigma0)."""
+            sigma0: float = float("nan"), keep_input_mask: bool = False):
+        """Whole S+C run. Returns (mask uint8 tensor, noise[K] ndarray, sigma0).
+
+        keep_input_mask: OR the detections into the given mask instead of
+        overwriting it."""
         import torch
         nx, ny, nz = _check_cube(cube)
         _check_like(mask, cube, torch.uint8, "mask")
@@ -259,6 +262,7 @@ class SofiaSC:
         opt.replacement = float(replacement)
         opt.sigma0 = float(sigma0)
         opt.storage = STORAGE[storage]
+        opt.keep_input_mask = 1 if keep_input_mask else 0
         opt.stream = _stream_ptr(stream)
         rc = self.lib.sofia_sc_run_ex(self.h, cube.data_ptr(), nx, ny, nz,
                                       _kernels(kernels), K, float(threshold),
@@ -284,12 +288,13 @@ class SofiaSC:
             desc[i].mask = m.data_ptr()
         return desc, masks
 
-    def _options(self, replacement, sigma0, storage, stream):
+    def _options(self, replacement, sigma0, storage, stream, keep_input_mask=False):
         opt = Options()
         self.lib.sofia_sc_default_options(ctypes.byref(opt))
         opt.replacement = float(replacement)
         opt.sigma0 = float(sigma0)
         opt.storage = STORAGE[storage]
+        opt.keep_input_mask = 1 if keep_input_mask else 0
         opt.stream = _stream_ptr(stream)
         return opt
 
@@ -313,7 +318,7 @@ class SofiaSC:
     def run_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
                   flux_range: str = "negative", replacement: float = 2.0, masks=None,
                   stream=None, allow_nostat: bool = False, storage: str = "f32",
-                  sigma0: float = float("nan")):
+                  sigma0: float = float("nan"), keep_input_mask: bool = False):
         """Independent S+C runs of many cubes in one graph launch.
 
         Returns (list of mask tensors, noise[n_cubes, K] ndarray, sigma0[n_cubes])."""
@@ -322,7 +327,7 @@ class SofiaSC:
         K = len(kernels)
         noise = (ctypes.c_double * (n * K))()
         s0 = (ctypes.c_double * n)()
-        opt = self._options(replacement, sigma0, storage, stream)
+        opt = self._options(replacement, sigma0, storage, stream, keep_input_mask)
         rc = self.lib.sofia_sc_run_batch(self.h, desc, n, _kernels(kernels), K,
                                          float(threshold), NOISE[noise_mode],
                                          RANGE[flux_range], noise, ctypes.byref(opt), s0)

@@ -21,13 +21,13 @@ namespace {
 enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
-    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_COUNT
+    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
-    "clip_fixup", "batch_graph"};
+    "clip_fixup", "batch_graph", "mask_or"};
 
 struct LaunchRec {
     int fam;
@@ -685,6 +685,7 @@ struct RunSpec {
     double repl;          // < 0: no replacement
     double sigma0;        // NaN: measure
     int storage;
+    bool keep;            // OR the detections into the caller's mask
     bool any_spatial() const {
         for (int k = 0; k < K; ++k)
             if (plans[k].spatial()) return true;
@@ -701,7 +702,8 @@ int check_options(sofia_sc *h, const sofia_sc_options *opt) {
     if (storage != SOFIA_SC_STORE_F32 && storage != SOFIA_SC_STORE_F16 &&
         storage != SOFIA_SC_STORE_BF16)
         return fail(h, SOFIA_SC_EINVAL, "unknown storage");
-    if (opt->reserved != 0) return fail(h, SOFIA_SC_EINVAL, "reserved option field must be 0");
+    if (opt->keep_input_mask != 0 && opt->keep_input_mask != 1)
+        return fail(h, SOFIA_SC_EINVAL, "keep_input_mask must be 0 or 1");
     if (!std::isnan(opt->sigma0) && !(std::isfinite(opt->sigma0) && opt->sigma0 > 0.0))
         return fail(h, SOFIA_SC_EINVAL, "sigma0 must be NaN (measure) or finite and > 0");
     return SOFIA_SC_OK;
@@ -758,11 +760,16 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
         rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(w.st, s); });
         if (rc) return rc;
     }
+    uint8_t *final_wm = nullptr;
     for (int k = 0; k < K; ++k) {
         const bool last = k == K - 1;
-        uint8_t *out = last ? r.mask : (have_wm ? w.wm[1 - cur] : w.wm[cur]);
+        // the last kernel clips straight into the caller's 0/1 mask, unless
+        // the detections are to be ORed into it afterwards
+        const bool to_user = last && !r.keep;
+        uint8_t *out = to_user ? r.mask : (have_wm ? w.wm[1 - cur] : w.wm[cur]);
+        if (last) final_wm = out;
         PairJob j{r.cube, q16 ? w.xq : nullptr, xtype, d, r.plans[k], k, repl_on && k >= 1,
-                  r.repl, r.mode, r.range, r.t, have_wm ? w.wm[cur] : nullptr, out, last,
+                  r.repl, r.mode, r.range, r.t, have_wm ? w.wm[cur] : nullptr, out, to_user,
                   k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
                   any_spatial, !last && r.plans[k + 1].spatial() && repl_on};
         if ((rc = run_pair(h, s, w, j))) return rc;
@@ -770,6 +777,12 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
             if (have_wm) cur = 1 - cur;
             have_wm = true;
         }
+    }
+    if (r.keep) {
+        rc = launch(h, s, F_MASK_OR, 3.0 * d.N, (double)d.N, [&] {
+            return launch_or_mask(final_wm, r.mask, d.N, s);
+        });
+        if (rc) return rc;
     }
     return SOFIA_SC_OK;
 }
@@ -810,7 +823,8 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)opt->stream;
     const RunSpec r{cube, Dims{nx, ny, nz, nx * ny, nx * ny * nz}, plans.data(), K, t, mode,
-                    range, mask, opt->replacement, opt->sigma0, opt->storage};
+                    range, mask, opt->replacement, opt->sigma0, opt->storage,
+                    opt->keep_input_mask != 0};
     if ((rc = ensure_state(h))) return rc;
     if ((rc = ensure_for(h, h->w, r))) return rc;
     if ((rc = enqueue_run(h, s, h->w, r))) return rc;
@@ -947,7 +961,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         }
         runs.push_back(RunSpec{c.cube, Dims{c.nx, c.ny, c.nz, c.nx * c.ny, c.nx * c.ny * c.nz},
                                plans.data(), K, t, mode, range, c.mask, opt->replacement,
-                               opt->sigma0, opt->storage});
+                               opt->sigma0, opt->storage, opt->keep_input_mask != 0});
         masks.push_back(c.mask);
     }
     std::sort(masks.begin(), masks.end());
@@ -1082,7 +1096,7 @@ void sofia_sc_default_options(sofia_sc_options *opt) {
     opt->replacement = 2.0;
     opt->sigma0 = NAN;
     opt->storage = SOFIA_SC_STORE_F32;
-    opt->reserved = 0;
+    opt->keep_input_mask = 0;
     opt->stream = nullptr;
 }
 
@@ -1281,7 +1295,8 @@ int sofia_sc_step_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     if (noise) *noise = NAN;
     if (!opt || opt->struct_size != sizeof(sofia_sc_options))
         return fail(h, SOFIA_SC_EINVAL, "options missing or of another size");
-    if (opt->reserved != 0) return fail(h, SOFIA_SC_EINVAL, "reserved option field must be 0");
+    if (opt->keep_input_mask != 0)
+        return fail(h, SOFIA_SC_EINVAL, "keep_input_mask must be 0 for a single step");
     return single_kernel(h, cube, nx, ny, nz, kernel, threshold, noise_mode, flux_range,
                          opt->replacement, opt->sigma0, mask_in, mask_out, noise, nullptr,
                          opt->storage, opt->stream);

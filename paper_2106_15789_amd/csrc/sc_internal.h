@@ -154,6 +154,8 @@ struct StripArgs {
 hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
                             int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
+// mask[i] |= 1 where wm[i] holds a detection.
+hipError_t launch_or_mask(const uint8_t *wm, uint8_t *mask, int64_t n, hipStream_t s);
 // Packed detection bits of a working mask (detected and not blanked); word
 // w of plane z holds columns 64w .. 64w+63 of that plane, bit b = column
 // 64w + b.

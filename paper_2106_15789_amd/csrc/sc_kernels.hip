@@ -480,6 +480,19 @@ static int grid_for(int64_t n, int threads, int cap) {
     return (int)g;
 }
 
+// mask[i] |= 1 wherever the working mask holds a detection (keep_input_mask).
+__global__ __launch_bounds__(256) void k_or_mask(const uint8_t *__restrict__ wm,
+                                                 uint8_t *__restrict__ mask, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (wm[i] & kDet) mask[i] = (uint8_t)(mask[i] | 1u);
+}
+
+hipError_t launch_or_mask(const uint8_t *wm, uint8_t *mask, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_or_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, wm, mask, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
                             int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_init_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,

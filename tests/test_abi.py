@@ -81,6 +81,7 @@ def test_default_options():
     sc.load().sofia_sc_default_options(ctypes.byref(opt))
     assert opt.struct_size == ctypes.sizeof(sc.Options)
     assert opt.replacement == 2.0
+    assert opt.keep_input_mask == 0
     assert not opt.stream
 
 

@@ -225,6 +225,41 @@ def test_bad_arguments_raise_einval(h):
         assert e.value.code == sc.EINVAL
 
 
+def test_keep_input_mask_ors_detections_into_the_callers_mask(h):
+    """keep_input_mask = 1: the run's detections are ORed into the given
+    mask (mask |= 1 where detected), other bytes keep their values; the run
+    itself does not depend on the given mask. Also for batches."""
+    x = cfg2_like(110, 90, 70, seed=46, n_gal=5)
+    xd = dev(x)
+    kernels = [(0.0, 0), (3.0, 7), (6.0, 3)]
+    ref, noise_ref, _ = h.run(xd, kernels, 3.5, "mad", "negative")
+    r = host(ref)
+    rng = np.random.default_rng(5)
+    prior = rng.choice(np.array([0, 1, 2, 6], np.uint8), size=x.shape, p=[0.7, 0.1, 0.1, 0.1])
+    m = dev(prior)
+    out, noise, _ = h.run(xd, kernels, 3.5, "mad", "negative", mask=m, keep_input_mask=True)
+    np.testing.assert_array_equal(host(out), prior | r)
+    np.testing.assert_array_equal(noise, noise_ref)
+    # batch: two cubes, each ORed into its own prior mask
+    y = cfg2_like(64, 50, 40, seed=47, n_gal=2)
+    yd = dev(y)
+    ref_y, _, _ = h.run(yd, kernels, 3.5, "mad", "negative")
+    prior_y = rng.choice(np.array([0, 1], np.uint8), size=y.shape)
+    masks = [dev(prior), dev(prior_y)]
+    outs, _, _ = h.run_batch([xd, yd], kernels, 3.5, "mad", "negative", masks=masks,
+                             keep_input_mask=True)
+    np.testing.assert_array_equal(host(outs[0]), prior | r)
+    np.testing.assert_array_equal(host(outs[1]), prior_y | host(ref_y))
+    # values other than 0 / 1 are refused
+    opt = sc.Options()
+    h.lib.sofia_sc_default_options(ctypes.byref(opt))
+    opt.keep_input_mask = 2
+    nz = (ctypes.c_double * 3)()
+    rc = h.lib.sofia_sc_run_ex(h.h, xd.data_ptr(), 110, 90, 70, sc._kernels(kernels), 3, 3.5,
+                               1, -1, m.data_ptr(), nz, ctypes.byref(opt), None)
+    assert rc == sc.EINVAL
+
+
 def test_plane_limit_is_einval_before_any_device_work(h):
     """nx * ny above SOFIA_SC_MAX_PLANE is refused by the argument checks,
     which run before any allocation or launch (the tiny buffer is never
@@ -317,7 +352,7 @@ def test_step_ex_f32_equals_step_and_checks_options(h):
     noise = ctypes.c_double()
     out = torch.empty(xd.shape, dtype=torch.uint8, device=xd.device)
     k = sc.Kernel(3.0, 3)
-    for field, val in [("struct_size", 8), ("storage", 7), ("reserved", 1)]:
+    for field, val in [("struct_size", 8), ("storage", 7), ("keep_input_mask", 1)]:
         bad = sc.Options.from_buffer_copy(opt)
         setattr(bad, field, val)
         rc = h.lib.sofia_sc_step_ex(h.h, xd.data_ptr(), 90, 70, 60, k, 3.5, 1, -1, None,
