@@ -93,6 +93,30 @@ def test_smooth_matches_oracle(h, kernel):
     assert err < 6e-6
 
 
+# Cascades with halo n r <= 6 take a separate row loop in strips that lie
+# inside the plane; planes several strips wide exercise it (and its edges).
+INTERIOR_KERNELS = [(3.0, 0), (4.0, 3), (5.0, 7), (6.0, 0), (2.0, 3), (4.5, 15)]
+
+
+@pytest.mark.parametrize("kernel", INTERIOR_KERNELS)
+def test_smooth_wide_planes_interior_path(h, kernel):
+    n_iter, r = sc.plan(kernel[0])
+    assert n_iter * r <= 6
+    x = cfg2_like(620, 90, 24, seed=33, n_gal=3, border=2)
+    rng = np.random.default_rng(2)
+    x[rng.random(x.shape) < 0.002] = np.nan
+    mask = (rng.random(x.shape) < 0.01).astype(np.uint8)
+    s_ref = oracle.smooth(x, kernel[0], kernel[1], mask, 2.0, 0.9)
+    s_gpu = host(h.smooth(dev(x), kernel, replacement=2.0, sigma0=0.9,
+                          mask_in=dev(mask))).astype(np.float64)
+    np.testing.assert_array_equal(np.isnan(s_gpu), np.isnan(s_ref))
+    fin = np.isfinite(s_ref)
+    scale = math.sqrt(np.mean(s_ref[fin] ** 2))
+    err = np.abs(s_gpu[fin] - s_ref[fin]).max() / scale
+    say(f"wide smooth {kernel} (n={n_iter}, r={r}): max |ds| / rms(s) = {err:.3g}")
+    assert err < 6e-6
+
+
 # --------------------------------------------------------- end-to-end runs
 
 def test_run_plain_64x64x128(h):
