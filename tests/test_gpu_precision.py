@@ -113,6 +113,8 @@ def _oracle_chain(xq, kernels, t, mode, rng_, repl, sigma0):
 CASES = [
     ("plain_64x64x128", None),
     ("cfg2_like", [(float(f), w) for f in (0, 3, 6) for w in (0, 3, 7, 15)]),
+    # planes several strips wide: the 16-bit loads of the interior row loop
+    ("wide_620x90x40", [(0.0, 0), (3.0, 3), (4.0, 0), (6.0, 7), (5.0, 15)]),
 ]
 
 
@@ -121,6 +123,10 @@ def _cube(name):
         wl = synth.workload(name)
         return (synth.generate(wl.cubes[0]), wl.kernels, wl.threshold, wl.noise_mode,
                 wl.flux_range)
+    if name == "wide_620x90x40":
+        spec = synth.CubeSpec(620, 90, 40, seed=62, radial=True, sigma_lo=0.8, sigma_hi=1.5,
+                              n_gal=4, nan_border=2)
+        return synth.generate(spec), CASES[2][1], 3.5, "mad", "negative"
     spec = synth.CubeSpec(150, 130, 120, seed=61, radial=True, sigma_lo=0.8, sigma_hi=1.5,
                           n_gal=8, nan_border=3)
     return synth.generate(spec), CASES[1][1], 3.5, "mad", "negative"
