@@ -47,6 +47,11 @@ MUTANTS = {
                     "fwhm / std::sqrt(2.0 * std::log(2.0))"),
     "union_dropped": ("if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);",
                       "if (false) std::memcpy(mask_out, mask_prev, (size_t)N);"),
+    # the boundary band excuses mask differences in every parity test
+    "band_too_wide": ("kBandWidth = 1e-5;", "kBandWidth = 1e-2;"),
+    "band_too_narrow": ("kBandWidth = 1e-5;", "kBandWidth = 1e-6;"),
+    "band_absolute_units": ("std::fabs(std::fabs(s) / (*sigma_k) - t) <= kBandWidth",
+                            "std::fabs(std::fabs(s) - T) <= kBandWidth"),
 }
 
 

@@ -370,3 +370,46 @@ def test_clip_is_strict_at_exact_threshold():
     assert res.mask.sum() == 0
     res = oracle.run(x, [(0.0, 0)], 0.999, "std", "all", repl=-1)
     assert res.mask.sum() == x.size
+
+
+@pytest.mark.parametrize("t", [3.5, 4.0])
+@pytest.mark.parametrize("m", [1.0, 64.0])
+def test_boundary_band_width_and_units(t, m):
+    """The boundary band is the set of finite voxels with | |s|/sigma_k - t |
+    <= 1e-5, i.e. within 1e-5 sigma_k of the threshold (the tolerance rule
+    for mask parity; detection is strict, Sect. 4.2).
+
+    Hand-built cube: every voxel is +-m (m a power of two) except a few test
+    voxels at |s| = sigma (t + d) for fixed offsets d, so the MAD over all
+    voxels is exactly 1.4826 m (the median of |s| is m). Each test voxel is a
+    float32, within 1.6e-7 sigma of its nominal offset; the offsets keep at
+    least 2e-6 sigma from the band edge, so their membership is fixed:
+    |d| in {0.5e-5, 0.8e-5} inside, |d| in {1.3e-5, 2e-5} outside. m = 64
+    puts sigma far from 1, so a band measured in absolute units instead of
+    units of sigma_k fails too."""
+    nz, ny, nx = 4, 16, 32
+    x = np.full((nz, ny, nx), m, np.float32)
+    x[:, :, 1::2] *= -1.0
+    sigma = 1.4826 * m
+    offsets = {0.5e-5: True, -0.5e-5: True, 0.8e-5: True, -0.8e-5: True,
+               1.3e-5: False, -1.3e-5: False, 2e-5: False, -2e-5: False}
+    spots = {}
+    for i, (d, inside) in enumerate(offsets.items()):
+        z, y, xx = i % nz, 3 + i, 5 + 2 * i
+        sign = -1.0 if i % 3 == 0 else 1.0
+        x[z, y, xx] = np.float32(sign * sigma * (t + d))
+        spots[(z, y, xx)] = (d, inside)
+    x[1, 0, 0] = np.nan          # blanked: never in the band, never detected
+    res = oracle.run(x, [(0.0, 0)], t, "mad", "all", repl=-1)
+    assert res.sigma[0] == sigma
+    band = res.band.astype(bool)
+    for (z, y, xx), (d, inside) in spots.items():
+        assert band[z, y, xx] == inside, (d, t, m)
+        assert res.mask[z, y, xx] == (1 if d > 0 else 0), (d, t, m)
+    assert int(band.sum()) == sum(offsets.values())
+    assert res.band_count[0] == int(band.sum())
+    assert not band[1, 0, 0] and res.mask[1, 0, 0] == 0
+    # the same classification through a single step
+    st = oracle.step(x, 0.0, 0, t, "mad", "all")
+    np.testing.assert_array_equal(st.band, res.band)
+    assert st.band_count == res.band_count[0]
