@@ -204,7 +204,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.storage,
         "data": "synthetic (seeded Philox noise + Gaussian mock galaxies)",
         "config": {
             "workload": args.workload, "n_cubes": len(wl.cubes),

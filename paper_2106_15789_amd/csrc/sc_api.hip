@@ -89,6 +89,7 @@ struct BatchKey {
     double t = 0, repl = 0;
     uint64_t sigma0_bits = 0;
     int mode = 0, range = 0, storage = 0;
+    int keep = 0;                    // keep_input_mask: changes the captured launches
     int lanes = 0, col_blocks = 0, strip_rows = 0;
     uint64_t work_gen = 0;
 };
@@ -848,7 +849,7 @@ bool same_key(const BatchKey &a, const BatchKey &b) {
             return false;
     return a.t == b.t && a.repl == b.repl && a.sigma0_bits == b.sigma0_bits &&
            a.mode == b.mode && a.range == b.range && a.storage == b.storage &&
-           a.lanes == b.lanes && a.col_blocks == b.col_blocks &&
+           a.keep == b.keep && a.lanes == b.lanes && a.col_blocks == b.col_blocks &&
            a.strip_rows == b.strip_rows && a.work_gen == b.work_gen;
 }
 
@@ -1004,6 +1005,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     key.mode = mode;
     key.range = range;
     key.storage = opt->storage;
+    key.keep = opt->keep_input_mask;
     key.lanes = L;
     key.col_blocks = h->tune.col_blocks;
     key.strip_rows = h->tune.strip_rows;

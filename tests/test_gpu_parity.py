@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+import gpu_chain
 import oracle
 import synth
 
@@ -20,6 +21,10 @@ import paper_2106_15789_amd as sc  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 SIGMA_RTOL = 1e-6
+# Smoothing bar: largest |s_gpu - s_oracle| over rms(s). The FP32 path rounds
+# each x pass once per window (running sums over pair sums of FP32 data) and
+# the result once; 2e-6 is the largest value measured on these cubes.
+SMOOTH_BAR = 3e-6
 
 
 def say(*a):
@@ -90,7 +95,7 @@ def test_smooth_matches_oracle(h, kernel):
     say(f"  max |ds| / rms(s) = {err:.3g}")
     # rms(s) is the std noise of s; a mask decision can only differ from the
     # oracle's inside the 1e-5 sigma band if this stays well below 1e-5
-    assert err < 6e-6
+    assert err < SMOOTH_BAR
 
 
 # Cascades with halo n r <= 6 take a separate row loop in strips that lie
@@ -114,7 +119,7 @@ def test_smooth_wide_planes_interior_path(h, kernel):
     scale = math.sqrt(np.mean(s_ref[fin] ** 2))
     err = np.abs(s_gpu[fin] - s_ref[fin]).max() / scale
     say(f"wide smooth {kernel} (n={n_iter}, r={r}): max |ds| / rms(s) = {err:.3g}")
-    assert err < 6e-6
+    assert err < SMOOTH_BAR
 
 
 # --------------------------------------------------------- end-to-end runs
@@ -157,21 +162,10 @@ def test_step_teacher_forced(h, mode, rng_):
 
 
 def test_run_cfg2_like_end_to_end(h):
+    """Whole run, every iteration checked from the GPU's own previous state."""
     x = cfg2_like()
-    ref = oracle.run(x, KERNELS_CFG2, 3.5, "mad", "negative", 2.0)
-    m, noise, s0 = h.run(dev(x), KERNELS_CFG2, 3.5, "mad", "negative", 2.0)
-    g = host(m)
-    diff = g != ref.mask
-    say("end-to-end: sigma rel", np.abs(noise / ref.sigma - 1).max(),
-        "band", ref.band_count.sum(), "diff", int(diff.sum()),
-        "outside band", int((diff & (ref.band == 0)).sum()))
-    assert_sigma(noise, ref.sigma, "sigma_k")
-    assert_sigma(s0, ref.sigma0, "sigma_0")
-    # with no band voxel, nothing can propagate: the masks must be identical
-    if ref.band_count.sum() == 0:
-        np.testing.assert_array_equal(g, ref.mask)
-    else:
-        assert int((diff & (ref.band == 0)).sum()) <= 50 * int(ref.band_count.sum())
+    gpu_chain.forced_chain(h, dev(x), x, KERNELS_CFG2, 3.5, "mad", "negative", 2.0,
+                           what="cfg2-like 200x170x160")
 
 
 def test_replacement_off_matches(h):

@@ -94,3 +94,52 @@ def test_fullsize_run_properties(h, cfg2):
                              wl.replacement)
     np.testing.assert_array_equal(noise2, noise)
     assert torch.equal(mask2.cpu(), torch.from_numpy(g))
+
+
+_CUT = {}
+
+
+def _gpu_state(h, xd, wl, k):
+    """The GPU's mask (host copy), noise and sigma_0 after its first k
+    iterations of the full-size run: the run cut to its first k kernels."""
+    if k not in _CUT:
+        m, n, s0 = h.run(xd, wl.kernels[:k], wl.threshold, wl.noise_mode, wl.flux_range,
+                         wl.replacement)
+        torch.cuda.synchronize()
+        _CUT.clear()   # keep at most two 1 GiB host masks
+        _CUT[k] = (m.cpu().numpy(), n, s0)
+        del m
+    return _CUT[k]
+
+
+@pytest.fixture(scope="module")
+def xd_full(cfg2):
+    return torch.from_numpy(cfg2[1]).cuda()
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_fullsize_gpu_forced_chain(h, cfg2, xd_full, k):
+    """Iteration k of the whole full-size run, checked against the oracle from
+    the GPU's own state after iterations 1..k-1 (its run cut to k-1 kernels)
+    and the GPU's sigma_0: noise to 1e-6, mask equal outside the band. The
+    twelve tests together cover the whole 12-kernel run of the benchmark."""
+    wl, x, s0, m1, band1 = cfg2
+    f, w = wl.kernels[k]
+    prev = None
+    if k:
+        prev, n_prev, s0_prev = _gpu_state(h, xd_full, wl, k)
+    cur, n_cur, s0_gpu = _gpu_state(h, xd_full, wl, k + 1)
+    if k:
+        np.testing.assert_array_equal(n_cur[:k], n_prev)
+        assert s0_gpu == s0_prev
+    assert abs(s0_gpu / s0 - 1) <= 1e-6
+    say(f"full-size chain step {k} ({f}, {w}): oracle step ...")
+    ref = oracle.step(x, f, w, wl.threshold, wl.noise_mode, wl.flux_range, prev,
+                      wl.replacement, s0_gpu)
+    diff = cur != ref.mask
+    out = int((diff & (ref.band == 0)).sum())
+    rel = abs(n_cur[k] / ref.sigma - 1)
+    say(f"  sigma rel {rel:.2e}, band {ref.band_count}, diff {int(diff.sum())} "
+        f"(outside the band {out}), detections {int(cur.sum())}")
+    assert rel <= 1e-6
+    assert out == 0
