@@ -4,9 +4,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The GPU library never calls it and it
 never calls the GPU library.
 
-``sc_oracle.cpp`` is the oracle proper (C++17, FP64, direct summation);
-``brute.py`` is an independent dense-matrix formulation used to pin it on tiny
-cubes. Citations are to Westmeier et al. 2021 (arXiv:2106.15789).
+``sc_oracle.cpp`` is the smooth-and-clip oracle proper (C++17, FP64, direct
+summation); ``nn_oracle.cpp`` the local noise normalisation (Sect. 4.1);
+``brute.py`` is an independent dense-matrix formulation used to pin them on
+tiny cubes. Citations are to Westmeier et al. 2021 (arXiv:2106.15789).
 """
 from __future__ import annotations
 
@@ -22,23 +23,61 @@ _LIB_PATH = os.path.join(_HERE, "libsc_oracle.so")
 # Tests that plant mistakes in a copy of the oracle point this at the copy.
 _LIB_OVERRIDE = os.environ.get("SC_ORACLE_LIB")
 _lib = None
+# The other oracle libraries: source file -> library, and the variable that
+# points a planted-mistake test at its copy.
+_EXTRA = {
+    "nn": ("nn_oracle.cpp", "libnn_oracle.so", "NN_ORACLE_LIB"),
+}
+_extra_libs = {}
 
 NOISE = {"std": 0, "mad": 1}
 RANGE = {"negative": -1, "all": 0, "positive": 1}
 ENOSTAT = -4
 
-def build(verbose: bool = False) -> str:
-    """Compile the oracle with g++ -O2 -fopenmp (no fast-math: IEEE FP64)."""
+def _compile(src_name: str, lib_path: str, verbose: bool) -> None:
     import subprocess
-    src = os.path.join(_HERE, "sc_oracle.cpp")
-    tmp = _LIB_PATH + ".tmp"
+    src = os.path.join(_HERE, src_name)
+    tmp = lib_path + ".tmp"
     cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
            "-ffp-contract=off", src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
+    os.replace(tmp, lib_path)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracles with g++ -O2 -fopenmp (no fast-math: IEEE FP64)."""
+    _compile("sc_oracle.cpp", _LIB_PATH, verbose)
+    for src, lib, _ in _EXTRA.values():
+        _compile(src, os.path.join(_HERE, lib), verbose)
     return _LIB_PATH
+
+
+def lib_paths() -> List[str]:
+    return [_LIB_PATH] + [os.path.join(_HERE, lib) for _, lib, _ in _EXTRA.values()]
+
+
+def _extra(name: str):
+    """Load one of the other oracle libraries (or its planted-mistake copy)."""
+    if name not in _extra_libs:
+        src, lib, env = _EXTRA[name]
+        path = os.environ.get(env) or os.path.join(_HERE, lib)
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: run __graft_entry__.build() first")
+        _extra_libs[name] = _bind_extra(name, ctypes.CDLL(path))
+    return _extra_libs[name]
+
+
+def _bind_extra(name, lib):
+    i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    if name == "nn":
+        lib.nno_blocks.argtypes = [i64, i64]
+        lib.nno_blocks.restype = i64
+        lib.nno_normalise.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, i32, i32,
+                                      vp, vp]
+        lib.nno_normalise.restype = ctypes.c_int
+    return lib
 
 
 def _load():
@@ -183,3 +222,28 @@ def run(cube: np.ndarray, kernels: Sequence[Tuple[float, int]], threshold: float
     if rc not in (0, ENOSTAT):
         raise ValueError("sco_run failed (%d)" % rc)
     return RunResult(mask, sig, s0.value, band, bc, rc)
+
+
+# ------------------------------------------------ local noise normalisation
+
+def nn_grid(nx: int, ny: int, nz: int, g_xy: int, g_z: int) -> Tuple[int, int, int]:
+    """Blocks (nbz, nby, nbx) of the noise grid (reading N1)."""
+    lib = _extra("nn")
+    return (int(lib.nno_blocks(nz, g_z)), int(lib.nno_blocks(ny, g_xy)),
+            int(lib.nno_blocks(nx, g_xy)))
+
+
+def normalise(cube: np.ndarray, w_xy: int, w_z: int, g_xy: int, g_z: int, mode: str,
+              flux_range: str, want_cube: bool = True):
+    """Local noise normalisation (Sect. 4.1): (sigma grid [nbz][nby][nbx]
+    FP64, normalised float32 cube or None)."""
+    x = _cube(cube)
+    nz, ny, nx = x.shape
+    sig = np.empty(nn_grid(nx, ny, nz, g_xy, g_z), dtype=np.float64)
+    y = np.empty(x.shape, dtype=np.float32) if want_cube else None
+    rc = _extra("nn").nno_normalise(x.ctypes.data, nx, ny, nz, int(w_xy), int(w_z),
+                                    int(g_xy), int(g_z), NOISE[mode], RANGE[flux_range],
+                                    sig.ctypes.data, None if y is None else y.ctypes.data)
+    if rc != 0:
+        raise ValueError("nno_normalise failed (%d)" % rc)
+    return sig, y

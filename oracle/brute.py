@@ -108,3 +108,40 @@ def run(cube: np.ndarray, kernels: Sequence[Tuple[float, int]], threshold: float
             hit = finite & (np.abs(s) > threshold * sk)
         mask = mask | hit.astype(np.uint8)
     return mask, np.array(sig), sigma0
+
+
+# ------------------------------------------------ local noise normalisation
+
+def _axis_blocks(n: int, g: int, w: int):
+    """Per block of one axis: (member indices, window indices). Members are
+    the voxels whose index // g is the block number; the centre is the lower
+    middle member; the window is every index within (w - 1) / 2 of it."""
+    idx = np.arange(n)
+    out = []
+    for b in range(int(np.ceil(n / g))):
+        members = np.flatnonzero(idx // g == b)
+        centre = members[(members.size - 1) // 2]
+        window = np.flatnonzero(np.abs(idx - centre) <= (w - 1) // 2)
+        out.append((members, window))
+    return out
+
+
+def normalise(cube: np.ndarray, w_xy: int, w_z: int, g_xy: int, g_z: int, mode: str,
+              flux_range: str):
+    """Noise of every block's window (sort-based median) and the cube divided
+    by its block's noise: (sigma [nbz][nby][nbx], float32 cube)."""
+    x = cube.astype(np.float64)
+    nz, ny, nx = x.shape
+    bx, by, bz = _axis_blocks(nx, g_xy, w_xy), _axis_blocks(ny, g_xy, w_xy), \
+        _axis_blocks(nz, g_z, w_z)
+    sig = np.empty((len(bz), len(by), len(bx)))
+    y = np.full(x.shape, np.nan, dtype=np.float32)
+    for k, (mz, wz) in enumerate(bz):
+        for j, (my, wy) in enumerate(by):
+            for i, (mx, wx) in enumerate(bx):
+                s = noise(x[np.ix_(wz, wy, wx)].ravel(), mode, flux_range)
+                sig[k, j, i] = s
+                if np.isfinite(s) and s > 0:
+                    with np.errstate(invalid="ignore"):
+                        y[np.ix_(mz, my, mx)] = (x[np.ix_(mz, my, mx)] / s).astype(np.float32)
+    return sig, y

@@ -19,7 +19,7 @@ def _ensure_built():
     import oracle
     if not os.path.exists(synth._LIB_PATH):
         synth.build()
-    if not os.path.exists(oracle._LIB_PATH):
+    if not all(os.path.exists(p) for p in oracle.lib_paths()):
         oracle.build()
 
 
