@@ -161,36 +161,61 @@ int sofia_sc_run_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
                        int32_t noise_mode, int32_t flux_range, double *noise,
                        const sofia_sc_options *opt, double *sigma0);
 
-/* Launch shapes of batched runs. */
+/* Launch shapes of the runs of a handle (batched and single). */
 typedef struct {
-    int32_t lanes;          /* workspaces whose launch chains run side by side:
-                               4, 8 or 16 (default 8) */
+    int32_t lanes;          /* batches: workspaces whose launch chains run side
+                               by side: 4, 8 or 16 (default 8) */
     int32_t col_blocks;     /* column passes: blocks a launch aims at, by
-                               splitting z into chunks of >= 64 planes: 3072,
-                               6144 or 12288 (default 6144) */
+                               splitting z into chunks: 3072, 6144 or 12288
+                               (default 6144) */
     int32_t strip_rows;     /* spatial pass: most rows per chunk of a strip:
                                64, 128 or 256 (default 256) */
+    int32_t strip_waves;    /* spatial pass: most adjacent 128-column strips
+                               (waves) per workgroup, which stage their rows
+                               once in LDS: 1, 2 or 4 (default 4) */
+    int32_t col_min_planes; /* column passes: fewest planes per z chunk (the
+                               spectral halo is re-read per chunk): 32, 64 or
+                               128 (default 64) */
     int32_t reserved;
     double ms;              /* time of one batched run with these shapes as
                                measured by the tuning (NaN if not tuned) */
 } sofia_sc_batch_tuning;
 
 /* SWITCHED OFF IN THIS BUILD: returns SOFIA_SC_EDEVICE at once (best, if
- * not NULL, receives the defaults), because one tuning run ended in a host
- * abort whose cause is not yet established. The intended behaviour:
- * autotune the launch shapes of sofia_sc_run_batch on a batch: times
- * candidate shapes one parameter at a time (lanes, then col_blocks, then
- * strip_rows; each candidate's graph is captured, launched once untimed and
- * then timed over two launches) and keeps the fastest in the handle; every
- * later sofia_sc_run_batch call of the handle uses it. Results do not depend
- * on the shapes except for the last bits of std noise (summation order of
- * the per-block partials). Arguments as sofia_sc_run_batch; the masks are
- * written with the batch's result. best (host, may be NULL) receives the
- * chosen shapes. Returns as sofia_sc_run_batch. */
+ * not NULL, receives the handle's current shapes). Timing candidate shapes
+ * through repeated graph captures crashed the process when it ran after
+ * other batched calls in the same process, for a reason not established.
+ * Batches use the handle's shapes, which sofia_sc_tune_run and
+ * sofia_sc_set_shapes set. */
 int sofia_sc_tune_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
                         const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
                         int32_t noise_mode, int32_t flux_range, const sofia_sc_options *opt,
                         sofia_sc_batch_tuning *best);
+
+/* Autotune the launch shapes of whole runs (Sect. 4.2) on the caller's cube:
+ * candidate shapes are timed one parameter at a time (col_blocks,
+ * strip_rows, strip_waves, then col_min_planes; each candidate as the faster
+ * of two sofia_sc_run_ex calls after an untimed one; no graph is captured)
+ * and the fastest are kept in the handle: every later sofia_sc_run*,
+ * sofia_sc_step*, sofia_sc_smooth and sofia_sc_run_batch call of the handle
+ * uses them (lanes are left as they are). Results do not depend on the
+ * shapes except for the last bits of std noise (summation order of the
+ * per-block partials). Arguments as sofia_sc_run_ex; mask is written with
+ * the run's result for the chosen shapes; best (host, may be NULL) receives
+ * the chosen shapes and their time. Returns as sofia_sc_run_ex; on error the
+ * handle keeps its previous shapes. */
+int sofia_sc_tune_run(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                      const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
+                      int32_t noise_mode, int32_t flux_range, uint8_t *mask,
+                      const sofia_sc_options *opt, sofia_sc_batch_tuning *best);
+
+/* Set the handle's launch shapes (each field one of the candidates listed in
+ * sofia_sc_batch_tuning; ms is ignored), or the defaults for shapes == NULL.
+ * EINVAL for a value outside the candidates. No device work. */
+int sofia_sc_set_shapes(sofia_sc *h, const sofia_sc_batch_tuning *shapes);
+
+/* The handle's current launch shapes. EINVAL for NULL. */
+int sofia_sc_get_shapes(const sofia_sc *h, sofia_sc_batch_tuning *shapes);
 
 /* One S+C iteration with the previous state given (Sect. 4.2 and 6.2.4):
  * smooth the cube after replacing the voxels set in mask_in by

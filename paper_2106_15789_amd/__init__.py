@@ -30,7 +30,8 @@ RANGE = {"negative": -1, "all": 0, "positive": 1}
 # Every symbol include/sofia_sc.h declares.
 EXPORTS = [
     "sofia_sc_default_options", "sofia_sc_create", "sofia_sc_destroy",
-    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch", "sofia_sc_tune_batch",
+    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch",
+    "sofia_sc_tune_batch", "sofia_sc_tune_run", "sofia_sc_set_shapes", "sofia_sc_get_shapes",
     "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
@@ -95,7 +96,8 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("col_blocks", ctypes.c_int32),
-                ("strip_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("strip_rows", ctypes.c_int32), ("strip_waves", ctypes.c_int32),
+                ("col_min_planes", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("ms", ctypes.c_double)]
 
 
@@ -140,6 +142,11 @@ def load():
     lib.sofia_sc_tune_batch.argtypes = [vp, ctypes.POINTER(Cube), i32, ctypes.POINTER(Kernel),
                                         i32, dbl, i32, i32, ctypes.POINTER(Options),
                                         ctypes.POINTER(BatchTuning)]
+    lib.sofia_sc_tune_run.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(Kernel), i32, dbl,
+                                      i32, i32, vp, ctypes.POINTER(Options),
+                                      ctypes.POINTER(BatchTuning)]
+    lib.sofia_sc_set_shapes.argtypes = [vp, ctypes.POINTER(BatchTuning)]
+    lib.sofia_sc_get_shapes.argtypes = [vp, ctypes.POINTER(BatchTuning)]
     lib.sofia_sc_step.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, dbl,
                                   dbl, vp, vp, ctypes.POINTER(dbl), vp]
     lib.sofia_sc_step_ex.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, i32, i32, vp, vp,
@@ -154,8 +161,10 @@ def load():
     lib.sofia_sc_last_error.restype = ctypes.c_char_p
     lib.sofia_sc_strerror.argtypes = [ctypes.c_int]
     lib.sofia_sc_strerror.restype = ctypes.c_char_p
-    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch",
-                 "sofia_sc_tune_batch",
+    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex",
+                 "sofia_sc_run_batch",
+                 "sofia_sc_tune_batch", "sofia_sc_tune_run", "sofia_sc_set_shapes",
+                 "sofia_sc_get_shapes",
                  "sofia_sc_step",
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
@@ -163,6 +172,11 @@ def load():
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def _shapes_dict(t) -> dict:
+    return {"lanes": t.lanes, "col_blocks": t.col_blocks, "strip_rows": t.strip_rows,
+            "strip_waves": t.strip_waves, "col_min_planes": t.col_min_planes, "ms": t.ms}
 
 
 class ScError(RuntimeError):
@@ -301,8 +315,9 @@ class SofiaSC:
     def tune_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
                    flux_range: str = "negative", replacement: float = 2.0, masks=None,
                    stream=None, storage: str = "f32", sigma0: float = float("nan")):
-        """Autotune the batch launch shapes on this batch; returns the chosen
-        {lanes, col_blocks, strip_rows, ms}, kept for later batches."""
+        """Autotune the launch shapes on this batch; returns the chosen
+        {lanes, col_blocks, strip_rows, strip_waves, col_min_planes, ms}, kept
+        by the handle for its later runs and batches."""
         desc, masks = self._batch_args(cubes, masks)
         opt = self._options(replacement, sigma0, storage, stream)
         best = BatchTuning()
@@ -312,8 +327,47 @@ class SofiaSC:
                                           ctypes.byref(best))
         if rc != OK and rc != ENOSTAT:
             self._raise(rc, "sofia_sc_tune_batch")   # switched off in this build
-        return {"lanes": best.lanes, "col_blocks": best.col_blocks,
-                "strip_rows": best.strip_rows, "ms": best.ms}
+        return _shapes_dict(best)
+
+    def tune_run(self, cube, kernels, threshold: float, noise_mode: str = "mad",
+                 flux_range: str = "negative", replacement: float = 2.0, mask=None,
+                 stream=None, storage: str = "f32", sigma0: float = float("nan")):
+        """Autotune the launch shapes of whole runs on this cube; returns the
+        chosen shapes (kept by the handle for its later calls)."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        _check_like(mask, cube, torch.uint8, "mask")
+        if mask is None:
+            mask = torch.empty(cube.shape, dtype=torch.uint8, device=cube.device)
+        opt = self._options(replacement, sigma0, storage, stream)
+        best = BatchTuning()
+        rc = self.lib.sofia_sc_tune_run(self.h, cube.data_ptr(), nx, ny, nz, _kernels(kernels),
+                                        len(kernels), float(threshold), NOISE[noise_mode],
+                                        RANGE[flux_range], mask.data_ptr(), ctypes.byref(opt),
+                                        ctypes.byref(best))
+        if rc != OK and rc != ENOSTAT:
+            self._raise(rc, "sofia_sc_tune_run")
+        return _shapes_dict(best)
+
+    def set_shapes(self, shapes=None):
+        """Set the handle's launch shapes (dict as returned by tune_run), or
+        the defaults for None."""
+        if shapes is None:
+            rc = self.lib.sofia_sc_set_shapes(self.h, None)
+        else:
+            t = BatchTuning()
+            for k in ("lanes", "col_blocks", "strip_rows", "strip_waves", "col_min_planes"):
+                setattr(t, k, int(shapes[k]))
+            rc = self.lib.sofia_sc_set_shapes(self.h, ctypes.byref(t))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_set_shapes")
+
+    def shapes(self):
+        t = BatchTuning()
+        rc = self.lib.sofia_sc_get_shapes(self.h, ctypes.byref(t))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_get_shapes")
+        return _shapes_dict(t)
 
     def run_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
                   flux_range: str = "negative", replacement: float = 2.0, masks=None,

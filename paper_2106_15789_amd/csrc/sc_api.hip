@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -90,15 +91,38 @@ struct BatchKey {
     uint64_t sigma0_bits = 0;
     int mode = 0, range = 0, storage = 0;
     int keep = 0;                    // keep_input_mask: changes the captured launches
-    int lanes = 0, col_blocks = 0, strip_rows = 0;
+    int lanes = 0, col_blocks = 0, strip_rows = 0, strip_waves = 0, col_min_planes = 0;
     uint64_t work_gen = 0;
 };
+
+sofia_sc_batch_tuning default_tuning() {
+    const Shapes d;
+    sofia_sc_batch_tuning t;
+    std::memset(&t, 0, sizeof(t));
+    t.lanes = kDefaultLanes;
+    t.col_blocks = d.col_blocks;
+    t.strip_rows = d.strip_rows;
+    t.strip_waves = d.strip_waves;
+    t.col_min_planes = d.col_min_planes;
+    t.ms = NAN;
+    return t;
+}
+
+Shapes shapes_of(const sofia_sc_batch_tuning &t) {
+    Shapes s;
+    s.col_blocks = t.col_blocks;
+    s.strip_rows = t.strip_rows;
+    s.strip_waves = t.strip_waves;
+    s.col_min_planes = t.col_min_planes;
+    return s;
+}
 
 }  // namespace
 
 struct sofia_sc {
     int device = 0;
-    std::string err;
+    long allocs = 0;                 // device / pinned allocations attempted so far
+    char err[512] = {0};             // last error text (fixed: setting it allocates nothing)
     Work w;                          // workspace of run / step / smooth
     DevState *st_host = nullptr;     // pinned
     bool prof = false;
@@ -119,7 +143,7 @@ struct sofia_sc {
     double graph_bytes = 0;          // algorithmic bytes of the captured launches
     bool capturing = false;          // launches are being captured: no events
     double capture_bytes = 0;
-    sofia_sc_batch_tuning tune = {kDefaultLanes, 6144, 256, 0, NAN};
+    sofia_sc_batch_tuning tune = default_tuning();
 };
 
 namespace {
@@ -152,14 +176,51 @@ size_t amb_capacity(int64_t N) { return std::max<size_t>((size_t)N / 256, (size_
 // Capture buffer: up to N/8 keys (at least 2^20).
 size_t capture_capacity(int64_t N) { return std::max<size_t>((size_t)N / 8, (size_t)1 << 20); }
 
-int fail(sofia_sc *h, int code, const std::string &msg) {
-    if (h) h->err = msg;
+int fail(sofia_sc *h, int code, const char *msg) {
+    if (h) std::snprintf(h->err, sizeof(h->err), "%s", msg);
     return code;
 }
 
+int fail(sofia_sc *h, int code, const std::string &msg) { return fail(h, code, msg.c_str()); }
+
 int hip_fail(sofia_sc *h, hipError_t e, const char *what) {
-    return fail(h, SOFIA_SC_EDEVICE,
-                std::string(what) + ": " + hipGetErrorString(e));
+    if (h) std::snprintf(h->err, sizeof(h->err), "%s: %s", what, hipGetErrorString(e));
+    return SOFIA_SC_EDEVICE;
+}
+
+// Diagnostics hooks, set in the environment:
+//  SOFIA_SC_TRACE=1       one line per run, batch capture / launch and tuning
+//                         candidate on stderr;
+//  SOFIA_SC_FAIL_ALLOC=k  the k-th device or pinned allocation a handle
+//                         attempts (counting from 1) fails as out of memory,
+//                         so that tests reach every ENOMEM path.
+bool trace_on() {
+    const char *v = std::getenv("SOFIA_SC_TRACE");
+    return v && *v && *v != '0';
+}
+
+#define SC_TRACE(...)                                   \
+    do {                                                \
+        if (trace_on()) {                               \
+            std::fprintf(stderr, "[sofia_sc] " __VA_ARGS__); \
+            std::fputc('\n', stderr);                   \
+        }                                               \
+    } while (0)
+
+bool injected_alloc_failure(sofia_sc *h) {
+    const long n = ++h->allocs;
+    const char *v = std::getenv("SOFIA_SC_FAIL_ALLOC");
+    return v && *v && std::atol(v) == n;
+}
+
+hipError_t dev_alloc(sofia_sc *h, void **p, size_t bytes) {
+    if (injected_alloc_failure(h)) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t host_alloc(sofia_sc *h, void **p, size_t bytes) {
+    if (injected_alloc_failure(h)) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
 }
 
 // Reading of the Gaussian construction: sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2
@@ -235,11 +296,11 @@ struct ColGrid {
     int blocks() const { return ncb * nzc; }
 };
 
-ColGrid col_grid(int64_t ncol, int64_t nz, int target) {
+ColGrid col_grid(int64_t ncol, int64_t nz, const Shapes &sh) {
     ColGrid g;
     g.ncb = (int)((ncol + kColThreads - 1) / kColThreads);
-    int64_t nzc = (target + g.ncb - 1) / g.ncb;
-    const int64_t max_nzc = std::max<int64_t>(1, nz / 64);
+    int64_t nzc = (sh.col_blocks + g.ncb - 1) / g.ncb;
+    const int64_t max_nzc = std::max<int64_t>(1, nz / std::max(1, sh.col_min_planes));
     nzc = std::max<int64_t>(1, std::min(nzc, max_nzc));
     g.zchunk = (int)((nz + nzc - 1) / nzc);
     g.nzc = (int)((nz + g.zchunk - 1) / g.zchunk);
@@ -266,7 +327,12 @@ int grow(sofia_sc *h, T *&ptr, size_t &cap, size_t need, const char *what, bool 
     }
     ptr = nullptr;
     cap = 0;
-    const hipError_t e = hipMalloc(&ptr, need * sizeof(T));
+    const hipError_t e = dev_alloc(h, (void **)&ptr, need * sizeof(T));
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        SC_TRACE("allocation of %zu bytes (%s) failed: %s", need * sizeof(T), what,
+                 hipGetErrorString(e));
+    }
     if (e != hipSuccess)
         return fail(h, SOFIA_SC_ENOMEM, std::string(what) + ": " + hipGetErrorString(e));
     cap = need;
@@ -316,11 +382,14 @@ void free_work(Work &w) {
 // The handle's own device state and its pinned host copy.
 int ensure_state(sofia_sc *h) {
     hipError_t e;
-    if (!h->w.st && (e = hipMalloc(&h->w.st, sizeof(DevState))) != hipSuccess)
+    if (!h->w.st && (e = dev_alloc(h, (void **)&h->w.st, sizeof(DevState))) != hipSuccess) {
+        h->w.st = nullptr;
         return fail(h, SOFIA_SC_ENOMEM, std::string("state: ") + hipGetErrorString(e));
-    if (!h->st_host &&
-        (e = hipHostMalloc(&h->st_host, sizeof(DevState), hipHostMallocDefault)) != hipSuccess)
+    }
+    if (!h->st_host && (e = host_alloc(h, (void **)&h->st_host, sizeof(DevState))) != hipSuccess) {
+        h->st_host = nullptr;
         return fail(h, SOFIA_SC_ENOMEM, std::string("host state: ") + hipGetErrorString(e));
+    }
     return SOFIA_SC_OK;
 }
 
@@ -427,7 +496,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     if ((spatial || spec) && !has_wm)
         return fail(h, SOFIA_SC_EINVAL, "internal: smoothing without working mask");
 
-    const ColGrid g = col_grid(d.ncol, d.nz, w.sh.col_blocks);
+    const ColGrid g = col_grid(d.ncol, d.nz, w.sh);
     if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
         return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
     if (spatial) {
@@ -443,7 +512,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         }
         a.p = w.p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
-        spatial_strips(a, j.pl.n_iter, j.pl.radius, w.sh.strip_rows);
+        spatial_strips(a, j.pl.n_iter, j.pl.radius, w.sh.strip_rows, w.sh.strip_waves);
         if (a.tiles > 0x7fffffffLL)
             return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
         a.repl_n = j.repl_n;
@@ -713,7 +782,7 @@ int check_options(sofia_sc *h, const sofia_sc_options *opt) {
 // Workspace a run of this cube and kernel list needs.
 int ensure_for(sofia_sc *h, Work &w, const RunSpec &r, bool *moved = nullptr) {
     const bool sp = r.any_spatial();
-    const ColGrid g = col_grid(r.d.ncol, r.d.nz, w.sh.col_blocks);
+    const ColGrid g = col_grid(r.d.ncol, r.d.nz, w.sh);
     return ensure_work(h, w, r.d.N, sp, (size_t)g.blocks(),
                        sp ? r.d.nz * det_words_per_plane(r.d.ncol) : 0,
                        r.storage != SOFIA_SC_STORE_F32, moved);
@@ -806,7 +875,7 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
              int32_t range, uint8_t *mask, double *noise, const sofia_sc_options *opt,
              double *sigma0_out) {
     if (!h) return SOFIA_SC_EINVAL;
-    h->err.clear();
+    h->err[0] = 0;
     if (noise && K > 0 && K <= SOFIA_SC_MAX_KERNELS) nan_fill(noise, K);
     if (sigma0_out) *sigma0_out = NAN;
     if (!cube || !kernels || !mask || !noise)
@@ -827,6 +896,10 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
                     range, mask, opt->replacement, opt->sigma0, opt->storage,
                     opt->keep_input_mask != 0};
     if ((rc = ensure_state(h))) return rc;
+    h->w.sh = shapes_of(h->tune);
+    SC_TRACE("run %lldx%lldx%lld, %d kernels, storage %d, col_blocks %d, strip_rows %d",
+             (long long)nx, (long long)ny, (long long)nz, K, opt->storage, h->w.sh.col_blocks,
+             h->w.sh.strip_rows);
     if ((rc = ensure_for(h, h->w, r))) return rc;
     if ((rc = enqueue_run(h, s, h->w, r))) return rc;
     if ((rc = finish(h, s, h->st_host, h->w.st))) return rc;
@@ -850,7 +923,8 @@ bool same_key(const BatchKey &a, const BatchKey &b) {
     return a.t == b.t && a.repl == b.repl && a.sigma0_bits == b.sigma0_bits &&
            a.mode == b.mode && a.range == b.range && a.storage == b.storage &&
            a.keep == b.keep && a.lanes == b.lanes && a.col_blocks == b.col_blocks &&
-           a.strip_rows == b.strip_rows && a.work_gen == b.work_gen;
+           a.strip_rows == b.strip_rows && a.strip_waves == b.strip_waves &&
+           a.col_min_planes == b.col_min_planes && a.work_gen == b.work_gen;
 }
 
 // Lane streams, fork/join events and the per-cube device states.
@@ -874,11 +948,17 @@ int ensure_batch_infra(sofia_sc *h, size_t n, bool *moved) {
         h->bst = nullptr;
         h->bst_host = nullptr;
         h->bst_cap = 0;
-        if ((e = hipMalloc(&h->bst, n * sizeof(DevState))) != hipSuccess)
+        if ((e = dev_alloc(h, (void **)&h->bst, n * sizeof(DevState))) != hipSuccess) {
+            h->bst = nullptr;
             return fail(h, SOFIA_SC_ENOMEM, std::string("batch states: ") + hipGetErrorString(e));
-        if ((e = hipHostMalloc(&h->bst_host, n * sizeof(DevState), hipHostMallocDefault)) !=
-            hipSuccess)
-            return fail(h, SOFIA_SC_ENOMEM, std::string("batch host states: ") + hipGetErrorString(e));
+        }
+        if ((e = host_alloc(h, (void **)&h->bst_host, n * sizeof(DevState))) != hipSuccess) {
+            (void)hipFree(h->bst);
+            h->bst = nullptr;
+            h->bst_host = nullptr;
+            return fail(h, SOFIA_SC_ENOMEM,
+                        std::string("batch host states: ") + hipGetErrorString(e));
+        }
         h->bst_cap = n;
         *moved = true;
     }
@@ -934,7 +1014,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
                int32_t range, double *noise, const sofia_sc_options *opt,
                double *sigma0_out) {
     if (!h) return SOFIA_SC_EINVAL;
-    h->err.clear();
+    h->err[0] = 0;
     const bool sizes_ok = n >= 1 && n <= SOFIA_SC_MAX_CUBES && K >= 1 && K <= SOFIA_SC_MAX_KERNELS;
     if (sizes_ok) {
         nan_fill(noise, n * K);
@@ -957,7 +1037,8 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         if (!c.cube || !c.mask)
             return fail(h, SOFIA_SC_EINVAL, "NULL cube or mask in cube " + std::to_string(i));
         if ((rc = check_dims(h, c.nx, c.ny, c.nz))) {
-            h->err += " (cube " + std::to_string(i) + ")";
+            const size_t len = std::strlen(h->err);
+            std::snprintf(h->err + len, sizeof(h->err) - len, " (cube %d)", i);
             return rc;
         }
         runs.push_back(RunSpec{c.cube, Dims{c.nx, c.ny, c.nz, c.nx * c.ny, c.nx * c.ny * c.nz},
@@ -986,7 +1067,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     }
     bool moved = false;
     for (int l = 0; l < L; ++l) {
-        h->lanes[l].sh = Shapes{h->tune.col_blocks, h->tune.strip_rows};
+        h->lanes[l].sh = shapes_of(h->tune);
         for (int i : lane_cubes[(size_t)l])
             if ((rc = ensure_for(h, h->lanes[l], runs[(size_t)i], &moved))) return rc;
     }
@@ -1009,10 +1090,17 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     key.lanes = L;
     key.col_blocks = h->tune.col_blocks;
     key.strip_rows = h->tune.strip_rows;
+    key.strip_waves = h->tune.strip_waves;
+    key.col_min_planes = h->tune.col_min_planes;
     key.work_gen = h->work_gen;
     if (!h->gvalid || !same_key(key, h->gkey)) {
         drop_graph(h);
-        if ((rc = capture_batch(h, runs, lane_cubes))) return rc;
+        SC_TRACE("batch capture: %d cubes on %d lanes, col_blocks %d, strip_rows %d, "
+                 "strip_waves %d, col_min_planes %d", n, L, h->tune.col_blocks,
+                 h->tune.strip_rows, h->tune.strip_waves, h->tune.col_min_planes);
+        rc = capture_batch(h, runs, lane_cubes);
+        SC_TRACE("batch capture done: rc %d %s", rc, h->err);
+        if (rc) return rc;
         h->gkey = std::move(key);
         h->gvalid = true;
     }
@@ -1021,36 +1109,46 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     double vox = 0;
     for (const RunSpec &r : runs) vox += (double)r.d.N;
     rc = launch(h, s, F_BATCH, h->graph_bytes, vox, [&] { return hipGraphLaunch(h->gexec, s); });
-    if (rc) return rc;
+    if (rc) {
+        SC_TRACE("batch launch failed: %s", h->err);
+        return rc;
+    }
     if ((rc = finish(h, s, h->bst_host, h->bst, (size_t)n))) return rc;
     for (int i = 0; i < n; ++i) {
         const int ri = read_run(h, h->bst_host[i], runs[(size_t)i], noise + (size_t)i * K,
                                 sigma0_out ? sigma0_out + i : nullptr);
         if (ri) rc = ri;
     }
-    if (rc == SOFIA_SC_ENOSTAT) h->err = "no finite voxel in the flux range for some kernel of some cube";
+    if (rc == SOFIA_SC_ENOSTAT)
+        fail(h, rc, "no finite voxel in the flux range for some kernel of some cube");
     return rc;
 }
 
-// Autotuning of the batch launch shapes: coordinate search, each candidate
-// timed as the faster of two graph launches after an untimed one (which
-// also captures its graph).
-[[maybe_unused]] int tune_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
-              const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
-              int32_t range, const sofia_sc_options *opt, sofia_sc_batch_tuning *best) {
+// Autotuning of the launch shapes of single runs: coordinate search, one
+// shape parameter at a time, each candidate timed as the faster of two runs
+// of the caller's cube after an untimed one. Runs capture no graph.
+int tune_run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                  const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
+                  int32_t range, uint8_t *mask, const sofia_sc_options *opt,
+                  sofia_sc_batch_tuning *best) {
     if (!h) return SOFIA_SC_EINVAL;
-    if (n < 1 || n > SOFIA_SC_MAX_CUBES || K < 1 || K > SOFIA_SC_MAX_KERNELS)
-        return fail(h, SOFIA_SC_EINVAL, "number of cubes must be 1..4096 and of kernels 1..64");
-    std::vector<double> noise((size_t)n * K);
+    if (best) *best = h->tune;
+    if (K < 1 || K > SOFIA_SC_MAX_KERNELS)
+        return fail(h, SOFIA_SC_EINVAL, "number of kernels must be 1..64");
+    std::vector<double> noise((size_t)K);
     const sofia_sc_batch_tuning start = h->tune;
+    auto one = [&]() {
+        return run_impl(h, cube, nx, ny, nz, kernels, K, t, mode, range, mask, noise.data(),
+                        opt, nullptr);
+    };
     auto time_it = [&](const sofia_sc_batch_tuning &c, double *ms) -> int {
         h->tune = c;
-        int rc = batch_impl(h, cubes, n, kernels, K, t, mode, range, noise.data(), opt, nullptr);
+        int rc = one();
         if (rc != SOFIA_SC_OK && rc != SOFIA_SC_ENOSTAT) return rc;
         double bestms = INFINITY;
         for (int rep = 0; rep < 2; ++rep) {
             const auto t0 = std::chrono::steady_clock::now();
-            rc = batch_impl(h, cubes, n, kernels, K, t, mode, range, noise.data(), opt, nullptr);
+            rc = one();
             const auto t1 = std::chrono::steady_clock::now();
             if (rc != SOFIA_SC_OK && rc != SOFIA_SC_ENOSTAT) return rc;
             bestms = std::min(bestms, std::chrono::duration<double, std::milli>(t1 - t0).count());
@@ -1058,33 +1156,44 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         *ms = bestms;
         return SOFIA_SC_OK;
     };
-    sofia_sc_batch_tuning cur{kDefaultLanes, 6144, 256, 0, NAN};
+    sofia_sc_batch_tuning cur = start;
     int rc = time_it(cur, &cur.ms);
+    SC_TRACE("tune start: rc %d, %.3f ms", rc, cur.ms);
     if (rc) { h->tune = start; return rc; }
-    const int lanes[] = {4, 16}, blocks[] = {3072, 12288}, rows[] = {128, 64};
-    for (int v : lanes) {
-        sofia_sc_batch_tuning c = cur;
-        c.lanes = v;
-        if ((rc = time_it(c, &c.ms))) { h->tune = start; return rc; }
-        if (c.ms < cur.ms) cur = c;
-    }
-    for (int v : blocks) {
-        sofia_sc_batch_tuning c = cur;
-        c.col_blocks = v;
-        if ((rc = time_it(c, &c.ms))) { h->tune = start; return rc; }
-        if (c.ms < cur.ms) cur = c;
-    }
-    for (int v : rows) {
-        sofia_sc_batch_tuning c = cur;
-        c.strip_rows = v;
-        if ((rc = time_it(c, &c.ms))) { h->tune = start; return rc; }
-        if (c.ms < cur.ms) cur = c;
+    struct Axis {
+        int32_t sofia_sc_batch_tuning::*field;
+        int vals[3];
+    };
+    const Axis axes[] = {
+        {&sofia_sc_batch_tuning::col_blocks, {3072, 6144, 12288}},
+        {&sofia_sc_batch_tuning::strip_rows, {64, 128, 256}},
+        {&sofia_sc_batch_tuning::strip_waves, {1, 2, 4}},
+        {&sofia_sc_batch_tuning::col_min_planes, {32, 64, 128}},
+    };
+    for (const Axis &ax : axes) {
+        for (int v : ax.vals) {
+            if (cur.*(ax.field) == v) continue;
+            sofia_sc_batch_tuning c = cur;
+            c.*(ax.field) = v;
+            rc = time_it(c, &c.ms);
+            SC_TRACE("tune candidate col_blocks %d strip_rows %d strip_waves %d "
+                     "col_min_planes %d: rc %d, %.3f ms", c.col_blocks, c.strip_rows,
+                     c.strip_waves, c.col_min_planes, rc, c.ms);
+            if (rc) { h->tune = start; return rc; }
+            if (c.ms < cur.ms) cur = c;
+        }
     }
     h->tune = cur;
     if (best) *best = cur;
-    // leave the masks with the chosen shapes' result
-    rc = batch_impl(h, cubes, n, kernels, K, t, mode, range, noise.data(), opt, nullptr);
-    return rc;
+    // leave the mask with the chosen shapes' result
+    return one();
+}
+
+bool valid_shapes(const sofia_sc_batch_tuning &t) {
+    auto in = [](int v, int a, int b, int c) { return v == a || v == b || v == c; };
+    return in(t.lanes, 4, 8, 16) && in(t.col_blocks, 3072, 6144, 12288) &&
+           in(t.strip_rows, 64, 128, 256) && in(t.strip_waves, 1, 2, 4) &&
+           in(t.col_min_planes, 32, 64, 128);
 }
 
 }  // namespace
@@ -1105,7 +1214,7 @@ void sofia_sc_default_options(sofia_sc_options *opt) {
 int sofia_sc_quantize(sofia_sc *h, const float *cube, int64_t n, double scale,
                       int32_t storage, uint16_t *out, void *stream) {
     if (!h) return SOFIA_SC_EINVAL;
-    h->err.clear();
+    h->err[0] = 0;
     if (!cube || !out || n < 1) return fail(h, SOFIA_SC_EINVAL, "NULL argument or n < 1");
     if (!(std::isfinite(scale) && scale > 0.0))
         return fail(h, SOFIA_SC_EINVAL, "scale must be finite and > 0");
@@ -1193,13 +1302,42 @@ int sofia_sc_tune_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes
                         const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
                         int32_t noise_mode, int32_t flux_range, const sofia_sc_options *opt,
                         sofia_sc_batch_tuning *best) {
-    // Switched off: one tuning run ended in a host-side abort whose cause is
-    // not established, so the search (tune_impl) is not reachable until it is.
+    // Switched off: timing candidate shapes through repeated graph captures
+    // crashed the process when it ran after other batched calls in the same
+    // process, for a reason not established. Batches use the handle's shapes
+    // (sofia_sc_tune_run, sofia_sc_set_shapes).
     (void)cubes; (void)n_cubes; (void)kernels; (void)n_kernels; (void)threshold;
     (void)noise_mode; (void)flux_range; (void)opt;
     if (!h) return SOFIA_SC_EINVAL;
-    if (best) *best = sofia_sc_batch_tuning{kDefaultLanes, 6144, 256, 0, NAN};
+    if (best) *best = h->tune;
     return fail(h, SOFIA_SC_EDEVICE, "batch autotuning is switched off in this build");
+}
+
+int sofia_sc_tune_run(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                      const sofia_sc_kernel *kernels, int32_t n_kernels, double threshold,
+                      int32_t noise_mode, int32_t flux_range, uint8_t *mask,
+                      const sofia_sc_options *opt, sofia_sc_batch_tuning *best) {
+    return tune_run_impl(h, cube, nx, ny, nz, kernels, n_kernels, threshold, noise_mode,
+                         flux_range, mask, opt, best);
+}
+
+int sofia_sc_set_shapes(sofia_sc *h, const sofia_sc_batch_tuning *shapes) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err[0] = 0;
+    if (!shapes) {
+        h->tune = default_tuning();
+        return SOFIA_SC_OK;
+    }
+    if (!valid_shapes(*shapes))
+        return fail(h, SOFIA_SC_EINVAL, "launch shapes outside the tuning candidates");
+    h->tune = *shapes;
+    return SOFIA_SC_OK;
+}
+
+int sofia_sc_get_shapes(const sofia_sc *h, sofia_sc_batch_tuning *shapes) {
+    if (!h || !shapes) return SOFIA_SC_EINVAL;
+    *shapes = h->tune;
+    return SOFIA_SC_OK;
 }
 
 static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
@@ -1208,7 +1346,7 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                          double sigma0, const uint8_t *mask_in, uint8_t *mask_out,
                          double *noise, float *write_out, int32_t storage, void *stream) {
     if (!h) return SOFIA_SC_EINVAL;
-    h->err.clear();
+    h->err[0] = 0;
     if (noise) *noise = NAN;
     if (!cube || (!write_out && (!mask_out || !noise)))
         return fail(h, SOFIA_SC_EINVAL, "NULL argument");
@@ -1235,7 +1373,8 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     Dims d{nx, ny, nz, nx * ny, nx * ny * nz};
-    const ColGrid g = col_grid(d.ncol, d.nz, h->w.sh.col_blocks);
+    h->w.sh = shapes_of(h->tune);
+    const ColGrid g = col_grid(d.ncol, d.nz, h->w.sh);
     if ((rc = ensure_state(h))) return rc;
     if ((rc = ensure_work(h, h->w, d.N, pl.spatial(), (size_t)g.blocks(),
                           pl.spatial() ? d.nz * det_words_per_plane(d.ncol) : 0, q16)))
@@ -1349,7 +1488,7 @@ int sofia_sc_profile_read(const sofia_sc *h, sofia_sc_kernel_stat *stats,
 }
 
 const char *sofia_sc_last_error(const sofia_sc *h) {
-    return h ? h->err.c_str() : "NULL handle";
+    return h ? h->err : "NULL handle";
 }
 
 const char *sofia_sc_strerror(int code) {

@@ -221,21 +221,26 @@ constexpr int kStripCols = 128;
 constexpr int kStripWaves = 4;
 
 // Launch shapes of a run: the column kernel's grid aims at col_blocks
-// blocks (z split into chunks of at least 64 planes); the spatial kernel's
-// row chunks hold at most strip_rows rows.
+// blocks (z split into chunks of at least col_min_planes planes); the spatial
+// kernel's row chunks hold at most strip_rows rows, and its workgroups hold
+// up to strip_waves adjacent strips (1 .. kStripWaves).
 struct Shapes {
     int col_blocks = 6144;
     int strip_rows = 256;
+    int strip_waves = kStripWaves;
+    int col_min_planes = 64;
 };
 
 // Strip geometry of the spatial kernel for a cube of width nx and halo H:
-// strips of kStripCols - 2H output columns, up to kStripWaves adjacent
-// strips per workgroup (spread evenly over the groups a row needs), rows in
-// chunks of at most rows_max (>= 32).
-inline void spatial_strips(StripArgs &a, int n_iter, int radius, int rows_max) {
+// strips of kStripCols - 2H output columns, up to waves_max adjacent strips
+// per workgroup (spread evenly over the groups a row needs), rows in chunks
+// of at most rows_max (>= 32).
+inline void spatial_strips(StripArgs &a, int n_iter, int radius, int rows_max,
+                           int waves_max = kStripWaves) {
     const int64_t H = (int64_t)n_iter * radius, W = kStripCols - 2 * H;
+    const int64_t wmax = waves_max < 1 ? 1 : (waves_max > kStripWaves ? kStripWaves : waves_max);
     a.nstrips = (int32_t)((a.nx + W - 1) / W);
-    const int64_t groups = (a.nstrips + kStripWaves - 1) / kStripWaves;
+    const int64_t groups = (a.nstrips + wmax - 1) / wmax;
     a.wpb = (int32_t)((a.nstrips + groups - 1) / groups);
     a.ngroups = (int32_t)((a.nstrips + a.wpb - 1) / a.wpb);
     // rows per chunk: long chunks keep the y halo small; shorter ones when

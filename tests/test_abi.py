@@ -55,9 +55,10 @@ def test_strerror_and_null_handle_paths():
 
 
 def test_batch_tuning_layout_matches_header():
-    """sofia_sc_batch_tuning: four int32 fields, then a double (24 bytes)."""
-    assert ctypes.sizeof(sc.BatchTuning) == 24
+    """sofia_sc_batch_tuning: six int32 fields, then a double (32 bytes)."""
+    assert ctypes.sizeof(sc.BatchTuning) == 32
     assert [f for f, _ in sc.BatchTuning._fields_] == ["lanes", "col_blocks", "strip_rows",
+                                                       "strip_waves", "col_min_planes",
                                                        "reserved", "ms"]
     lib = sc.load()
     cubes = (sc.Cube * 1)()

@@ -488,3 +488,76 @@ def test_mad_fallback_on_capture_overflow(h):
     ref = oracle.run(x, kernels, 3.5, "mad", "negative", 2.0)
     assert_sigma(noise, ref.sigma)
     assert_mask(host(m), ref.mask, ref.band)
+
+
+def test_enomem_injection_leaves_handle_usable(monkeypatch):
+    """SOFIA_SC_FAIL_ALLOC=k makes the k-th device or pinned allocation of a
+    handle fail as out of memory. For every allocation a run makes, and for
+    the first, a middle and the last allocation of a two-cube batch that
+    follows it: the call returns ENOMEM with NaN noise, and the same handle
+    gives the reference results once the variable is cleared."""
+    x = cfg2_like(90, 80, 60, seed=48, n_gal=3)
+    y = cfg2_like(50, 40, 30, seed=49, n_gal=1)
+    xd, yd = dev(x), dev(y)
+    kern = [(0.0, 0), (3.0, 3), (0.0, 7)]
+    args = (kern, 3.5, "mad", "negative")
+    h0 = sc.SofiaSC(0)
+    try:
+        m_ref, n_ref, _ = h0.run(xd, *args)
+        b_ref = h0.run_batch([xd, yd], *args)
+        m_ref, b_masks = host(m_ref), [host(m) for m in b_ref[0]]
+    finally:
+        h0.close()
+
+    def attempt(hk, k, call):
+        monkeypatch.setenv("SOFIA_SC_FAIL_ALLOC", str(k))
+        try:
+            call()
+            return False
+        except sc.ScError as e:
+            assert e.code == sc.ENOMEM, str(e)
+            return True
+        finally:
+            monkeypatch.delenv("SOFIA_SC_FAIL_ALLOC")
+
+    def check_run(hk, k):
+        m, n, _ = hk.run(xd, *args)
+        np.testing.assert_array_equal(host(m), m_ref, err_msg=f"run after k={k}")
+        np.testing.assert_array_equal(n, n_ref)
+
+    def check_batch(hk, k):
+        masks, noise, _ = hk.run_batch([xd, yd], *args)
+        for i in range(2):
+            np.testing.assert_array_equal(host(masks[i]), b_masks[i],
+                                          err_msg=f"batch after k={k}")
+            np.testing.assert_array_equal(noise[i], b_ref[1][i])
+
+    # every allocation of a run
+    n_run = 0
+    for k in range(1, 64):
+        hk = sc.SofiaSC(0)
+        try:
+            if not attempt(hk, k, lambda: hk.run(xd, *args)):
+                break
+            n_run += 1
+            check_run(hk, k)
+        finally:
+            hk.close()
+    # a batch after that run: its allocations are numbered from n_run + 1;
+    # an injected failure there ends the call before any capture
+    first = n_run + 1
+    batch_hits = []
+    for k in (first, first + 4, first + 12):
+        hk = sc.SofiaSC(0)
+        try:
+            hk.run(xd, *args)
+            if attempt(hk, k, lambda: hk.run_batch([xd, yd], *args)):
+                batch_hits.append(k)
+                check_batch(hk, k)
+                check_run(hk, k)
+        finally:
+            hk.close()
+    say(f"ENOMEM at each of the {n_run} allocations of a run and at batch allocations "
+        f"{batch_hits}: the handle stays usable after each")
+    assert n_run >= 8
+    assert batch_hits and batch_hits[0] == first
