@@ -129,6 +129,29 @@ int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     int32_t flux_range, uint8_t *mask, double *noise,
                     const sofia_sc_options *opt, double *sigma0);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture of their own work around the call, tight serving loops, harnesses
+ * that forbid hipMalloc. The same whole run as sofia_sc_run_ex (same
+ * arguments, options, results and errors, bit for bit), but no device or
+ * pinned-host allocation and no allocating library call: the workspace is a
+ * fixed device array of SOFIA_SC_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every device it runs on until the process ends (its address is taken
+ * once per device by sofia_sc_create). The result copy goes to the caller's
+ * pageable host memory, and the call returns after the work has completed.
+ * Every call on one GPU shares that GPU's array, whatever the handle: calls
+ * that overlap on one GPU (two host threads, or two streams) race and must
+ * not be made. Profiling (sofia_sc_profile) records nothing for these calls.
+ * EINVAL as sofia_sc_run_ex, and for a cube of more than
+ * SOFIA_SC_NOALLOC_MAX_VOXELS voxels or a shape whose workspace exceeds the
+ * array (very tall, thin cubes): the message says which. */
+#define SOFIA_SC_NOALLOC_MAX_VOXELS (1LL << 22)
+#define SOFIA_SC_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int sofia_sc_run_noalloc(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                         int64_t nz, const sofia_sc_kernel *kernels,
+                         int32_t n_kernels, double threshold, int32_t noise_mode,
+                         int32_t flux_range, uint8_t *mask, double *noise,
+                         const sofia_sc_options *opt, double *sigma0);
+
 /* One cube of a batch: device pointers, owned by the caller. */
 typedef struct {
     const float *cube;      /* float32 [nz][ny][nx], read only */

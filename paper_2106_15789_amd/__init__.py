@@ -30,7 +30,7 @@ RANGE = {"negative": -1, "all": 0, "positive": 1}
 # Every symbol include/sofia_sc.h declares.
 EXPORTS = [
     "sofia_sc_default_options", "sofia_sc_create", "sofia_sc_destroy",
-    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_batch",
+    "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_noalloc", "sofia_sc_run_batch",
     "sofia_sc_tune_batch", "sofia_sc_tune_run", "sofia_sc_set_shapes", "sofia_sc_get_shapes",
     "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
@@ -136,6 +136,7 @@ def load():
     lib.sofia_sc_run_ex.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(Kernel), i32,
                                     dbl, i32, i32, vp, ctypes.POINTER(dbl),
                                     ctypes.POINTER(Options), ctypes.POINTER(dbl)]
+    lib.sofia_sc_run_noalloc.argtypes = lib.sofia_sc_run_ex.argtypes
     lib.sofia_sc_run_batch.argtypes = [vp, ctypes.POINTER(Cube), i32, ctypes.POINTER(Kernel),
                                        i32, dbl, i32, i32, ctypes.POINTER(dbl),
                                        ctypes.POINTER(Options), ctypes.POINTER(dbl)]
@@ -161,7 +162,7 @@ def load():
     lib.sofia_sc_last_error.restype = ctypes.c_char_p
     lib.sofia_sc_strerror.argtypes = [ctypes.c_int]
     lib.sofia_sc_strerror.restype = ctypes.c_char_p
-    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex",
+    for name in ("sofia_sc_create", "sofia_sc_run", "sofia_sc_run_ex", "sofia_sc_run_noalloc",
                  "sofia_sc_run_batch",
                  "sofia_sc_tune_batch", "sofia_sc_tune_run", "sofia_sc_set_shapes",
                  "sofia_sc_get_shapes",
@@ -285,6 +286,31 @@ class SofiaSC:
                                       ctypes.byref(s0))
         if rc != OK and not (allow_nostat and rc == ENOSTAT):
             self._raise(rc, "sofia_sc_run_ex")
+        return mask, np.array(noise[:], dtype=np.float64), s0.value
+
+    def run_noalloc(self, cube, kernels, threshold: float, noise_mode: str = "mad",
+                    flux_range: str = "negative", replacement: float = 2.0, mask=None,
+                    stream=None, allow_nostat: bool = False, storage: str = "f32",
+                    sigma0: float = float("nan"), keep_input_mask: bool = False):
+        """run() through sofia_sc_run_noalloc: no device allocation by the
+        library (workspace in its fixed device scratch array). The caller
+        supplies the mask (and the cube): allocating them is the caller's."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        if mask is None:
+            raise ValueError("run_noalloc: the caller supplies the mask")
+        _check_like(mask, cube, torch.uint8, "mask")
+        K = len(kernels)
+        noise = (ctypes.c_double * K)()
+        s0 = ctypes.c_double()
+        opt = self._options(replacement, sigma0, storage, stream, keep_input_mask)
+        rc = self.lib.sofia_sc_run_noalloc(self.h, cube.data_ptr(), nx, ny, nz,
+                                           _kernels(kernels), K, float(threshold),
+                                           NOISE[noise_mode], RANGE[flux_range],
+                                           mask.data_ptr(), noise, ctypes.byref(opt),
+                                           ctypes.byref(s0))
+        if rc != OK and not (allow_nostat and rc == ENOSTAT):
+            self._raise(rc, "sofia_sc_run_noalloc")
         return mask, np.array(noise[:], dtype=np.float64), s0.value
 
     def _batch_args(self, cubes, masks):

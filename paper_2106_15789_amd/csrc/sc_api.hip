@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -123,6 +124,7 @@ struct sofia_sc {
     int device = 0;
     long allocs = 0;                 // device / pinned allocations attempted so far
     char err[512] = {0};             // last error text (fixed: setting it allocates nothing)
+    bool noalloc_call = false;       // inside sofia_sc_run_noalloc: no profiling events
     Work w;                          // workspace of run / step / smooth
     DevState *st_host = nullptr;     // pinned
     bool prof = false;
@@ -417,14 +419,14 @@ int launch(sofia_sc *h, hipStream_t s, int fam, double bytes, double vox, F &&f,
         const hipError_t e = f();
         return e == hipSuccess ? SOFIA_SC_OK : hip_fail(h, e, kFamilyName[fam]);
     }
-    if (h->prof) {
+    if (h->prof && !h->noalloc_call) {
         e0 = take_event(h);
         e1 = take_event(h);
         if (e0) (void)hipEventRecord(e0, s);
     }
     const hipError_t e = f();
     if (e != hipSuccess) return hip_fail(h, e, kFamilyName[fam]);
-    if (h->prof && e0 && e1) {
+    if (h->prof && !h->noalloc_call && e0 && e1) {
         (void)hipEventRecord(e1, s);
         h->recs.push_back({fam, bytes, vox, e0, e1, cond});
     }
@@ -1196,6 +1198,130 @@ bool valid_shapes(const sofia_sc_batch_tuning &t) {
            in(t.col_min_planes, 32, 64, 128);
 }
 
+// ---- the entry point that allocates nothing (sofia_sc_run_noalloc)
+//
+// Its workspace is carved out of `scratch`, a file-scope device array of
+// fixed size: every GPU holds its own copy, at its own address, from module
+// load to process end. Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol): sofia_sc_create looks
+// up the device address once per device with that device current and keeps
+// it in g_scratch; only that pointer is used afterwards.
+
+constexpr size_t kScratchBytes = (size_t)SOFIA_SC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Called by sofia_sc_create with the handle's device current.
+int init_scratch(sofia_sc *h) {
+    if (h->device >= kMaxDevices) return SOFIA_SC_OK;   // noalloc refuses such devices
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[h->device]) return SOFIA_SC_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(h, e, "scratch symbol address");
+    g_scratch[h->device] = ptr;
+    return SOFIA_SC_OK;
+}
+
+void *scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
+}
+
+// Lays a run's workspace out in one buffer, 256-byte aligned pieces. With
+// base == nullptr it only counts the bytes.
+struct Carver {
+    uint8_t *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+// The same buffers ensure_work grows, for one run of r, carved from base.
+size_t carve_work(Work &w, uint8_t *base, const RunSpec &r) {
+    Carver c{base};
+    const bool sp = r.any_spatial();
+    const ColGrid g = col_grid(r.d.ncol, r.d.nz, w.sh);
+    const size_t parts = (size_t)g.blocks();
+    const size_t N = (size_t)r.d.N;
+    w.st = c.take<DevState>(1);
+    w.hist = c.take<unsigned long long>(kHistWords);
+    w.wm[0] = c.take<uint8_t>(N);
+    w.wm[1] = c.take<uint8_t>(N);
+    w.wm_cap = N;
+    w.p = sp ? c.take<float>(N) : nullptr;
+    w.p_cap = sp ? N : 0;
+    w.det_cap = sp ? (size_t)(r.d.nz * det_words_per_plane(r.d.ncol)) : 0;
+    w.det = sp ? c.take<uint64_t>(w.det_cap) : nullptr;
+    w.amb_cap = amb_capacity(r.d.N);
+    w.amb = c.take<AmbEntry>(w.amb_cap);
+    w.cap_cap = capture_capacity(r.d.N);
+    w.cap_buf = c.take<uint32_t>(w.cap_cap);
+    w.part_cap = parts;
+    w.part_sum = c.take<double>(parts);
+    w.part_cnt = c.take<unsigned long long>(2 * parts);
+    const bool q16 = r.storage != SOFIA_SC_STORE_F32;
+    w.xq_cap = q16 ? N : 0;
+    w.xq = q16 ? c.take<uint16_t>(N) : nullptr;
+    return c.off;
+}
+
+int noalloc_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                 const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
+                 int32_t range, uint8_t *mask, double *noise, const sofia_sc_options *opt,
+                 double *sigma0_out) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err[0] = 0;
+    if (noise && K > 0 && K <= SOFIA_SC_MAX_KERNELS) nan_fill(noise, K);
+    if (sigma0_out) *sigma0_out = NAN;
+    if (!cube || !kernels || !mask || !noise) return fail(h, SOFIA_SC_EINVAL, "NULL argument");
+    if (K < 1 || K > SOFIA_SC_MAX_KERNELS)
+        return fail(h, SOFIA_SC_EINVAL, "number of kernels must be 1..64");
+    int rc;
+    if ((rc = check_options(h, opt))) return rc;
+    if ((rc = check_dims(h, nx, ny, nz))) return rc;
+    if ((rc = check_modes(h, t, mode, range))) return rc;
+    if (nx * ny * nz > SOFIA_SC_NOALLOC_MAX_VOXELS)
+        return fail(h, SOFIA_SC_EINVAL,
+                    "cube larger than SOFIA_SC_NOALLOC_MAX_VOXELS for sofia_sc_run_noalloc");
+    Plan plans[SOFIA_SC_MAX_KERNELS];
+    for (int k = 0; k < K; ++k)
+        if ((rc = make_plan(h, kernels[k], &plans[k]))) return rc;
+    const RunSpec r{cube, Dims{nx, ny, nz, nx * ny, nx * ny * nz}, plans, K, t, mode,
+                    range, mask, opt->replacement, opt->sigma0, opt->storage,
+                    opt->keep_input_mask != 0};
+    Work w;
+    w.sh = shapes_of(h->tune);
+    if (carve_work(w, nullptr, r) > kScratchBytes)
+        return fail(h, SOFIA_SC_EINVAL,
+                    "this cube shape needs more workspace than the no-allocation scratch "
+                    "(SOFIA_SC_NOALLOC_SCRATCH_BYTES) holds");
+    DeviceGuard dg(h->device);
+    if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
+    uint8_t *base = (uint8_t *)scratch_of(h->device);
+    if (!base) return fail(h, SOFIA_SC_EDEVICE, "no scratch address for this device");
+    carve_work(w, base, r);
+    hipStream_t s = (hipStream_t)opt->stream;
+    h->noalloc_call = true;
+    rc = enqueue_run(h, s, w, r);
+    h->noalloc_call = false;
+    if (rc) return rc;
+    DevState hs;
+    hipError_t e = hipMemcpyAsync(&hs, w.st, sizeof(DevState), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(h, e, "copy of noise values");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "stream");
+    return read_run(h, hs, r, noise, sigma0_out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1243,6 +1369,15 @@ int sofia_sc_create(sofia_sc **out, int device_ordinal) {
     sofia_sc *h = new (std::nothrow) sofia_sc();
     if (!h) return SOFIA_SC_ENOMEM;
     h->device = device_ordinal;
+    {
+        // set-up of the no-allocation scratch of this device (once per device)
+        DeviceGuard dg(device_ordinal);
+        const int rc = dg.err != hipSuccess ? SOFIA_SC_EDEVICE : init_scratch(h);
+        if (rc != SOFIA_SC_OK) {
+            delete h;
+            return rc;
+        }
+    }
     *out = h;
     return SOFIA_SC_OK;
 }
@@ -1288,6 +1423,15 @@ int sofia_sc_run_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                     const sofia_sc_options *opt, double *sigma0) {
     return run_impl(h, cube, nx, ny, nz, kernels, n_kernels, threshold, noise_mode,
                     flux_range, mask, noise, opt, sigma0);
+}
+
+int sofia_sc_run_noalloc(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
+                         int64_t nz, const sofia_sc_kernel *kernels, int32_t n_kernels,
+                         double threshold, int32_t noise_mode, int32_t flux_range,
+                         uint8_t *mask, double *noise, const sofia_sc_options *opt,
+                         double *sigma0) {
+    return noalloc_impl(h, cube, nx, ny, nz, kernels, n_kernels, threshold, noise_mode,
+                        flux_range, mask, noise, opt, sigma0);
 }
 
 int sofia_sc_run_batch(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n_cubes,
