@@ -6,6 +6,7 @@ never calls the GPU library.
 
 ``sc_oracle.cpp`` is the smooth-and-clip oracle proper (C++17, FP64, direct
 summation); ``nn_oracle.cpp`` the local noise normalisation (Sect. 4.1);
+``link_oracle.cpp`` the friends-of-friends linker (Sect. 4.3);
 ``brute.py`` is an independent dense-matrix formulation used to pin them on
 tiny cubes. Citations are to Westmeier et al. 2021 (arXiv:2106.15789).
 """
@@ -27,6 +28,7 @@ _lib = None
 # points a planted-mistake test at its copy.
 _EXTRA = {
     "nn": ("nn_oracle.cpp", "libnn_oracle.so", "NN_ORACLE_LIB"),
+    "link": ("link_oracle.cpp", "liblink_oracle.so", "LINK_ORACLE_LIB"),
 }
 _extra_libs = {}
 
@@ -77,6 +79,10 @@ def _bind_extra(name, lib):
         lib.nno_normalise.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, i32, i32,
                                       vp, vp]
         lib.nno_normalise.restype = ctypes.c_int
+    if name == "link":
+        lib.lko_link.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, i32, i32, vp,
+                                 ctypes.POINTER(i64), vp, i64]
+        lib.lko_link.restype = ctypes.c_int
     return lib
 
 
@@ -247,3 +253,25 @@ def normalise(cube: np.ndarray, w_xy: int, w_z: int, g_xy: int, g_z: int, mode: 
     if rc != 0:
         raise ValueError("nno_normalise failed (%d)" % rc)
     return sig, y
+
+
+# ----------------------------------------------------------------- linker
+
+def link(mask: np.ndarray, r_xy: int, r_z: int, min_xy: int = 0, min_z: int = 0,
+         max_xy: int = 0, max_z: int = 0):
+    """Friends-of-friends linker (Sect. 4.3): (int32 label cube, number of
+    kept detections, [n][7] int64 boxes x0, x1, y0, y1, z0, z1, voxels)."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    if m.ndim != 3:
+        raise ValueError("mask must be 3-D [nz][ny][nx]")
+    nz, ny, nx = m.shape
+    labels = np.empty(m.shape, dtype=np.int32)
+    n = ctypes.c_int64()
+    cap = int(m.sum()) + 1
+    boxes = np.empty((cap, 7), dtype=np.int64)
+    rc = _extra("link").lko_link(m.ctypes.data, nx, ny, nz, int(r_xy), int(r_z), int(min_xy),
+                                 int(min_z), int(max_xy), int(max_z), labels.ctypes.data,
+                                 ctypes.byref(n), boxes.ctypes.data, cap)
+    if rc != 0:
+        raise ValueError("lko_link failed (%d)" % rc)
+    return labels, n.value, boxes[:n.value].copy()

@@ -145,3 +145,62 @@ def normalise(cube: np.ndarray, w_xy: int, w_z: int, g_xy: int, g_z: int, mode: 
                     with np.errstate(invalid="ignore"):
                         y[np.ix_(mz, my, mx)] = (x[np.ix_(mz, my, mx)] / s).astype(np.float32)
     return sig, y
+
+
+# ----------------------------------------------------------------- linker
+
+def link(mask: np.ndarray, r_xy: int, r_z: int, min_xy: int = 0, min_z: int = 0,
+         max_xy: int = 0, max_z: int = 0):
+    """Friends-of-friends on tiny masks: every pair of detected voxels is
+    tested against the ellipsoid (scaled squared distance <= 1, radius-0
+    axes admit offset 0 only), the components come from scipy's
+    connected_components, sizes from the voxels' coordinates, and labels are
+    handed out by sorting the kept components by their smallest index."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    nz, ny, nx = mask.shape
+    idx = np.flatnonzero(mask.ravel() != 0)
+    z, y, x = idx // (nx * ny), (idx // nx) % ny, idx % nx
+    n = idx.size
+    labels = np.zeros(mask.shape, dtype=np.int32)
+    if n == 0:
+        return labels, 0, np.zeros((0, 7), dtype=np.int64)
+    dx = x[:, None] - x[None, :]
+    dy = y[:, None] - y[None, :]
+    dz = z[:, None] - z[None, :]
+    d = np.zeros((n, n))
+    ok = np.ones((n, n), dtype=bool)
+    if r_xy > 0:
+        d += (dx ** 2 + dy ** 2) / float(r_xy) ** 2
+    else:
+        ok &= (dx == 0) & (dy == 0)
+    if r_z > 0:
+        d += dz ** 2 / float(r_z) ** 2
+    else:
+        ok &= dz == 0
+    adj = ok & (d <= 1.0 + 1e-12)
+    i, j = np.nonzero(adj)
+    ncomp, comp = connected_components(coo_matrix((np.ones(i.size), (i, j)), shape=(n, n)),
+                                       directed=False)
+    kept = []
+    for c in range(ncomp):
+        sel = comp == c
+        ex = x[sel].max() - x[sel].min() + 1
+        ey = y[sel].max() - y[sel].min() + 1
+        ez = z[sel].max() - z[sel].min() + 1
+        keep = ex >= min_xy and ey >= min_xy and ez >= min_z
+        if max_xy > 0 and (ex > max_xy or ey > max_xy):
+            keep = False
+        if max_z > 0 and ez > max_z:
+            keep = False
+        if keep:
+            kept.append((idx[sel].min(), c))
+    kept.sort()
+    boxes = []
+    flat = labels.ravel()
+    for lab, (_, c) in enumerate(kept, start=1):
+        sel = comp == c
+        flat[idx[sel]] = lab
+        boxes.append([x[sel].min(), x[sel].max(), y[sel].min(), y[sel].max(), z[sel].min(),
+                      z[sel].max(), int(sel.sum())])
+    return labels, len(kept), np.array(boxes, dtype=np.int64).reshape(-1, 7)
