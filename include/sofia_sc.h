@@ -285,6 +285,44 @@ int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
 int sofia_sc_quantize(sofia_sc *h, const float *cube, int64_t n, double scale,
                       int32_t storage, uint16_t *out, void *stream);
 
+/* Local noise normalisation (Sect. 4.1, last paragraph: where the noise
+ * level is not constant, the cube is divided by the noise measured in a
+ * running window before a constant threshold is applied; the speed test of
+ * Sect. 5 uses a window of 31 pixels and 31 channels). The noise is measured
+ * on a grid: each axis is cut into blocks of grid voxels (the last block may
+ * be shorter); the window of a block is window voxels centred on the block's
+ * middle voxel (the lower middle for an even block length), clipped to the
+ * cube, spatial windows square (window_xy in x and y) and window_z long; its
+ * noise uses the smooth-and-clip estimators over the finite voxels of the
+ * flux range (RMS about zero, or 1.4826 x the median of |v| with the mean of
+ * the two central order statistics for an even count). Every voxel of a
+ * block is then divided by that noise in FP64 and rounded to float32;
+ * non-finite voxels, and every voxel of a block whose noise is not finite
+ * and > 0 (no voxel selected, or zero noise), become NaN (blanked).
+ *  cube        device, float32 [nz][ny][nx], read only (unless out == cube).
+ *  window_xy, window_z  odd window sizes, 1..SOFIA_SC_NORM_MAX_WINDOW; with
+ *              MAD noise window_xy^2 * window_z <= SOFIA_SC_NORM_MAX_MAD_VOXELS.
+ *  grid_xy, grid_z  block sizes; 0 = (window + 1) / 2 (windows of adjacent
+ *              blocks then overlap by about half).
+ *  out         device, float32 [nz][ny][nx] or NULL (noise grid only); may
+ *              equal cube (in place).
+ *  noise_grid  host, double [nbz][nby][nbx] (sofia_sc_normalise_grid gives
+ *              the counts) or NULL.
+ * Returns after the work has completed. EINVAL for NULL cube, both outputs
+ * NULL, bad dimensions, windows, grid steps or enums. */
+#define SOFIA_SC_NORM_MAX_WINDOW 255
+#define SOFIA_SC_NORM_MAX_MAD_VOXELS 32768
+int sofia_sc_normalise(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                       int32_t window_xy, int32_t window_z, int32_t grid_xy, int32_t grid_z,
+                       int32_t noise_mode, int32_t flux_range, float *out, double *noise_grid,
+                       void *stream);
+
+/* Blocks per axis of the noise grid of sofia_sc_normalise for a cube and
+ * window / grid settings (grid 0 = default). No device work. */
+int sofia_sc_normalise_grid(int64_t nx, int64_t ny, int64_t nz, int32_t window_xy,
+                            int32_t window_z, int32_t grid_xy, int32_t grid_z, int64_t *nbx,
+                            int64_t *nby, int64_t *nbz);
+
 /* Spatial cascade for a FWHM: n_iter boxcars of radius r per axis, chosen to
  * match the Gaussian variance, sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2, with
  * n_iter r (r+1) / 3 (n_iter in 3..6, r >= 1; ties go to the larger n_iter).

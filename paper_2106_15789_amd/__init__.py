@@ -21,7 +21,7 @@ HEADER = os.path.join(ROOT, "include", "sofia_sc.h")
 SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
     "sc_kernels.hip", "sc_spatial_n3.hip", "sc_spatial_n4.hip", "sc_spatial_n5.hip",
     "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip", "sc_col_selclip.hip",
-    "sc_col_clip.hip", "sc_col_write.hip", "sc_api.hip")]
+    "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
 NOISE = {"std": 0, "mad": 1}
@@ -34,6 +34,7 @@ EXPORTS = [
     "sofia_sc_tune_batch", "sofia_sc_tune_run", "sofia_sc_set_shapes", "sofia_sc_get_shapes",
     "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
+    "sofia_sc_normalise", "sofia_sc_normalise_grid",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
 ]
@@ -154,6 +155,11 @@ def load():
                                      ctypes.POINTER(dbl), ctypes.POINTER(Options)]
     lib.sofia_sc_smooth.argtypes = [vp, vp, i64, i64, i64, Kernel, dbl, dbl, vp, vp, vp]
     lib.sofia_sc_plan.argtypes = [dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.sofia_sc_normalise.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, i32, i32,
+                                       vp, vp, vp]
+    lib.sofia_sc_normalise_grid.argtypes = [i64, i64, i64, i32, i32, i32, i32,
+                                            ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                            ctypes.POINTER(i64)]
     lib.sofia_sc_quantize.argtypes = [vp, vp, i64, dbl, i32, vp, vp]
     lib.sofia_sc_profile.argtypes = [vp, ctypes.c_int]
     lib.sofia_sc_profile_read.argtypes = [vp, ctypes.POINTER(KernelStat), i32,
@@ -169,6 +175,7 @@ def load():
                  "sofia_sc_step",
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
+                 "sofia_sc_normalise", "sofia_sc_normalise_grid",
                  "sofia_sc_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -483,6 +490,36 @@ class SofiaSC:
         if rc != OK:
             self._raise(rc, "sofia_sc_smooth")
         return out
+
+    def normalise(self, cube, window_xy: int = 31, window_z: int = 31, grid_xy: int = 0,
+                  grid_z: int = 0, noise_mode: str = "mad", flux_range: str = "negative",
+                  out=None, grid: bool = True, stream=None):
+        """Local noise normalisation (Sect. 4.1). Returns (normalised cube
+        tensor or None, noise grid [nbz][nby][nbx] ndarray or None). out may
+        be the cube itself (in place); out=False skips the division."""
+        import torch
+        nx, ny, nz = _check_cube(cube)
+        if out is None:
+            out = torch.empty_like(cube)
+        elif out is not False:
+            _check_like(out, cube, torch.float32, "out")
+        g = None
+        if grid:
+            nb = [ctypes.c_int64() for _ in range(3)]
+            rc = self.lib.sofia_sc_normalise_grid(nx, ny, nz, int(window_xy), int(window_z),
+                                                  int(grid_xy), int(grid_z), *map(ctypes.byref, nb))
+            if rc != OK:
+                raise ScError(rc, "sofia_sc_normalise_grid: bad settings")
+            g = np.empty((nb[2].value, nb[1].value, nb[0].value), dtype=np.float64)
+        rc = self.lib.sofia_sc_normalise(self.h, cube.data_ptr(), nx, ny, nz, int(window_xy),
+                                         int(window_z), int(grid_xy), int(grid_z),
+                                         NOISE[noise_mode], RANGE[flux_range],
+                                         None if out is False else out.data_ptr(),
+                                         None if g is None else g.ctypes.data,
+                                         _stream_ptr(stream))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_normalise")
+        return (None if out is False else out), g
 
     def quantize(self, cube, scale: float, storage: str = "f16", out=None, stream=None):
         """The 16-bit noise-scaled copy a F16/BF16 run stores (uint16 bit patterns)."""

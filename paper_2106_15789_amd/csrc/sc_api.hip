@@ -23,13 +23,14 @@ namespace {
 enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
-    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_COUNT
+    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
+    F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
-    "clip_fixup", "batch_graph", "mask_or"};
+    "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide"};
 
 struct LaunchRec {
     int fam;
@@ -146,6 +147,8 @@ struct sofia_sc {
     bool capturing = false;          // launches are being captured: no events
     double capture_bytes = 0;
     sofia_sc_batch_tuning tune = default_tuning();
+    double *nn_sigma = nullptr;      // noise grid of the local noise normalisation
+    size_t nn_cap = 0;
 };
 
 namespace {
@@ -1198,6 +1201,64 @@ bool valid_shapes(const sofia_sc_batch_tuning &t) {
            in(t.col_min_planes, 32, 64, 128);
 }
 
+
+// ---- local noise normalisation (Sect. 4.1)
+
+int normalise_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                   int32_t wxy, int32_t wz, int32_t gxy, int32_t gz, int32_t mode,
+                   int32_t range, float *out, double *grid, void *stream) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err[0] = 0;
+    if (!cube || (!out && !grid)) return fail(h, SOFIA_SC_EINVAL, "NULL argument");
+    int rc;
+    if ((rc = check_dims(h, nx, ny, nz))) return rc;
+    if ((rc = check_modes(h, 1.0, mode, range))) return rc;
+    auto odd_ok = [](int32_t w) { return w >= 1 && w <= SOFIA_SC_NORM_MAX_WINDOW && (w & 1); };
+    if (!odd_ok(wxy) || !odd_ok(wz))
+        return fail(h, SOFIA_SC_EINVAL, "window sizes must be odd, 1..SOFIA_SC_NORM_MAX_WINDOW");
+    if (gxy == 0) gxy = (wxy + 1) / 2;
+    if (gz == 0) gz = (wz + 1) / 2;
+    if (gxy < 1 || gz < 1 || gxy > 65536 || gz > 65536)
+        return fail(h, SOFIA_SC_EINVAL, "grid steps must be 0 (default) or 1..65536");
+    if (mode == SOFIA_SC_NOISE_MAD && (int64_t)wxy * wxy * wz > kNormMaxWindow)
+        return fail(h, SOFIA_SC_EINVAL,
+                    "MAD window larger than SOFIA_SC_NORM_MAX_MAD_VOXELS voxels");
+    NormArgs a{};
+    a.x = cube;
+    a.y = out;
+    a.nx = nx; a.ny = ny; a.nz = nz;
+    a.wxy = wxy; a.wz = wz; a.gxy = gxy; a.gz = gz;
+    a.nbx = (int32_t)((nx + gxy - 1) / gxy);
+    a.nby = (int32_t)((ny + gxy - 1) / gxy);
+    a.nbz = (int32_t)((nz + gz - 1) / gz);
+    a.range = range;
+    const int64_t nb = (int64_t)a.nbx * a.nby * a.nbz;
+    if (nb > 0x7fffffffLL) return fail(h, SOFIA_SC_EINVAL, "noise grid too large");
+    DeviceGuard dg(h->device);
+    if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
+    if ((rc = grow(h, h->nn_sigma, h->nn_cap, (size_t)nb, "noise grid", nullptr))) return rc;
+    a.sigma = h->nn_sigma;
+    hipStream_t s = (hipStream_t)stream;
+    const double N = (double)nx * ny * nz;
+    SC_TRACE("normalise %lldx%lldx%lld, window %d/%d, grid %d/%d, %lld blocks", (long long)nx,
+             (long long)ny, (long long)nz, wxy, wz, gxy, gz, (long long)nb);
+    rc = launch(h, s, F_NORM_NOISE, 4.0 * N + 8.0 * nb, N,
+                [&] { return launch_window_noise(mode, a, s); });
+    if (rc) return rc;
+    if (out) {
+        rc = launch(h, s, F_NORM_DIVIDE, 8.0 * N + 8.0 * nb, N,
+                    [&] { return launch_norm_divide(a, s); });
+        if (rc) return rc;
+    }
+    hipError_t e;
+    if (grid && (e = hipMemcpyAsync(grid, a.sigma, (size_t)nb * sizeof(double),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(h, e, "copy of the noise grid");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "stream");
+    if (h->prof) collect_profile(h);
+    return SOFIA_SC_OK;
+}
+
 // ---- the entry point that allocates nothing (sofia_sc_run_noalloc)
 //
 // Its workspace is carved out of `scratch`, a file-scope device array of
@@ -1397,6 +1458,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->st_host) (void)hipHostFree(h->st_host);
         if (h->bst) (void)hipFree(h->bst);
         if (h->bst_host) (void)hipHostFree(h->bst_host);
+        if (h->nn_sigma) (void)hipFree(h->nn_sigma);
         for (int l = 0; l < kBatchLanes; ++l) {
             if (h->lane_s[l]) (void)hipStreamDestroy(h->lane_s[l]);
             if (h->join_ev[l]) (void)hipEventDestroy(h->join_ev[l]);
@@ -1595,6 +1657,27 @@ int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     return single_kernel(h, cube, nx, ny, nz, kernel, 1.0, SOFIA_SC_NOISE_STD,
                          SOFIA_SC_FLUX_ALL, replacement, sigma0, mask_in, nullptr,
                          nullptr, out, SOFIA_SC_STORE_F32, stream);
+}
+
+int sofia_sc_normalise(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
+                       int32_t window_xy, int32_t window_z, int32_t grid_xy, int32_t grid_z,
+                       int32_t noise_mode, int32_t flux_range, float *out, double *noise_grid,
+                       void *stream) {
+    return normalise_impl(h, cube, nx, ny, nz, window_xy, window_z, grid_xy, grid_z,
+                          noise_mode, flux_range, out, noise_grid, stream);
+}
+
+int sofia_sc_normalise_grid(int64_t nx, int64_t ny, int64_t nz, int32_t window_xy,
+                            int32_t window_z, int32_t grid_xy, int32_t grid_z, int64_t *nbx,
+                            int64_t *nby, int64_t *nbz) {
+    if (!nbx || !nby || !nbz || nx < 1 || ny < 1 || nz < 1) return SOFIA_SC_EINVAL;
+    if (grid_xy == 0) grid_xy = (window_xy + 1) / 2;
+    if (grid_z == 0) grid_z = (window_z + 1) / 2;
+    if (grid_xy < 1 || grid_z < 1) return SOFIA_SC_EINVAL;
+    *nbx = (nx + grid_xy - 1) / grid_xy;
+    *nby = (ny + grid_xy - 1) / grid_xy;
+    *nbz = (nz + grid_z - 1) / grid_z;
+    return SOFIA_SC_OK;
 }
 
 int sofia_sc_plan(double spatial_fwhm_px, int32_t *n_iter, int32_t *radius) {

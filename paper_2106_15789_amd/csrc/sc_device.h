@@ -47,6 +47,15 @@ __device__ __forceinline__ void buf_st_u8(uint8_t v, __amdgpu_buffer_rsrc_t r, u
     __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)voff, (int)soff, 0);
 }
 
+// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
+// b % 8). Remap so that each XCD works through one contiguous range of
+// workgroups: neighbouring row chunks then share their halo rows through the
+// same L2 instead of fetching them from HBM once per XCD.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t q = nb / 8, r = nb % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
 __device__ __forceinline__ bool in_flux_range(double s, int range) {
     return range < 0 ? (s < 0.0) : (range > 0 ? (s > 0.0) : true);
 }

@@ -150,6 +150,58 @@ struct StripArgs {
     const DevState *st;
 };
 
+// Arguments of the local noise normalisation (sc_norm.hip). The noise is
+// measured per block of a grid (gxy x gxy x gz voxels) in a window of
+// wxy x wxy x wz voxels around the block's centre; every voxel of a block is
+// then divided by that noise.
+struct NormArgs {
+    const float *x;              // input cube
+    float *y;                    // normalised cube (may equal x)
+    double *sigma;               // [nbz][nby][nbx] noise per block
+    int64_t nx, ny, nz;
+    int32_t wxy, wz;             // window sizes (odd)
+    int32_t gxy, gz;             // grid steps
+    int32_t nbx, nby, nbz;       // blocks per axis
+    int32_t range;               // -1 negative, 0 all, +1 positive
+};
+
+// Largest window (voxels) whose keys the exact-median kernel stages in LDS.
+constexpr int kNormMaxWindow = SOFIA_SC_NORM_MAX_MAD_VOXELS;
+constexpr int kNormThreads = 1024;
+
+hipError_t launch_window_noise(int mode, const NormArgs &a, hipStream_t s);
+hipError_t launch_norm_divide(const NormArgs &a, hipStream_t s);
+
+// Arguments of the linker (sc_link.hip). L is the caller's int32 label cube,
+// used as the union-find forest; off[] holds the forward half of the
+// friends' offsets, each packed as (dx + 128) | (dy + 128) << 8 | (dz + 128) << 16.
+constexpr int kLinkMaxOffsets = 160;
+struct LinkArgs {
+    const uint8_t *mask;
+    int *L;
+    int *box;                    // [nc][8]: x0, x1, y0, y1, z0, z1, count, pad
+    int *label_of;               // [nc]: label of each detection, 0 = dropped
+    int64_t nx, ny, nz;
+    int32_t min_xy, min_z, max_xy, max_z;
+    int32_t n_off;
+    int32_t off[kLinkMaxOffsets];
+};
+
+hipError_t launch_link_init(const uint8_t *mask, int *L, int64_t n, hipStream_t s);
+hipError_t launch_link_union(const LinkArgs &a, hipStream_t s);
+hipError_t launch_link_flatten(int *L, int64_t n, hipStream_t s);
+// Blocks of the count / assign steps over n items.
+int64_t link_scan_blocks(int64_t n);
+// Count flagged items per block (roots, or kept detections) and scan the
+// counts in place; counts[blocks] receives the total.
+hipError_t launch_link_number(bool roots, const LinkArgs &a, int64_t n, int *counts,
+                              hipStream_t s);
+hipError_t launch_link_assign(bool roots, const LinkArgs &a, int64_t n, const int *counts,
+                              hipStream_t s);
+hipError_t launch_link_resolve(const LinkArgs &a, int64_t nc, hipStream_t s);
+hipError_t launch_link_label(const LinkArgs &a, hipStream_t s);
+hipError_t launch_link_boxes_out(const LinkArgs &a, int64_t nc, long long *out, hipStream_t s);
+
 // ---- launchers (sc_kernels.hip). Each returns the launch's hipError_t.
 hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
                             int64_t n, hipStream_t s);

@@ -86,15 +86,6 @@ __device__ __forceinline__ void box_pairs(float &c0, float &c1) {
     }
 }
 
-// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
-// b % 8). Remap so that each XCD works through one contiguous range of
-// workgroups: neighbouring row chunks then share their halo rows through the
-// same L2 instead of fetching them from HBM once per XCD.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
-    const int64_t q = nb / 8, r = nb % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
-}
-
 template <int R, int NIT, int XT, bool RP>
 __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
     constexpr int H = R * NIT;

@@ -143,3 +143,26 @@ def test_fullsize_gpu_forced_chain(h, cfg2, xd_full, k):
         f"(outside the band {out}), detections {int(cur.sum())}")
     assert rel <= 1e-6
     assert out == 0
+
+
+def test_fullsize_noise_normalisation_bit_exact(h, cfg2, xd_full):
+    """Local noise normalisation of the 1024^3 cube with the paper's window of
+    31 pixels and 31 channels (Sect. 5), MAD on negative voxels, grid 16:
+    noise grid and normalised cube equal to the oracle's bit for bit. Then the
+    first S+C iteration on the normalised cube against the oracle."""
+    wl, x, s0, m1, band1 = cfg2
+    sig_ref, y_ref = oracle.normalise(x, 31, 31, 16, 16, "mad", "negative")
+    y, sig = h.normalise(xd_full, 31, 31, 16, 16, "mad", "negative")
+    np.testing.assert_array_equal(sig, sig_ref)
+    yh = y.cpu().numpy()
+    np.testing.assert_array_equal(yh, y_ref)
+    fin = np.isfinite(sig_ref)
+    say(f"full-size normalisation: grid {sig.shape}, sigma {sig_ref[fin].min():.3f}.."
+        f"{sig_ref[fin].max():.3f}, equal bit for bit")
+    ref = oracle.step(y_ref, 0.0, 0, 3.5, "mad", "negative")
+    out, s1 = h.step(y, (0.0, 0), 3.5, "mad", "negative", -1.0, float("nan"))
+    g = out.cpu().numpy()
+    assert abs(s1 / ref.sigma - 1) <= 1e-6
+    assert int(((g != ref.mask) & (ref.band == 0)).sum()) == 0
+    say(f"  first S+C step on the normalised cube: sigma {s1:.6f} (oracle {ref.sigma:.6f}), "
+        f"{int(g.sum())} detections vs {int(m1.sum())} before normalisation")
