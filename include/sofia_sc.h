@@ -323,6 +323,33 @@ int sofia_sc_normalise_grid(int64_t nx, int64_t ny, int64_t nz, int32_t window_x
                             int32_t window_z, int32_t grid_xy, int32_t grid_z, int64_t *nbx,
                             int64_t *nby, int64_t *nbz);
 
+/* Linker (Sect. 4.3): merges the detected voxels (mask != 0) into
+ * detections by friends-of-friends: two detected voxels are friends when
+ * their offset lies in the ellipsoid (dx^2 + dy^2) / radius_xy^2 +
+ * dz^2 / radius_z^2 <= 1 (an axis of radius 0 admits offset 0 only), and a
+ * detection is a connected set of friends, spatially and spectrally alike.
+ * A detection is dropped when its bounding-box extent along x or y is below
+ * min_size_xy or along z below min_size_z, or, for max_size_xy > 0 /
+ * max_size_z > 0, above those. Kept detections are numbered 1, 2, ... in the
+ * raster order (z, y, x) of their first voxel. The mock-galaxy run of
+ * Sect. 6 uses radius 2 and minimum sizes of 8 pixels and 5 channels.
+ *  mask        device, uint8 [nz][ny][nx], read only.
+ *  labels      device, int32 [nz][ny][nx]: the detection number of every
+ *              voxel, 0 where none (also for dropped detections); used as
+ *              workspace during the call.
+ *  n_sources   host: number of kept detections.
+ *  boxes       host, int64 [box_capacity][7] or NULL: per kept detection in
+ *              label order x_min, x_max, y_min, y_max, z_min, z_max, voxel
+ *              count (the first box_capacity of them).
+ * Returns after the work has completed. EINVAL for NULL pointers, bad
+ * dimensions, nx*ny*nz >= 2^31, radii outside 0..SOFIA_SC_LINK_MAX_RADIUS or
+ * negative sizes. */
+#define SOFIA_SC_LINK_MAX_RADIUS 4
+int sofia_sc_link(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                  int32_t radius_xy, int32_t radius_z, int32_t min_size_xy, int32_t min_size_z,
+                  int32_t max_size_xy, int32_t max_size_z, int32_t *labels, int64_t *n_sources,
+                  int64_t *boxes, int64_t box_capacity, void *stream);
+
 /* Spatial cascade for a FWHM: n_iter boxcars of radius r per axis, chosen to
  * match the Gaussian variance, sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2, with
  * n_iter r (r+1) / 3 (n_iter in 3..6, r >= 1; ties go to the larger n_iter).

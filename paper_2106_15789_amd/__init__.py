@@ -21,7 +21,7 @@ HEADER = os.path.join(ROOT, "include", "sofia_sc.h")
 SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
     "sc_kernels.hip", "sc_spatial_n3.hip", "sc_spatial_n4.hip", "sc_spatial_n5.hip",
     "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip", "sc_col_selclip.hip",
-    "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_api.hip")]
+    "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_link.hip", "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
 NOISE = {"std": 0, "mad": 1}
@@ -34,7 +34,7 @@ EXPORTS = [
     "sofia_sc_tune_batch", "sofia_sc_tune_run", "sofia_sc_set_shapes", "sofia_sc_get_shapes",
     "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
-    "sofia_sc_normalise", "sofia_sc_normalise_grid",
+    "sofia_sc_normalise", "sofia_sc_normalise_grid", "sofia_sc_link",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
 ]
@@ -157,6 +157,8 @@ def load():
     lib.sofia_sc_plan.argtypes = [dbl, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.sofia_sc_normalise.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, i32, i32,
                                        vp, vp, vp]
+    lib.sofia_sc_link.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, i32, i32, vp,
+                                  ctypes.POINTER(i64), vp, i64, vp]
     lib.sofia_sc_normalise_grid.argtypes = [i64, i64, i64, i32, i32, i32, i32,
                                             ctypes.POINTER(i64), ctypes.POINTER(i64),
                                             ctypes.POINTER(i64)]
@@ -175,7 +177,7 @@ def load():
                  "sofia_sc_step",
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
-                 "sofia_sc_normalise", "sofia_sc_normalise_grid",
+                 "sofia_sc_normalise", "sofia_sc_normalise_grid", "sofia_sc_link",
                  "sofia_sc_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -520,6 +522,36 @@ class SofiaSC:
         if rc != OK:
             self._raise(rc, "sofia_sc_normalise")
         return (None if out is False else out), g
+
+    def link(self, mask, radius_xy: int = 2, radius_z: int = 2, min_size_xy: int = 0,
+             min_size_z: int = 0, max_size_xy: int = 0, max_size_z: int = 0, labels=None,
+             boxes: bool = True, stream=None):
+        """Friends-of-friends linker (Sect. 4.3). Returns (int32 label tensor,
+        number of kept detections, [n][7] int64 boxes or None)."""
+        import torch
+        if not (isinstance(mask, torch.Tensor) and mask.is_cuda and mask.dtype == torch.uint8
+                and mask.dim() == 3 and mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous 3-D uint8 CUDA tensor [nz][ny][nx]")
+        nz, ny, nx = mask.shape
+        if labels is None:
+            labels = torch.empty(mask.shape, dtype=torch.int32, device=mask.device)
+        elif not (labels.dtype == torch.int32 and labels.is_contiguous()
+                  and labels.shape == mask.shape and labels.device == mask.device):
+            raise ValueError("labels must be a contiguous int32 tensor shaped like the mask")
+        n = ctypes.c_int64()
+        cap = 0
+        out = None
+        if boxes:
+            cap = int(torch.count_nonzero(mask).item())
+            out = np.empty((max(cap, 1), 7), dtype=np.int64)
+        rc = self.lib.sofia_sc_link(self.h, mask.data_ptr(), nx, ny, nz, int(radius_xy),
+                                    int(radius_z), int(min_size_xy), int(min_size_z),
+                                    int(max_size_xy), int(max_size_z), labels.data_ptr(),
+                                    ctypes.byref(n), None if out is None else out.ctypes.data,
+                                    cap, _stream_ptr(stream))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_link")
+        return labels, n.value, (None if out is None else out[:n.value].copy())
 
     def quantize(self, cube, scale: float, storage: str = "f16", out=None, stream=None):
         """The 16-bit noise-scaled copy a F16/BF16 run stores (uint16 bit patterns)."""

@@ -24,13 +24,14 @@ enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
     F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
-    F_COUNT
+    F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
-    "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide"};
+    "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide",
+    "link_union", "link_number", "link_label"};
 
 struct LaunchRec {
     int fam;
@@ -149,6 +150,17 @@ struct sofia_sc {
     sofia_sc_batch_tuning tune = default_tuning();
     double *nn_sigma = nullptr;      // noise grid of the local noise normalisation
     size_t nn_cap = 0;
+    // linker workspace: block counts, per-detection boxes and labels, output boxes
+    int *lk_counts = nullptr;
+    size_t lk_counts_cap = 0;
+    int *lk_box = nullptr;
+    size_t lk_box_cap = 0;
+    int *lk_label = nullptr;
+    size_t lk_label_cap = 0;
+    int *lk_kcounts = nullptr;
+    size_t lk_kcounts_cap = 0;
+    long long *lk_out = nullptr;
+    size_t lk_out_cap = 0;
 };
 
 namespace {
@@ -1259,6 +1271,118 @@ int normalise_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64
     return SOFIA_SC_OK;
 }
 
+
+// ---- linker (Sect. 4.3)
+
+int link_impl(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+              int32_t rxy, int32_t rz, int32_t min_xy, int32_t min_z, int32_t max_xy,
+              int32_t max_z, int32_t *labels, int64_t *n_sources, int64_t *boxes, int64_t cap,
+              void *stream) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err[0] = 0;
+    if (n_sources) *n_sources = -1;
+    if (!mask || !labels || !n_sources || (cap > 0 && !boxes) || cap < 0)
+        return fail(h, SOFIA_SC_EINVAL, "NULL argument or negative capacity");
+    int rc;
+    if ((rc = check_dims(h, nx, ny, nz))) return rc;
+    const int64_t N = nx * ny * nz;
+    if (N > 0x7fffffffLL)
+        return fail(h, SOFIA_SC_EINVAL, "the linker takes cubes of fewer than 2^31 voxels");
+    if (rxy < 0 || rz < 0 || rxy > SOFIA_SC_LINK_MAX_RADIUS || rz > SOFIA_SC_LINK_MAX_RADIUS)
+        return fail(h, SOFIA_SC_EINVAL, "linker radii must be 0..SOFIA_SC_LINK_MAX_RADIUS");
+    if (min_xy < 0 || min_z < 0 || max_xy < 0 || max_z < 0)
+        return fail(h, SOFIA_SC_EINVAL, "size limits must be >= 0");
+    LinkArgs a{};
+    a.mask = mask;
+    a.L = labels;
+    a.nx = nx; a.ny = ny; a.nz = nz;
+    a.min_xy = min_xy; a.min_z = min_z; a.max_xy = max_xy; a.max_z = max_z;
+    // the forward half of the ellipsoid's offsets (the later voxel in raster
+    // order): each friendship is tested once, from its earlier voxel
+    const int64_t A = (int64_t)rxy * rxy, C = (int64_t)rz * rz;
+    for (int dz = 0; dz <= rz; ++dz)
+        for (int dy = -rxy; dy <= rxy; ++dy)
+            for (int dx = -rxy; dx <= rxy; ++dx) {
+                if (dz == 0 && (dy < 0 || (dy == 0 && dx <= 0))) continue;
+                const int64_t sxy = (int64_t)dx * dx + (int64_t)dy * dy, sz = (int64_t)dz * dz;
+                bool in;
+                if (rxy > 0 && rz > 0) in = sxy * C + sz * A <= A * C;
+                else if (rxy > 0) in = sz == 0 && sxy <= A;
+                else if (rz > 0) in = sxy == 0 && sz <= C;
+                else in = false;
+                if (!in) continue;
+                if (a.n_off == kLinkMaxOffsets)
+                    return fail(h, SOFIA_SC_EINVAL, "linker radii give too many offsets");
+                a.off[a.n_off++] = (dx + 128) | ((dy + 128) << 8) | ((dz + 128) << 16);
+            }
+    DeviceGuard dg(h->device);
+    if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const double Nd = (double)N;
+    SC_TRACE("link %lldx%lldx%lld, radii %d/%d, %d offsets", (long long)nx, (long long)ny,
+             (long long)nz, rxy, rz, a.n_off);
+    const int64_t nb = link_scan_blocks(N);
+    if ((rc = grow(h, h->lk_counts, h->lk_counts_cap, (size_t)nb + 1, "link counts", nullptr)))
+        return rc;
+    rc = launch(h, s, F_LINK_UNION, 5.0 * Nd, Nd, [&] { return launch_link_init(mask, labels, N, s); });
+    if (!rc) rc = launch(h, s, F_LINK_UNION, Nd, Nd, [&] { return launch_link_union(a, s); });
+    if (!rc) rc = launch(h, s, F_LINK_UNION, 4.0 * Nd, Nd, [&] { return launch_link_flatten(labels, N, s); });
+    if (!rc) rc = launch(h, s, F_LINK_NUMBER, 4.0 * Nd, Nd, [&] {
+        return launch_link_number(true, a, N, h->lk_counts, s);
+    });
+    if (rc) return rc;
+    int nc = 0;
+    hipError_t e = hipMemcpyAsync(&nc, h->lk_counts + nb, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "count of detections");
+    int n_kept = 0;
+    if (nc > 0) {
+        const int64_t nbc = link_scan_blocks(nc);
+        if ((rc = grow(h, h->lk_box, h->lk_box_cap, (size_t)nc * 8, "link boxes", nullptr)) ||
+            (rc = grow(h, h->lk_label, h->lk_label_cap, (size_t)nc, "link labels", nullptr)) ||
+            (rc = grow(h, h->lk_kcounts, h->lk_kcounts_cap, (size_t)nbc + 1, "link counts",
+                       nullptr)))
+            return rc;
+        a.box = h->lk_box;
+        a.label_of = h->lk_label;
+        rc = launch(h, s, F_LINK_NUMBER, 4.0 * Nd, Nd, [&] {
+            return launch_link_assign(true, a, N, h->lk_counts, s);
+        });
+        if (!rc) rc = launch(h, s, F_LINK_NUMBER, 4.0 * Nd, Nd, [&] {
+            return launch_link_resolve(a, nc, s);
+        });
+        if (!rc) rc = launch(h, s, F_LINK_NUMBER, 32.0 * nc, nc, [&] {
+            return launch_link_number(false, a, nc, h->lk_kcounts, s);
+        });
+        if (!rc) rc = launch(h, s, F_LINK_NUMBER, 32.0 * nc, nc, [&] {
+            return launch_link_assign(false, a, nc, h->lk_kcounts, s);
+        });
+        if (rc) return rc;
+        e = hipMemcpyAsync(&n_kept, h->lk_kcounts + nbc, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "count of kept detections");
+    }
+    rc = launch(h, s, F_LINK_LABEL, 8.0 * Nd, Nd, [&] { return launch_link_label(a, s); });
+    if (rc) return rc;
+    if (boxes && cap > 0 && n_kept > 0) {
+        if ((rc = grow(h, h->lk_out, h->lk_out_cap, (size_t)n_kept * 7, "link output boxes",
+                       nullptr)))
+            return rc;
+        rc = launch(h, s, F_LINK_LABEL, 0, 0, [&] {
+            return launch_link_boxes_out(a, nc, h->lk_out, s);
+        });
+        if (rc) return rc;
+        const int64_t nout = std::min<int64_t>(cap, n_kept);
+        e = hipMemcpyAsync(boxes, h->lk_out, (size_t)nout * 7 * sizeof(long long),
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(h, e, "copy of the boxes");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(h, e, "stream");
+    if (h->prof) collect_profile(h);
+    *n_sources = n_kept;
+    return SOFIA_SC_OK;
+}
+
 // ---- the entry point that allocates nothing (sofia_sc_run_noalloc)
 //
 // Its workspace is carved out of `scratch`, a file-scope device array of
@@ -1459,6 +1583,9 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->bst) (void)hipFree(h->bst);
         if (h->bst_host) (void)hipHostFree(h->bst_host);
         if (h->nn_sigma) (void)hipFree(h->nn_sigma);
+        void *lk[] = {h->lk_counts, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out};
+        for (void *p : lk)
+            if (p) (void)hipFree(p);
         for (int l = 0; l < kBatchLanes; ++l) {
             if (h->lane_s[l]) (void)hipStreamDestroy(h->lane_s[l]);
             if (h->join_ev[l]) (void)hipEventDestroy(h->join_ev[l]);
@@ -1665,6 +1792,14 @@ int sofia_sc_normalise(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, i
                        void *stream) {
     return normalise_impl(h, cube, nx, ny, nz, window_xy, window_z, grid_xy, grid_z,
                           noise_mode, flux_range, out, noise_grid, stream);
+}
+
+int sofia_sc_link(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
+                  int32_t radius_xy, int32_t radius_z, int32_t min_size_xy, int32_t min_size_z,
+                  int32_t max_size_xy, int32_t max_size_z, int32_t *labels, int64_t *n_sources,
+                  int64_t *boxes, int64_t box_capacity, void *stream) {
+    return link_impl(h, mask, nx, ny, nz, radius_xy, radius_z, min_size_xy, min_size_z,
+                     max_size_xy, max_size_z, labels, n_sources, boxes, box_capacity, stream);
 }
 
 int sofia_sc_normalise_grid(int64_t nx, int64_t ny, int64_t nz, int32_t window_xy,

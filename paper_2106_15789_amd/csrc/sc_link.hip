@@ -1,0 +1,335 @@
+// Linker (Westmeier et al. 2021, Sect. 4.3): the detected voxels of the mask
+// are merged into detections by friends-of-friends over a merging radius,
+// spatially and spectrally alike, each detection gets a unique identifier,
+// and detections outside the spatial and spectral size limits are dropped.
+// Friends are the voxels whose offset lies in the ellipsoid
+// (dx^2 + dy^2) / r_xy^2 + dz^2 / r_z^2 <= 1 (an axis of radius 0 admits
+// offset 0 only); a detection's size is its bounding-box extent; kept
+// detections are numbered 1, 2, ... in the raster order of their first voxel.
+//
+// Work split (the label cube itself is the union-find forest, int32 voxel
+// indices):
+//  * k_link_init: every detected voxel its own root, -1 elsewhere;
+//  * k_link_union: one thread per voxel unites a detected voxel with its
+//    detected friends at the forward half of the offsets (the other half is
+//    the friends' own forward half). Unions hook the larger root under the
+//    smaller one with a compare-and-swap, so every tree's root ends as the
+//    smallest index of its detection: the canonical label, independent of
+//    the order in which the threads ran;
+//  * k_link_flatten: every detected voxel points straight at its root;
+//  * per-block counts, one scan and a block-local scan number the roots in
+//    raster order; k_link_resolve then gives every voxel its detection's
+//    number and accumulates the bounding boxes with atomics;
+//  * the same count/scan/assign steps number the kept detections, and
+//    k_link_label writes the final labels.
+// Forest links are read with agent-scope atomic loads: a CU's vector cache is
+// not coherent with the other CUs' writes.
+#include <limits.h>
+
+#include "sc_device.h"
+
+namespace sc {
+
+namespace {
+
+__device__ __forceinline__ int ld_link(const int *L, int i) {
+    return __hip_atomic_load(L + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of voxel x, halving the path on the way (every link only ever moves
+// to a smaller index, so a halving write never breaks a tree; writes are
+// minima, so concurrent halvings and flattening never raise a link).
+__device__ int find_root(int *L, int x) {
+    while (true) {
+        const int p = ld_link(L, x);
+        if (p == x) return x;
+        const int g = ld_link(L, p);
+        // a minimum, not a store: another thread may already have linked x
+        // closer to the root, and a link must never move away from it
+        if (g != p) atomicMin(L + x, g);
+        x = p;
+    }
+}
+
+__device__ void unite(int *L, int a, int b) {
+    while (true) {
+        a = find_root(L, a);
+        b = find_root(L, b);
+        if (a == b) return;
+        if (a > b) { const int t = a; a = b; b = t; }
+        // hook root b under the smaller root a
+        const int old = atomicCAS(L + b, b, a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
+__device__ __forceinline__ void decode_off(int code, int &dx, int &dy, int &dz) {
+    dx = (code & 255) - 128;
+    dy = ((code >> 8) & 255) - 128;
+    dz = ((code >> 16) & 255) - 128;
+}
+
+constexpr int kScanItems = 4096;    // items per block of the count / assign steps
+constexpr int kScanThreads = 1024;  // 4 consecutive items per thread
+
+// Exclusive block scan of one value per thread (kScanThreads values);
+// returns the exclusive prefix; *total gets the block's sum.
+__device__ int block_excl_scan(int v, int *buf, int *total) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    if (lane == 63) buf[wave] = x;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            const int t = buf[w];
+            buf[w] = acc;
+            acc += t;
+        }
+        buf[kScanThreads / 64] = acc;
+    }
+    __syncthreads();
+    const int ex = x - v + buf[wave];
+    *total = buf[kScanThreads / 64];
+    __syncthreads();
+    return ex;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_link_init(const uint8_t *__restrict__ mask,
+                                                   int *__restrict__ L, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        L[i] = mask[i] ? (int)i : -1;
+}
+
+__global__ __launch_bounds__(256) void k_link_union(LinkArgs a) {
+    const int64_t n = a.nx * a.ny * a.nz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (!a.mask[i]) continue;
+        const int64_t x = i % a.nx, y = (i / a.nx) % a.ny, z = i / (a.nx * a.ny);
+        for (int k = 0; k < a.n_off; ++k) {
+            int dx, dy, dz;
+            decode_off(a.off[k], dx, dy, dz);
+            const int64_t xx = x + dx, yy = y + dy, zz = z + dz;
+            if (xx < 0 || xx >= a.nx || yy < 0 || yy >= a.ny || zz < 0 || zz >= a.nz) continue;
+            const int64_t j = (zz * a.ny + yy) * a.nx + xx;
+            if (a.mask[j]) unite(a.L, (int)i, (int)j);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_link_flatten(int *L, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (ld_link(L, (int)i) < 0) continue;
+        const int r = find_root(L, (int)i);
+        // the root is the smallest index on the path: after every thread's
+        // minimum, each detected voxel links straight to its root
+        atomicMin(L + i, r);
+    }
+}
+
+// Flags of the count / assign steps: item i is a root (ROOTS) or a kept
+// detection (otherwise).
+template <bool ROOTS>
+__device__ __forceinline__ bool link_flag(const LinkArgs &a, int64_t i) {
+    if (ROOTS) return a.L[i] == (int)i;
+    const int *b = a.box + 8 * i;
+    const int ex = b[1] - b[0] + 1, ey = b[3] - b[2] + 1, ez = b[5] - b[4] + 1;
+    bool keep = ex >= a.min_xy && ey >= a.min_xy && ez >= a.min_z;
+    if (a.max_xy > 0 && (ex > a.max_xy || ey > a.max_xy)) keep = false;
+    if (a.max_z > 0 && ez > a.max_z) keep = false;
+    return keep;
+}
+
+template <bool ROOTS>
+__global__ __launch_bounds__(kScanThreads) void k_link_count(LinkArgs a, int64_t n,
+                                                             int *counts) {
+    __shared__ int buf[kScanThreads / 64 + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanItems + 4 * threadIdx.x;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < n && link_flag<ROOTS>(a, i0 + k)) ++c;
+    int total;
+    block_excl_scan(c, buf, &total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Exclusive scan of nb block counts in place (one workgroup); counts[nb]
+// receives the total.
+__global__ __launch_bounds__(kScanThreads) void k_link_scan(int *counts, int64_t nb) {
+    __shared__ int buf[kScanThreads / 64 + 1];
+    const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    int s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += counts[b];
+    int total;
+    int ex = block_excl_scan(s, buf, &total);
+    for (int64_t b = b0; b < b1; ++b) {
+        const int c = counts[b];
+        counts[b] = ex;
+        ex += c;
+    }
+    if (threadIdx.x == 0) counts[nb] = total;
+}
+
+// Roots: the detection number (raster order) into the root's own link,
+// encoded as -2 - number. Kept detections: label_of[c] = 1 + rank or 0.
+template <bool ROOTS>
+__global__ __launch_bounds__(kScanThreads) void k_link_assign(LinkArgs a, int64_t n,
+                                                              const int *offsets) {
+    __shared__ int buf[kScanThreads / 64 + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanItems + 4 * threadIdx.x;
+    bool f[4];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[k] = i0 + k < n && link_flag<ROOTS>(a, i0 + k);
+        c += f[k] ? 1 : 0;
+    }
+    int total;
+    int rank = offsets[blockIdx.x] + block_excl_scan(c, buf, &total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (i0 + k >= n) break;
+        if (ROOTS) {
+            if (f[k]) a.L[i0 + k] = -2 - rank++;
+        } else {
+            a.label_of[i0 + k] = f[k] ? 1 + rank++ : 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_link_box_init(int *box, int64_t nc) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride) {
+        int *b = box + 8 * c;
+        b[0] = INT_MAX; b[1] = -1; b[2] = INT_MAX; b[3] = -1; b[4] = INT_MAX; b[5] = -1;
+        b[6] = 0; b[7] = 0;
+    }
+}
+
+// Every detected voxel: its detection's number (from its root) and its share
+// of the detection's bounding box and voxel count.
+__global__ __launch_bounds__(256) void k_link_resolve(LinkArgs a) {
+    const int64_t n = a.nx * a.ny * a.nz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int p = a.L[i];
+        if (p == -1) continue;
+        const int code = p >= 0 ? a.L[p] : p;   // a non-root points at its root
+        const int c = -2 - code;
+        if (p >= 0) a.L[i] = code;
+        const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / (a.nx * a.ny));
+        int *b = a.box + 8 * (int64_t)c;
+        atomicMin(b + 0, x); atomicMax(b + 1, x);
+        atomicMin(b + 2, y); atomicMax(b + 3, y);
+        atomicMin(b + 4, z); atomicMax(b + 5, z);
+        atomicAdd(b + 6, 1);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_link_label(LinkArgs a) {
+    const int64_t n = a.nx * a.ny * a.nz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int p = a.L[i];
+        a.L[i] = p <= -2 ? a.label_of[-2 - p] : 0;
+    }
+}
+
+// Boxes of the kept detections in label order: x0, x1, y0, y1, z0, z1, count.
+__global__ __launch_bounds__(256) void k_link_boxes_out(LinkArgs a, int64_t nc,
+                                                        long long *out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride) {
+        const int l = a.label_of[c];
+        if (!l) continue;
+        const int *b = a.box + 8 * c;
+        long long *o = out + 7 * (int64_t)(l - 1);
+        for (int k = 0; k < 7; ++k) o[k] = b[k];
+    }
+}
+
+namespace {
+unsigned grid_of(int64_t n, int per) {
+    const int64_t g = (n + per - 1) / per;
+    return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+}  // namespace
+
+hipError_t launch_link_init(const uint8_t *mask, int *L, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_init, dim3(grid_of(n, 256)), dim3(256), 0, s, mask, L, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_union(const LinkArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_union, dim3(grid_of(a.nx * a.ny * a.nz, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_flatten(int *L, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_flatten, dim3(grid_of(n, 256)), dim3(256), 0, s, L, n);
+    return hipGetLastError();
+}
+
+int64_t link_scan_blocks(int64_t n) { return (n + kScanItems - 1) / kScanItems; }
+
+hipError_t launch_link_number(bool roots, const LinkArgs &a, int64_t n, int *counts,
+                              hipStream_t s) {
+    const int64_t nb = link_scan_blocks(n);
+    if (nb < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (roots)
+        hipLaunchKernelGGL(k_link_count<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n,
+                           counts);
+    else
+        hipLaunchKernelGGL(k_link_count<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a,
+                           n, counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_link_scan, dim3(1), dim3(kScanThreads), 0, s, counts, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_assign(bool roots, const LinkArgs &a, int64_t n, const int *counts,
+                              hipStream_t s) {
+    const int64_t nb = link_scan_blocks(n);
+    if (roots)
+        hipLaunchKernelGGL(k_link_assign<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a,
+                           n, counts);
+    else
+        hipLaunchKernelGGL(k_link_assign<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a,
+                           n, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_resolve(const LinkArgs &a, int64_t nc, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_box_init, dim3(grid_of(nc, 256)), dim3(256), 0, s, a.box, nc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_link_resolve, dim3(grid_of(a.nx * a.ny * a.nz, 256)), dim3(256), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_label(const LinkArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_label, dim3(grid_of(a.nx * a.ny * a.nz, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_boxes_out(const LinkArgs &a, int64_t nc, long long *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_boxes_out, dim3(grid_of(nc, 256)), dim3(256), 0, s, a, nc, out);
+    return hipGetLastError();
+}
+
+}  // namespace sc

@@ -166,3 +166,21 @@ def test_fullsize_noise_normalisation_bit_exact(h, cfg2, xd_full):
     assert int(((g != ref.mask) & (ref.band == 0)).sum()) == 0
     say(f"  first S+C step on the normalised cube: sigma {s1:.6f} (oracle {ref.sigma:.6f}), "
         f"{int(g.sum())} detections vs {int(m1.sum())} before normalisation")
+
+
+def test_fullsize_linker_bit_exact(h, cfg2, xd_full):
+    """The whole 12-kernel run's mask of the 1024^3 cube, linked on the GPU
+    with the mock run's settings (radius 2, minimum 8 pixels / 5 channels,
+    Sect. 6) and without size filter: labels, counts and boxes equal to the
+    oracle's."""
+    mask, _, _ = _gpu_state(h, xd_full, cfg2[0], 12)
+    md = torch.from_numpy(mask).cuda()
+    for filt in [(8, 5, 0, 0), (0, 0, 0, 0)]:
+        lab_ref, n_ref, box_ref = oracle.link(mask, 2, 2, *filt)
+        lab, n, boxes = h.link(md, 2, 2, *filt)
+        assert n == n_ref
+        np.testing.assert_array_equal(lab.cpu().numpy(), lab_ref)
+        np.testing.assert_array_equal(boxes, box_ref)
+        say(f"full-size linker {filt}: {n} detections from {int(mask.sum())} voxels, "
+            f"equal to the oracle")
+        del lab, lab_ref
