@@ -110,8 +110,13 @@ def _bind(lib):
                              ctypes.POINTER(i64)]
     lib.sco_run.argtypes = [vp, i64, i64, i64, vp, vp, i32, dbl, i32, i32,
                             dbl, vp, vp, ctypes.POINTER(dbl), vp, vp]
-    for f in (lib.sco_plan, lib.sco_smooth, lib.sco_noise, lib.sco_step,
-              lib.sco_run):
+    fns = [lib.sco_plan, lib.sco_smooth, lib.sco_noise, lib.sco_step, lib.sco_run]
+    if hasattr(lib, "sco_step_sub"):
+        lib.sco_step_sub.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, dbl, i32, i32,
+                                     i32, dbl, vp, ctypes.POINTER(dbl), vp,
+                                     ctypes.POINTER(i64)]
+        fns.append(lib.sco_step_sub)
+    for f in fns:
         f.restype = ctypes.c_int
     _lib = lib
     return _lib
@@ -180,19 +185,32 @@ class StepResult:
 
 def step(cube: np.ndarray, fwhm: float, width: int, threshold: float,
          mode: str, flux_range: str, mask_prev: Optional[np.ndarray] = None,
-         repl: float = -1.0, sigma0: float = float("nan")) -> StepResult:
-    """One S+C iteration (teacher-forcing unit): mask_prev OR new detections."""
+         repl: float = -1.0, sigma0: float = float("nan"), plane_stride: int = 1,
+         sigma_given: float = float("nan")) -> StepResult:
+    """One S+C iteration (teacher-forcing unit): mask_prev OR new detections.
+
+    plane_stride > 1 measures the noise on every plane_stride-th plane only;
+    a finite sigma_given replaces the measurement (clip of a slab with the
+    noise of the whole cube)."""
     x = _cube(cube)
     m = _mask_in(mask_prev, x.shape)
     nz, ny, nx = x.shape
     out = np.empty(x.shape, dtype=np.uint8)
     band = np.zeros(x.shape, dtype=np.uint8)
     sig, nb = ctypes.c_double(), ctypes.c_int64()
-    rc = _load().sco_step(x.ctypes.data, nx, ny, nz,
-                          None if m is None else m.ctypes.data, float(repl),
-                          float(sigma0), float(fwhm), int(width), float(threshold),
-                          NOISE[mode], RANGE[flux_range], out.ctypes.data,
-                          ctypes.byref(sig), band.ctypes.data, ctypes.byref(nb))
+    if plane_stride != 1 or not np.isnan(sigma_given):
+        rc = _load().sco_step_sub(x.ctypes.data, nx, ny, nz,
+                                  None if m is None else m.ctypes.data, float(repl),
+                                  float(sigma0), float(fwhm), int(width), float(threshold),
+                                  NOISE[mode], RANGE[flux_range], int(plane_stride),
+                                  float(sigma_given), out.ctypes.data, ctypes.byref(sig),
+                                  band.ctypes.data, ctypes.byref(nb))
+    else:
+        rc = _load().sco_step(x.ctypes.data, nx, ny, nz,
+                              None if m is None else m.ctypes.data, float(repl),
+                              float(sigma0), float(fwhm), int(width), float(threshold),
+                              NOISE[mode], RANGE[flux_range], out.ctypes.data,
+                              ctypes.byref(sig), band.ctypes.data, ctypes.byref(nb))
     if rc not in (0, ENOSTAT):
         raise ValueError("sco_step failed (%d)" % rc)
     return StepResult(out, sig.value, band, nb.value, rc)

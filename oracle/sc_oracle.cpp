@@ -307,6 +307,54 @@ int sco_step(const float *X, int64_t nx, int64_t ny, int64_t nz,
                           band_count);
 }
 
+// One S+C iteration with two variants of the noise measurement (step f):
+//  plane_stride > 1: the noise is measured on the planes z = 0, s, 2s, ...
+//    only (noise subsampling; every voxel is still clipped);
+//  sigma_given finite: no measurement, sigma_k = sigma_given (the clip of
+//    step g with a noise measured elsewhere, e.g. on the whole of a larger
+//    cube of which X is a slab).
+// Otherwise as sco_step.
+int sco_step_sub(const float *X, int64_t nx, int64_t ny, int64_t nz,
+                 const uint8_t *mask_prev, double repl, double sigma0, double fwhm,
+                 int32_t width, double t, int32_t mode, int32_t range, int32_t plane_stride,
+                 double sigma_given, uint8_t *mask_out, double *sigma_k, uint8_t *band,
+                 int64_t *band_count) {
+    if (!X || !mask_out || !sigma_k || !valid_common(nx, ny, nz, mode, range))
+        return -1;
+    if (!std::isfinite(t) || t <= 0.0 || plane_stride < 1) return -1;
+    const int64_t N = nx * ny * nz, ncol = nx * ny;
+    std::vector<double> S;
+    int rc = smooth(X, nx, ny, nz, mask_prev, repl, sigma0, fwhm, width, S);
+    if (rc != 0) return rc;
+    if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);
+    else std::memset(mask_out, 0, (size_t)N);
+    double sig = sigma_given;
+    if (!std::isfinite(sigma_given)) {
+        // step f on the sampled planes: the others are left out as if blanked
+        std::vector<double> Ssub(S);
+        for (int64_t i = 0; i < N; ++i)
+            if ((i / ncol) % plane_stride != 0) Ssub[(size_t)i] = NAN;
+        int64_t m = 0;
+        rc = noise(Ssub.data(), N, mode, range, &sig, &m);
+        if (rc != 0) { *sigma_k = sig; return rc; }
+    }
+    *sigma_k = sig;
+    // step g with that noise
+    const double T = t * sig;
+    int64_t nb = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        const double s = S[(size_t)i];
+        if (!std::isfinite(s)) continue;
+        if (std::fabs(s) > T) mask_out[i] = 1;
+        if (sig > 0.0 && std::fabs(std::fabs(s) / sig - t) <= kBandWidth) {
+            ++nb;
+            if (band) band[i] = 1;
+        }
+    }
+    if (band_count) *band_count = nb;
+    return 0;
+}
+
 // Whole S+C run over K kernels in list order. sigma0 gets the noise of the
 // unsmoothed input (NaN if replacement is off). band (optional, N bytes) is
 // the OR over k of the per-kernel boundary bands; band_count[k] its size.

@@ -45,13 +45,24 @@ MUTANTS = {
                               "(d == best_d && (n < best_n ||"),
     "fwhm_factor": ("fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)))",
                     "fwhm / std::sqrt(2.0 * std::log(2.0))"),
-    "union_dropped": ("if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);",
-                      "if (false) std::memcpy(mask_out, mask_prev, (size_t)N);"),
+    "union_dropped": ("if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);\n"
+                      "    else std::memset(mask_out, 0, (size_t)N);\n    return noise_and_clip(",
+                      "if (false) std::memcpy(mask_out, mask_prev, (size_t)N);\n"
+                      "    else std::memset(mask_out, 0, (size_t)N);\n    return noise_and_clip("),
     # the boundary band excuses mask differences in every parity test
     "band_too_wide": ("kBandWidth = 1e-5;", "kBandWidth = 1e-2;"),
     "band_too_narrow": ("kBandWidth = 1e-5;", "kBandWidth = 1e-6;"),
     "band_absolute_units": ("std::fabs(std::fabs(s) / (*sigma_k) - t) <= kBandWidth",
                             "std::fabs(std::fabs(s) - T) <= kBandWidth"),
+    # the subsampled / given-noise step
+    "sub_stride_offset": ("if ((i / ncol) % plane_stride != 0) Ssub[(size_t)i] = NAN;",
+                          "if ((i / ncol) % plane_stride != 1) Ssub[(size_t)i] = NAN;"),
+    "sub_clip_not_strict": ("if (std::fabs(s) > T) mask_out[i] = 1;",
+                            "if (std::fabs(s) >= T) mask_out[i] = 1;"),
+    "sub_band_absolute": ("std::fabs(std::fabs(s) / sig - t) <= kBandWidth",
+                          "std::fabs(std::fabs(s) - T) <= kBandWidth"),
+    "sub_union_dropped": ("    if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);\n    else std::memset(mask_out, 0, (size_t)N);\n    double sig",
+                          "    std::memset(mask_out, 0, (size_t)N);\n    double sig"),
 }
 
 

@@ -413,3 +413,45 @@ def test_boundary_band_width_and_units(t, m):
     st = oracle.step(x, 0.0, 0, t, "mad", "all")
     np.testing.assert_array_equal(st.band, res.band)
     assert st.band_count == res.band_count[0]
+
+
+def test_noise_plane_subsampling_and_given_noise():
+    """Noise subsampling (every s-th plane) equals the noise of the sub-array
+    of those planes of the oracle's own smoothed cube; the clip covers every
+    voxel. A given noise skips the measurement: the clip of step g with it.
+    Stride 1 is the plain step."""
+    x = _cfg_like(11)
+    prev = oracle.step(x, 0.0, 0, 3.5, "mad", "negative").mask
+    for f, w, stride in [(0.0, 0, 4), (3.0, 7, 3), (6.0, 3, 5)]:
+        s = oracle.smooth(x, f, w, prev, 2.0, 0.9)
+        sub, _ = oracle.noise(s[::stride], "mad", "negative")
+        st = oracle.step(x, f, w, 3.5, "mad", "negative", prev, 2.0, 0.9, plane_stride=stride)
+        assert st.sigma == sub
+        fin = np.isfinite(s)
+        with np.errstate(invalid="ignore"):
+            expect = prev | (fin & (np.abs(s) > 3.5 * sub)).astype(np.uint8)
+        np.testing.assert_array_equal(st.mask, expect)
+        full = oracle.step(x, f, w, 3.5, "mad", "negative", prev, 2.0, 0.9)
+        one = oracle.step(x, f, w, 3.5, "mad", "negative", prev, 2.0, 0.9, plane_stride=1)
+        np.testing.assert_array_equal(one.mask, full.mask)
+        assert one.sigma == full.sigma
+        given = oracle.step(x, f, w, 3.5, "mad", "negative", prev, 2.0, 0.9,
+                            sigma_given=full.sigma)
+        np.testing.assert_array_equal(given.mask, full.mask)
+        np.testing.assert_array_equal(given.band, full.band)
+        assert given.sigma == full.sigma
+
+
+def test_given_noise_clip_is_strict_and_banded():
+    """With the noise given, the clip is still strict (|s| > t sigma_k) and the
+    band still measured in units of that noise."""
+    x = np.full((4, 3, 5), 2.0, np.float32)
+    x[::2] *= -1
+    st = oracle.step(x, 0.0, 0, 1.0, "std", "all", sigma_given=2.0)
+    assert st.sigma == 2.0 and st.mask.sum() == 0 and st.band_count == x.size
+    st = oracle.step(x, 0.0, 0, 0.999, "std", "all", sigma_given=2.0)
+    assert st.mask.sum() == x.size and st.band_count == 0
+    st = oracle.step(x * np.float32(64), 0.0, 0, 1.0 + 0.8e-5, "std", "all", sigma_given=128.0)
+    assert st.band_count == x.size and st.mask.sum() == 0
+    st = oracle.step(x * np.float32(64), 0.0, 0, 1.0 + 2e-5, "std", "all", sigma_given=128.0)
+    assert st.band_count == 0
