@@ -86,6 +86,11 @@ typedef struct {
                                (default); 1: mask[i] |= 1 where the run
                                detects, every other byte keeps its value (the
                                caller's mask takes no part in the run) */
+    int32_t noise_plane_stride; /* noise subsampling: every noise (sigma_0 and
+                               each sigma_k) is measured on the planes
+                               z = 0, s, 2s, ... only; every voxel is still
+                               smoothed and clipped. 0 or 1 (default): every
+                               plane, the whole cube */
     void *stream;           /* hipStream_t to run on; NULL = null stream */
 } sofia_sc_options;
 

@@ -89,6 +89,7 @@ class Options(ctypes.Structure):
                 ("sigma0", ctypes.c_double),
                 ("storage", ctypes.c_int32),
                 ("keep_input_mask", ctypes.c_int32),
+                ("noise_plane_stride", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -268,11 +269,13 @@ class SofiaSC:
     def run(self, cube, kernels, threshold: float, noise_mode: str = "mad",
             flux_range: str = "negative", replacement: float = 2.0, mask=None,
             stream=None, allow_nostat: bool = False, storage: str = "f32",
-            sigma0: float = float("nan"), keep_input_mask: bool = False):
+            sigma0: float = float("nan"), keep_input_mask: bool = False,
+            noise_plane_stride: int = 0):
         """Whole S+C run. Returns (mask uint8 tensor, noise[K] ndarray, sigma0).
 
         keep_input_mask: OR the detections into the given mask instead of
-        overwriting it."""
+        overwriting it. noise_plane_stride: measure every noise on every n-th
+        plane only."""
         import torch
         nx, ny, nz = _check_cube(cube)
         _check_like(mask, cube, torch.uint8, "mask")
@@ -287,6 +290,7 @@ class SofiaSC:
         opt.sigma0 = float(sigma0)
         opt.storage = STORAGE[storage]
         opt.keep_input_mask = 1 if keep_input_mask else 0
+        opt.noise_plane_stride = int(noise_plane_stride)
         opt.stream = _stream_ptr(stream)
         rc = self.lib.sofia_sc_run_ex(self.h, cube.data_ptr(), nx, ny, nz,
                                       _kernels(kernels), K, float(threshold),
@@ -300,7 +304,8 @@ class SofiaSC:
     def run_noalloc(self, cube, kernels, threshold: float, noise_mode: str = "mad",
                     flux_range: str = "negative", replacement: float = 2.0, mask=None,
                     stream=None, allow_nostat: bool = False, storage: str = "f32",
-                    sigma0: float = float("nan"), keep_input_mask: bool = False):
+                    sigma0: float = float("nan"), keep_input_mask: bool = False,
+                    noise_plane_stride: int = 0):
         """run() through sofia_sc_run_noalloc: no device allocation by the
         library (workspace in its fixed device scratch array). The caller
         supplies the mask (and the cube): allocating them is the caller's."""
@@ -312,7 +317,8 @@ class SofiaSC:
         K = len(kernels)
         noise = (ctypes.c_double * K)()
         s0 = ctypes.c_double()
-        opt = self._options(replacement, sigma0, storage, stream, keep_input_mask)
+        opt = self._options(replacement, sigma0, storage, stream, keep_input_mask,
+                            noise_plane_stride)
         rc = self.lib.sofia_sc_run_noalloc(self.h, cube.data_ptr(), nx, ny, nz,
                                            _kernels(kernels), K, float(threshold),
                                            NOISE[noise_mode], RANGE[flux_range],
@@ -337,13 +343,15 @@ class SofiaSC:
             desc[i].mask = m.data_ptr()
         return desc, masks
 
-    def _options(self, replacement, sigma0, storage, stream, keep_input_mask=False):
+    def _options(self, replacement, sigma0, storage, stream, keep_input_mask=False,
+                 noise_plane_stride=0):
         opt = Options()
         self.lib.sofia_sc_default_options(ctypes.byref(opt))
         opt.replacement = float(replacement)
         opt.sigma0 = float(sigma0)
         opt.storage = STORAGE[storage]
         opt.keep_input_mask = 1 if keep_input_mask else 0
+        opt.noise_plane_stride = int(noise_plane_stride)
         opt.stream = _stream_ptr(stream)
         return opt
 
@@ -407,7 +415,8 @@ class SofiaSC:
     def run_batch(self, cubes, kernels, threshold: float, noise_mode: str = "mad",
                   flux_range: str = "negative", replacement: float = 2.0, masks=None,
                   stream=None, allow_nostat: bool = False, storage: str = "f32",
-                  sigma0: float = float("nan"), keep_input_mask: bool = False):
+                  sigma0: float = float("nan"), keep_input_mask: bool = False,
+                  noise_plane_stride: int = 0):
         """Independent S+C runs of many cubes in one graph launch.
 
         Returns (list of mask tensors, noise[n_cubes, K] ndarray, sigma0[n_cubes])."""
@@ -416,7 +425,8 @@ class SofiaSC:
         K = len(kernels)
         noise = (ctypes.c_double * (n * K))()
         s0 = (ctypes.c_double * n)()
-        opt = self._options(replacement, sigma0, storage, stream, keep_input_mask)
+        opt = self._options(replacement, sigma0, storage, stream, keep_input_mask,
+                            noise_plane_stride)
         rc = self.lib.sofia_sc_run_batch(self.h, desc, n, _kernels(kernels), K,
                                          float(threshold), NOISE[noise_mode],
                                          RANGE[flux_range], noise, ctypes.byref(opt), s0)
@@ -450,8 +460,8 @@ class SofiaSC:
     def step_ex(self, cube, kernel, threshold: float, noise_mode: str, flux_range: str,
                 mask_in=None, mask_out=None, replacement: float = 2.0,
                 sigma0: float = float("nan"), storage: str = "f32", stream=None,
-                allow_nostat: bool = False):
-        """step with options (storage among them). Returns (mask_out, noise)."""
+                allow_nostat: bool = False, noise_plane_stride: int = 0):
+        """step with options (storage, noise subsampling). Returns (mask_out, noise)."""
         import torch
         nx, ny, nz = _check_cube(cube)
         _check_like(mask_in, cube, torch.uint8, "mask_in")
@@ -464,6 +474,7 @@ class SofiaSC:
         opt.replacement = float(replacement)
         opt.sigma0 = float(sigma0)
         opt.storage = STORAGE[storage]
+        opt.noise_plane_stride = int(noise_plane_stride)
         opt.stream = _stream_ptr(stream)
         k = Kernel(float(kernel[0]), int(kernel[1]))
         rc = self.lib.sofia_sc_step_ex(self.h, cube.data_ptr(), nx, ny, nz, k,

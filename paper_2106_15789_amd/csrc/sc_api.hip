@@ -94,6 +94,7 @@ struct BatchKey {
     uint64_t sigma0_bits = 0;
     int mode = 0, range = 0, storage = 0;
     int keep = 0;                    // keep_input_mask: changes the captured launches
+    int zstride = 1;                 // noise plane stride
     int lanes = 0, col_blocks = 0, strip_rows = 0, strip_waves = 0, col_min_planes = 0;
     uint64_t work_gen = 0;
 };
@@ -500,6 +501,7 @@ struct PairJob {
                             // the packed detection bits, the spatial pass reads them
     bool det_next = false;  // the next kernel is spatial with replacement: the
                             // clip must write the packed bits
+    int zstride = 1;        // the noise is measured on every zstride-th plane
 };
 
 int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
@@ -565,6 +567,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     c.hist2 = hist2_of(w);
     c.hist2c = hist2c_of(w);
     c.cb_stride = 1;
+    c.zstride = j.zstride;
     c.cap_buf = w.cap_buf;
     c.cap_count = cap_count_of(w);
     c.cap_capacity = (unsigned long long)w.cap_cap;
@@ -773,6 +776,7 @@ struct RunSpec {
     double sigma0;        // NaN: measure
     int storage;
     bool keep;            // OR the detections into the caller's mask
+    int zstride = 1;      // noise measured on every zstride-th plane
     bool any_spatial() const {
         for (int k = 0; k < K; ++k)
             if (plans[k].spatial()) return true;
@@ -793,7 +797,14 @@ int check_options(sofia_sc *h, const sofia_sc_options *opt) {
         return fail(h, SOFIA_SC_EINVAL, "keep_input_mask must be 0 or 1");
     if (!std::isnan(opt->sigma0) && !(std::isfinite(opt->sigma0) && opt->sigma0 > 0.0))
         return fail(h, SOFIA_SC_EINVAL, "sigma0 must be NaN (measure) or finite and > 0");
+    if (opt->noise_plane_stride < 0 || opt->noise_plane_stride > (1 << 30))
+        return fail(h, SOFIA_SC_EINVAL, "noise_plane_stride must be 0..2^30");
     return SOFIA_SC_OK;
+}
+
+// Planes the noise is measured on: every plane_stride(opt)-th (0 and 1: all).
+int plane_stride(const sofia_sc_options *opt) {
+    return opt->noise_plane_stride > 1 ? opt->noise_plane_stride : 1;
 }
 
 // Workspace a run of this cube and kernel list needs.
@@ -835,6 +846,7 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     if (!given0 && (q16 || (repl_on && !first_identity))) {
         PairJob j{r.cube, nullptr, ST_F32, d, Plan{0, 0, 1}, -1, false, 0.0, r.mode, r.range,
                   r.t, have_wm ? w.wm[cur] : nullptr, nullptr, false, false, nullptr};
+        j.zstride = r.zstride;
         if ((rc = run_pair(h, s, w, j))) return rc;
     }
     int xtype = ST_F32;
@@ -859,6 +871,7 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
                   r.repl, r.mode, r.range, r.t, have_wm ? w.wm[cur] : nullptr, out, to_user,
                   k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
                   any_spatial, !last && r.plans[k + 1].spatial() && repl_on};
+        j.zstride = r.zstride;
         if ((rc = run_pair(h, s, w, j))) return rc;
         if (!last) {
             if (have_wm) cur = 1 - cur;
@@ -911,7 +924,7 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     hipStream_t s = (hipStream_t)opt->stream;
     const RunSpec r{cube, Dims{nx, ny, nz, nx * ny, nx * ny * nz}, plans.data(), K, t, mode,
                     range, mask, opt->replacement, opt->sigma0, opt->storage,
-                    opt->keep_input_mask != 0};
+                    opt->keep_input_mask != 0, plane_stride(opt)};
     if ((rc = ensure_state(h))) return rc;
     h->w.sh = shapes_of(h->tune);
     SC_TRACE("run %lldx%lldx%lld, %d kernels, storage %d, col_blocks %d, strip_rows %d",
@@ -939,7 +952,7 @@ bool same_key(const BatchKey &a, const BatchKey &b) {
             return false;
     return a.t == b.t && a.repl == b.repl && a.sigma0_bits == b.sigma0_bits &&
            a.mode == b.mode && a.range == b.range && a.storage == b.storage &&
-           a.keep == b.keep && a.lanes == b.lanes && a.col_blocks == b.col_blocks &&
+           a.keep == b.keep && a.zstride == b.zstride && a.lanes == b.lanes && a.col_blocks == b.col_blocks &&
            a.strip_rows == b.strip_rows && a.strip_waves == b.strip_waves &&
            a.col_min_planes == b.col_min_planes && a.work_gen == b.work_gen;
 }
@@ -1060,7 +1073,8 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         }
         runs.push_back(RunSpec{c.cube, Dims{c.nx, c.ny, c.nz, c.nx * c.ny, c.nx * c.ny * c.nz},
                                plans.data(), K, t, mode, range, c.mask, opt->replacement,
-                               opt->sigma0, opt->storage, opt->keep_input_mask != 0});
+                               opt->sigma0, opt->storage, opt->keep_input_mask != 0,
+                               plane_stride(opt)});
         masks.push_back(c.mask);
     }
     std::sort(masks.begin(), masks.end());
@@ -1104,6 +1118,7 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
     key.range = range;
     key.storage = opt->storage;
     key.keep = opt->keep_input_mask;
+    key.zstride = plane_stride(opt);
     key.lanes = L;
     key.col_blocks = h->tune.col_blocks;
     key.strip_rows = h->tune.strip_rows;
@@ -1483,7 +1498,7 @@ int noalloc_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t
         if ((rc = make_plan(h, kernels[k], &plans[k]))) return rc;
     const RunSpec r{cube, Dims{nx, ny, nz, nx * ny, nx * ny * nz}, plans, K, t, mode,
                     range, mask, opt->replacement, opt->sigma0, opt->storage,
-                    opt->keep_input_mask != 0};
+                    opt->keep_input_mask != 0, plane_stride(opt)};
     Work w;
     w.sh = shapes_of(h->tune);
     if (carve_work(w, nullptr, r) > kScratchBytes)
@@ -1677,7 +1692,8 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
                          int64_t nz, sofia_sc_kernel kernel, double threshold,
                          int32_t mode, int32_t range, double replacement,
                          double sigma0, const uint8_t *mask_in, uint8_t *mask_out,
-                         double *noise, float *write_out, int32_t storage, void *stream) {
+                         double *noise, float *write_out, int32_t storage, void *stream,
+                         int zstride = 1) {
     if (!h) return SOFIA_SC_EINVAL;
     h->err[0] = 0;
     if (noise) *noise = NAN;
@@ -1742,6 +1758,7 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
               write_out ? 0 : mode, write_out ? 0 : range, write_out ? 1.0 : threshold,
               w.wm[0], write_out ? nullptr : mask_out, true, false, write_out,
               pl.spatial()};
+    j.zstride = zstride;
     if ((rc = run_pair(h, s, w, j))) return rc;
     if ((rc = finish(h, s, h->st_host, w.st))) return rc;
     if (write_out) return SOFIA_SC_OK;
@@ -1771,9 +1788,11 @@ int sofia_sc_step_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
         return fail(h, SOFIA_SC_EINVAL, "options missing or of another size");
     if (opt->keep_input_mask != 0)
         return fail(h, SOFIA_SC_EINVAL, "keep_input_mask must be 0 for a single step");
+    if (opt->noise_plane_stride < 0 || opt->noise_plane_stride > (1 << 30))
+        return fail(h, SOFIA_SC_EINVAL, "noise_plane_stride must be 0..2^30");
     return single_kernel(h, cube, nx, ny, nz, kernel, threshold, noise_mode, flux_range,
                          opt->replacement, opt->sigma0, mask_in, mask_out, noise, nullptr,
-                         opt->storage, opt->stream);
+                         opt->storage, opt->stream, plane_stride(opt));
 }
 
 int sofia_sc_smooth(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,

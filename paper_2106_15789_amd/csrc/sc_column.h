@@ -170,19 +170,21 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // Per-voxel operation on the smoothed value s of output plane zo; po =
     // zo * ncol + col0 and zw = zo * wpp are kept as running sums by the
     // caller (no 64-bit multiply per plane).
-    auto consume = [&](int64_t po, int64_t zw, double s, bool blank, uint8_t wb) {
+    // zs: the output plane is one the noise is measured on (every plane
+    // unless the noise is subsampled); the clip takes every plane.
+    auto consume = [&](int64_t po, int64_t zw, double s, bool blank, uint8_t wb, bool zs) {
         if (OP == OP_STD) {
-            const bool sel = !blank & in_range(s);
+            const bool sel = !blank & in_range(s) & zs;
             acc.sum += sel ? s * s : 0.0;
             acc.cnt += sel ? 1ull : 0ull;
         } else if (OP == OP_HIST1) {
-            if (!blank & in_range(s)) {
+            if (!blank & in_range(s) & zs) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
             }
         } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
             // predicates combine bitwise: no branch per voxel
-            const bool sel = !blank & in_range(s);
+            const bool sel = !blank & in_range(s) & zs;
             const uint32_t key = __float_as_uint(fabsf((float)s));
             n_sel += sel ? 1u : 0u;
             n_below += (sel & (key < klo)) ? 1u : 0u;
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_HIST2) {
-            if (!blank & in_range(s)) {
+            if (!blank & in_range(s) & zs) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 const uint32_t k1 = key >> kL1Shift;
                 const uint32_t lo = key & (kL2Bins - 1);
@@ -297,11 +299,12 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             if (zi >= ze) break;
             if (!SPEC) {
                 const float xv = in_value(g, j);
+                const bool zs = a.zstride <= 1 || zi % a.zstride == 0;
                 if (SRC == SRC_X) {
                     const bool blank = !isfinite(xv);
-                    consume(po, zw, (double)raw_value(xv, g.b[j]), blank, g.b[j]);
+                    consume(po, zw, (double)raw_value(xv, g.b[j]), blank, g.b[j], zs);
                 } else {
-                    consume(po, zw, (double)xv, (g.b[j] & kBlank) != 0, g.b[j]);
+                    consume(po, zw, (double)xv, (g.b[j] & kBlank) != 0, g.b[j], zs);
                 }
                 continue;
             }
@@ -330,7 +333,9 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             }
             S += (double)vn - (double)vo;
             const int zo = zi - h;
-            if (zo >= z0) consume(po, zw, S * inv_w, (wb_out & kBlank) != 0, wb_out);
+            if (zo >= z0)
+                consume(po, zw, S * inv_w, (wb_out & kBlank) != 0, wb_out,
+                        a.zstride <= 1 || zo % a.zstride == 0);
         }
         // The buffer holds one more group on top of kCapFlushAt entries.
         if (capture && fill > kCapFlushAt) flush();

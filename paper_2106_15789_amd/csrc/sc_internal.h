@@ -126,7 +126,7 @@ struct ColArgs {
     unsigned long long *amb_count;
     unsigned long long amb_capacity;
     int32_t skip_if_fused;       // OP_CLIP: do nothing when st->fused_ok
-    int32_t pad2;
+    int32_t zstride;             // noise passes select voxels of every zstride-th plane only
 };
 
 // Arguments of the strip-streaming spatial kernel. A strip is 128 adjacent

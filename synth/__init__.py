@@ -198,9 +198,9 @@ def workload(name: str) -> Workload:
     if name == "large_2048x2048x4096":
         return Workload(
             name, [CubeSpec(2048, 2048, 4096, seed=4, radial=True, sigma_lo=0.8,
-                            sigma_hi=1.5, n_gal=20000)],
+                            sigma_hi=1.5, n_gal=20000, nan_border=26)],
             _pairs([0, 3, 6, 9], [0, 3, 7, 15, 31]), 3.5, "mad", "negative",
-            notes="64 GiB float32; spatially varying sigma; no blanked border")
+            notes="64 GiB float32; spatially varying sigma; 26-px NaN border (5 % of voxels)")
     if name == "batch96":
         return Workload(
             name, batch_specs(96, seed=3, xy=(96, 512), z=(128, 1024)),

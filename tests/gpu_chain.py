@@ -33,7 +33,8 @@ def say(*a):
 
 
 def forced_chain(h, xd, x, kernels, t, mode, rng_, repl, what="", storage="f32",
-                 sigma0=float("nan"), x_oracle=None, full=None, sigma_ok=None):
+                 sigma0=float("nan"), x_oracle=None, full=None, sigma_ok=None,
+                 plane_stride=1):
     """Check every iteration of the GPU run of `kernels` on cube xd (host copy
     x) against the oracle from the GPU's own previous state.
 
@@ -43,16 +44,19 @@ def forced_chain(h, xd, x, kernels, t, mode, rng_, repl, what="", storage="f32",
     full: the whole run's (mask tensor, noise, sigma_0) if already taken.
     sigma_ok(k, mask_prev, ref_sigma, gpu_sigma): replaces the 1e-6 noise
     bar (16-bit storage, where the test derives a bar of its own).
+    plane_stride: noise subsampling, on both sides.
     Returns (largest sigma relative error, band voxels summed over steps)."""
     import torch
     q16 = storage != "f32"
     xo = x if x_oracle is None else x_oracle
+    ps = plane_stride
     if full is None:
-        full = h.run(xd, kernels, t, mode, rng_, repl, storage=storage, sigma0=sigma0)
+        full = h.run(xd, kernels, t, mode, rng_, repl, storage=storage, sigma0=sigma0,
+                     noise_plane_stride=ps)
     fm, fn, fs0 = full
     if not q16 and repl >= 0 and np.isnan(sigma0):
         raw = np.where(np.isfinite(x), x, np.nan).astype(np.float64)
-        s0_ref, _ = oracle.noise(raw, mode, rng_)
+        s0_ref, _ = oracle.noise(raw[::ps], mode, rng_)
         del raw
         assert abs(fs0 / s0_ref - 1) <= SIGMA_RTOL, f"{what}: sigma_0 {fs0} vs {s0_ref}"
     unit = sigma0 if q16 else 1.0
@@ -64,13 +68,13 @@ def forced_chain(h, xd, x, kernels, t, mode, rng_, repl, what="", storage="f32",
             m_k, n_k = fm, fn
         else:
             m_k, n_k, s_k = h.run(xd, kernels[:k + 1], t, mode, rng_, repl, storage=storage,
-                                  sigma0=sigma0)
+                                  sigma0=sigma0, noise_plane_stride=ps)
             np.testing.assert_array_equal(n_k, fn[:k + 1],
                                           err_msg=f"{what}: cut run {k + 1} noise")
             assert (np.isnan(s_k) and np.isnan(fs0)) or s_k == fs0, f"{what}: cut run sigma_0"
         torch.cuda.synchronize()
         g = m_k.cpu().numpy()
-        ref = oracle.step(xo, f, w, t, mode, rng_, prev, repl, s0_oracle)
+        ref = oracle.step(xo, f, w, t, mode, rng_, prev, repl, s0_oracle, plane_stride=ps)
         rel = abs(n_k[k] / unit / ref.sigma - 1)
         diff = g != ref.mask
         out = int((diff & (ref.band == 0)).sum())

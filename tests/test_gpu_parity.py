@@ -561,3 +561,35 @@ def test_enomem_injection_leaves_handle_usable(monkeypatch):
         f"{batch_hits}: the handle stays usable after each")
     assert n_run >= 8
     assert batch_hits and batch_hits[0] == first
+
+
+@pytest.mark.parametrize("stride", [2, 5, 16])
+def test_noise_plane_subsampling(h, stride):
+    """Noise subsampling (every noise measured on the planes z = 0, s, 2s, ...
+    only; every voxel still smoothed and clipped): single steps against the
+    oracle's subsampled step in every mode, and whole runs as a GPU-forced
+    chain; a batch equals its single runs."""
+    x = cfg2_like(130, 110, 96, seed=61, n_gal=6)
+    xd = dev(x)
+    prev = (np.random.default_rng(stride).random(x.shape) < 0.02).astype(np.uint8)
+    for mode, rng_ in [("mad", "negative"), ("std", "all"), ("mad", "all")]:
+        for f, w in [(0.0, 0), (3.0, 7), (6.0, 15)]:
+            ref = oracle.step(x, f, w, 3.5, mode, rng_, prev, 2.0, 0.9, plane_stride=stride)
+            out, sk = h.step_ex(xd, (f, w), 3.5, mode, rng_, mask_in=dev(prev),
+                                replacement=2.0, sigma0=0.9, noise_plane_stride=stride)
+            assert_sigma(sk, ref.sigma, f"stride {stride} {mode} {rng_} ({f}, {w})")
+            assert_mask(host(out), ref.mask, ref.band, f"stride {stride} ({f}, {w})")
+    gpu_chain.forced_chain(h, xd, x, KERNELS_CFG2, 3.5, "mad", "negative", 2.0,
+                           what=f"subsampled run, stride {stride}", plane_stride=stride)
+    y = cfg2_like(70, 60, 50, seed=62, n_gal=2)
+    yd = dev(y)
+    singles = [h.run(c, KERNELS_CFG2[:6], 3.5, "mad", "negative", noise_plane_stride=stride)
+               for c in (xd, yd)]
+    masks, noise, s0 = h.run_batch([xd, yd], KERNELS_CFG2[:6], 3.5, "mad", "negative",
+                                   noise_plane_stride=stride)
+    for i in range(2):
+        np.testing.assert_array_equal(host(masks[i]), host(singles[i][0]))
+        np.testing.assert_array_equal(noise[i], singles[i][1])
+    # the subsampled noise differs from the whole-cube one
+    whole = h.run(xd, KERNELS_CFG2[:6], 3.5, "mad", "negative")[1]
+    assert not np.array_equal(whole, singles[0][1])

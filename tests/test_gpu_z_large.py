@@ -72,3 +72,102 @@ def test_large_plane_teacher_forced_step(h, slab, kernel):
         f"{ref.band_count}, diff {int(diff.sum())}, detections {int(ref.mask.sum())}")
     assert abs(sk / ref.sigma - 1) <= 1e-6
     assert int((diff & (ref.band == 0)).sum()) == 0
+
+
+# ---------------------------------------------------------------- whole cube
+#
+# The whole 2048 x 2048 x 4096 cube (64 GiB) in HBM, as the benchmark runs it.
+# Its noise values cannot be recomputed on the host in a test, but the noise
+# of a deterministic subsample can: with noise subsampling, the GPU measures
+# the noise of the planes z = 0, s, 2s, ... of the full-cube smoothing, and the
+# oracle smooths a slab of (w - 1) / 2 planes on each side of every sampled
+# plane, which gives that plane's smoothed values exactly (the spatial passes
+# work plane by plane, the spectral window of a plane ends within the slab).
+# The masks are checked on z-slabs teacher-forced with the GPU's own previous
+# mask, sigma_0 and sigma_k (the oracle clips the slab with the GPU's noise).
+
+@pytest.fixture(scope="module")
+def whole():
+    wl = synth.workload("large_2048x2048x4096")
+    spec = wl.cubes[0]
+    x = torch.empty(spec.shape, dtype=torch.float32, device="cuda")
+    slab = (1 << 28) // (spec.nx * spec.ny)
+    for z0 in range(0, spec.nz, slab):
+        x[z0:z0 + slab].copy_(torch.from_numpy(synth.generate(spec, z0=z0, z1=z0 + slab)))
+    torch.cuda.synchronize()
+    say(f"whole large cube generated: {tuple(x.shape)}")
+    return wl, spec, x
+
+
+def _prev(h, wl, x, k):
+    """The GPU's mask (device) and sigma_0 after its first k iterations."""
+    m, n, s0 = h.run(x, wl.kernels[:k], wl.threshold, wl.noise_mode, wl.flux_range,
+                     wl.replacement)
+    torch.cuda.synchronize()
+    return m, n, s0
+
+
+def test_large_sigma0_on_a_1_in_64_plane_subsample(h, whole):
+    wl, spec, x = whole
+    out, s_gpu = h.step_ex(x, (0.0, 0), 3.5, "mad", "negative", replacement=-1.0,
+                           noise_plane_stride=64)
+    del out
+    planes = [synth.generate(spec, z0=z, z1=z + 1) for z in range(0, spec.nz, 64)]
+    raw = np.concatenate([p.ravel() for p in planes]).astype(np.float64)
+    raw[~np.isfinite(raw)] = np.nan
+    s_ref, m = oracle.noise(raw, "mad", "negative")
+    say(f"whole cube, 1/64 planes: sigma gpu {s_gpu} oracle {s_ref} ({m} voxels)")
+    assert abs(s_gpu / s_ref - 1) <= 1e-6
+
+
+@pytest.mark.parametrize("k,stride", [(7, 512), (19, 512)])
+def test_large_sigma_k_on_a_plane_subsample(h, whole, k, stride):
+    """Kernel k of the whole-cube run, from the GPU's own state after k - 1
+    iterations: its noise over every stride-th plane on both sides."""
+    wl, spec, x = whole
+    f, w = wl.kernels[k]
+    prev, _, s0 = _prev(h, wl, x, k)
+    out, s_gpu = h.step_ex(x, (f, w), 3.5, "mad", "negative", mask_in=prev, replacement=2.0,
+                           sigma0=s0, noise_plane_stride=stride)
+    del out
+    hw = (w - 1) // 2 if w >= 3 else 0
+    vals = []
+    for z in range(0, spec.nz, stride):
+        lo, hi = max(0, z - hw), min(spec.nz, z + hw + 1)
+        xs = synth.generate(spec, z0=lo, z1=hi)
+        ms = prev[lo:hi].cpu().numpy()
+        s = oracle.smooth(xs, f, w, ms, 2.0, s0)
+        vals.append(s[z - lo].ravel())
+    s_ref, m = oracle.noise(np.concatenate(vals), "mad", "negative")
+    say(f"whole cube kernel {k} ({f}, {w}), 1/{stride} planes: sigma gpu {s_gpu} "
+        f"oracle {s_ref} ({m} voxels), rel {abs(s_gpu / s_ref - 1):.2e}")
+    assert abs(s_gpu / s_ref - 1) <= 1e-6
+    del prev
+
+
+@pytest.mark.parametrize("k", [7, 19])
+def test_large_masks_on_teacher_forced_slabs(h, whole, k):
+    """Kernel k of the whole-cube run, from the GPU's own previous mask and
+    sigma_0: the GPU's mask on three 32-plane slabs (the cube's first planes,
+    its middle, its last planes) against the oracle's clip of the slab with
+    the GPU's noise, outside the boundary band."""
+    wl, spec, x = whole
+    f, w = wl.kernels[k]
+    prev, _, s0 = _prev(h, wl, x, k)
+    out, s_k = h.step_ex(x, (f, w), 3.5, "mad", "negative", mask_in=prev, replacement=2.0,
+                         sigma0=s0)
+    hw = (w - 1) // 2 if w >= 3 else 0
+    for z0 in (0, spec.nz // 2 - 16, spec.nz - 32):
+        z1 = z0 + 32
+        lo, hi = max(0, z0 - hw), min(spec.nz, z1 + hw)
+        xs = synth.generate(spec, z0=lo, z1=hi)
+        ref = oracle.step(xs, f, w, 3.5, "mad", "negative", prev[lo:hi].cpu().numpy(), 2.0,
+                          s0, sigma_given=s_k)
+        g = out[z0:z1].cpu().numpy()
+        r = ref.mask[z0 - lo:z1 - lo]
+        band = ref.band[z0 - lo:z1 - lo]
+        diff = g != r
+        say(f"whole cube kernel {k} ({f}, {w}) slab {z0}-{z1 - 1}: {int(r.sum())} detected, "
+            f"diff {int(diff.sum())} (band {int(band.sum())})")
+        assert int((diff & (band == 0)).sum()) == 0
+    del prev, out
