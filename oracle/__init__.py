@@ -293,3 +293,17 @@ def link(mask: np.ndarray, r_xy: int, r_z: int, min_xy: int = 0, min_z: int = 0,
     if rc != 0:
         raise ValueError("lko_link failed (%d)" % rc)
     return labels, n.value, boxes[:n.value].copy()
+
+
+def param_module():
+    """The parameterisation / reliability oracle (oracle/param.py), or the
+    planted-mistake copy a test points PARAM_ORACLE_FILE at."""
+    path = os.environ.get("PARAM_ORACLE_FILE")
+    if not path:
+        from oracle import param
+        return param
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("param_mutant", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
