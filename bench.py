@@ -263,7 +263,30 @@ def extras(sc, torch, synth, stream, large_x=None, large_wl=None):
             "unit": "voxels/s", "sources": n_src,
             "family_ms": {s["name"]: s["total_ms"] / s["launches"] for s in st}}
         say(f"linker: {tl * 1e3:.1f} ms, {n_src} sources")
-        del lab
+        # parameterisation and reliability of the linker's detections
+        rec = torch.empty(max(n_src, 1) * sc.SOURCE_DTYPE.itemsize, dtype=torch.uint8,
+                          device="cuda")
+        _, n_kept = h.parameterise(x, lab, n_src, sigma_rms=s0, out=rec)
+        h.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            h.parameterise(x, lab, n_src, sigma_rms=s0, out=rec)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / 5
+        h.profile(False)
+        st = h.profile_read()
+        out["parameterise_1024cube"] = {
+            "sources": n_src, "kept": n_kept, "scale": 0.4, "rel_threshold": 0.9,
+            "snr_threshold": 2.8, "ms": tp * 1e3, "value": x.numel() / tp,
+            "unit": "voxels/s",
+            "family_ms": {s["name"]: s["total_ms"] / s["launches"] for s in st},
+            "kernel_gbs": family_gbs(st),
+            "density_pairs_per_s": {s["name"]: s["voxels"] / (s["total_ms"] * 1e-3)
+                                    for s in st if s["name"] == "reliability"
+                                    and s["total_ms"] > 0}}
+        say(f"parameterisation: {tp * 1e3:.1f} ms, {n_kept} of {n_src} kept")
+        del lab, rec
     finally:
         h.close()
     del x, m

@@ -355,6 +355,63 @@ int sofia_sc_link(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int6
                   int32_t max_size_xy, int32_t max_size_z, int32_t *labels, int64_t *n_sources,
                   int64_t *boxes, int64_t box_capacity, void *stream);
 
+/* Parameters of one detection (Sect. 4.5; Eq. 4 and 5) and its reliability
+ * (Sect. 4.4). */
+typedef struct {
+    int64_t n_vox;        /* finite voxels carrying the detection's label */
+    double sum;           /* sum of their values */
+    double peak;          /* largest value */
+    double min;           /* smallest value */
+    double mean;          /* sum / n_vox */
+    double x, y, z;       /* value-weighted centroid in pixels (NaN for sum 0) */
+    double flux;          /* channel_width / Omega x sum (Eq. 4) */
+    double flux_err;      /* sqrt(n_vox) x channel_width x sigma_rms / sqrt(Omega) (Eq. 5) */
+    double snr;           /* flux / flux_err */
+    double reliability;   /* max(0, (P - N) / P) for a positive sum, else 0 */
+    int32_t kept;         /* 1: positive, reliability and SNR at their thresholds */
+    int32_t pad;
+} sofia_sc_source;
+
+typedef struct {
+    int32_t struct_size;      /* sizeof(sofia_sc_param_options) */
+    int32_t pad;
+    double channel_width;     /* of Eq. 4 and 5 (default 1) */
+    double beam_major_px;     /* Gaussian beam FWHM in pixels; both > 0 give */
+    double beam_minor_px;     /* Omega = pi a b / (4 ln 2), else Omega = 1 */
+    double sigma_rms;         /* noise of Eq. 5 (default 1) */
+    double rel_scale;         /* kernel scale factor of the density (0.4) */
+    double rel_threshold;     /* reliability threshold (0.9) */
+    double snr_threshold;     /* integrated-SNR threshold (2.8) */
+} sofia_sc_param_options;
+
+/* Defaults of the mock-galaxy run of Sect. 6 (no beam, unit channel width
+ * and noise). */
+void sofia_sc_param_defaults(sofia_sc_param_options *opt);
+
+/* Parameterisation and reliability of detections 1..n_sources of a label
+ * cube (e.g. the linker's).
+ * Parameters: every voxel whose label l is in 1..n_sources and whose value
+ * is finite counts toward detection l. Reliability: the parameter vector of
+ * a detection with a positive sum is log10 (peak, sum, mean), with a
+ * negative sum log10 (-min, -sum, -mean); the densities P and N at a
+ * positive detection are sums over the positive and the negative detections
+ * (itself included) of exp(-d^T C^-1 d / 2), C the sample covariance
+ * (divisor n - 1) of the negative detections' vectors times rel_scale^2.
+ * With fewer than three negative detections or a C that is not positive
+ * definite, every positive detection has reliability 1. Detections with a
+ * zero sum take part in neither density.
+ *  cube      device, float [nz][ny][nx].
+ *  labels    device, int32 [nz][ny][nx]; other labels are ignored.
+ *  out       device, sofia_sc_source [n_sources], written.
+ *  n_kept    host: number of detections with kept = 1.
+ * The density costs n_sources^2 kernel evaluations. Returns after the work
+ * has completed. EINVAL for NULL pointers, bad dimensions, n_sources < 0 or
+ * >= 2^31, non-positive channel width, negative sigma_rms or scale <= 0. */
+int sofia_sc_parameterise(sofia_sc *h, const float *cube, const int32_t *labels, int64_t nx,
+                          int64_t ny, int64_t nz, int64_t n_sources,
+                          const sofia_sc_param_options *opt, sofia_sc_source *out,
+                          int64_t *n_kept, void *stream);
+
 /* Spatial cascade for a FWHM: n_iter boxcars of radius r per axis, chosen to
  * match the Gaussian variance, sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2, with
  * n_iter r (r+1) / 3 (n_iter in 3..6, r >= 1; ties go to the larger n_iter).

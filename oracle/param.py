@@ -60,11 +60,23 @@ def parameterise(cube: np.ndarray, labels: np.ndarray, n: int, channel_width: fl
                  beam=(0.0, 0.0), sigma_rms: float = 1.0) -> dict:
     """Per-detection parameters for labels 1..n (arrays of length n)."""
     x = np.asarray(cube, dtype=np.float64).ravel()
+    lab = np.asarray(labels).ravel()
+    return parameterise_voxels(np.arange(x.size), x, lab, cube.shape, n, channel_width, beam,
+                               sigma_rms)
+
+
+def parameterise_voxels(index: np.ndarray, values: np.ndarray, labels: np.ndarray, shape,
+                        n: int, channel_width: float = 1.0, beam=(0.0, 0.0),
+                        sigma_rms: float = 1.0) -> dict:
+    """parameterise() over a subset of a cube of the given shape (nz, ny, nx)
+    that holds at least every labelled voxel: their raster indices, values and
+    labels."""
+    x = np.asarray(values, dtype=np.float64).ravel()
     lab = np.asarray(labels).ravel().astype(np.int64)
     ok = (lab > 0) & (lab <= n) & np.isfinite(x)
     lab, v = lab[ok], x[ok]
-    idx = np.flatnonzero(ok)
-    nz, ny, nx = cube.shape
+    idx = np.asarray(index, dtype=np.int64).ravel()[ok]
+    nz, ny, nx = shape
     px, py, pz = idx % nx, (idx // nx) % ny, idx // (nx * ny)
     count = np.bincount(lab, minlength=n + 1)[1:]
     s = np.bincount(lab, weights=v, minlength=n + 1)[1:]
@@ -96,23 +108,33 @@ def _vectors(p: dict, sign: int) -> np.ndarray:
     return np.log10(np.stack([-p["min"], -p["sum"], -p["mean"]], axis=1))
 
 
-def reliability(p: dict, scale: float = 0.4) -> np.ndarray:
-    """Reliability of every detection (P4-P6)."""
+def reliability(p: dict, scale: float = 0.4, at=None) -> np.ndarray:
+    """Reliability of every detection (P4-P6). With `at` (detection indices)
+    only those are evaluated, the others are NaN; the densities still sum
+    over every detection."""
     s = p["sum"]
     pos, neg = s > 0, s < 0
+    only = np.ones(s.size, dtype=bool)
+    if at is not None:
+        only[:] = False
+        only[np.asarray(at, dtype=np.int64)] = True
+
+    def result(R):
+        return np.where(only, R, np.nan)
+
     R = np.zeros(s.size)
     if not pos.any():
-        return R
+        return result(R)
     vp = _vectors({k: v[pos] for k, v in p.items()}, +1)
     if neg.sum() < 3:
         R[pos] = 1.0
-        return R
+        return result(R)
     vn = _vectors({k: v[neg] for k, v in p.items()}, -1)
     cov = np.cov(vn.T, ddof=1) * scale * scale
     det = np.linalg.det(cov)
     if not (np.isfinite(det) and det > 0):
         R[pos] = 1.0
-        return R
+        return result(R)
     inv = np.linalg.inv(cov)
 
     def density(at, of):
@@ -120,17 +142,25 @@ def reliability(p: dict, scale: float = 0.4) -> np.ndarray:
         q = np.einsum("ijk,kl,ijl->ij", d, inv, d)
         return np.exp(-0.5 * q).sum(axis=1)
 
-    P = density(vp, vp)
-    N = density(vp, vn)
-    R[pos] = np.maximum(0.0, (P - N) / P)
-    return R
+    ev = pos & only
+    va = _vectors({k: v[ev] for k, v in p.items()}, +1)
+    P = density(va, vp)
+    N = density(va, vn)
+    R[ev] = np.maximum(0.0, (P - N) / P)
+    return result(R)
 
 
 def catalogue(cube, labels, n, channel_width=1.0, beam=(0.0, 0.0), sigma_rms=1.0,
               scale=0.4, rel_threshold=0.9, snr_threshold=2.8) -> dict:
     """Parameters, reliability and the kept flag (P7) of detections 1..n."""
     p = parameterise(cube, labels, n, channel_width, beam, sigma_rms)
-    p["reliability"] = reliability(p, scale)
+    return finish(p, scale, rel_threshold, snr_threshold)
+
+
+def finish(p: dict, scale=0.4, rel_threshold=0.9, snr_threshold=2.8, at=None) -> dict:
+    """Adds reliability and the kept flag (P7) to parameters p (with `at`,
+    only for those detections: see reliability())."""
+    p["reliability"] = reliability(p, scale, at)
     with np.errstate(invalid="ignore"):
         p["kept"] = ((p["sum"] > 0) & (p["reliability"] >= rel_threshold) &
                      (p["snr"] >= snr_threshold)).astype(np.int32)

@@ -21,7 +21,8 @@ HEADER = os.path.join(ROOT, "include", "sofia_sc.h")
 SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
     "sc_kernels.hip", "sc_spatial_n3.hip", "sc_spatial_n4.hip", "sc_spatial_n5.hip",
     "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip", "sc_col_selclip.hip",
-    "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_link.hip", "sc_api.hip")]
+    "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_link.hip", "sc_param.hip",
+    "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
 NOISE = {"std": 0, "mad": 1}
@@ -35,6 +36,7 @@ EXPORTS = [
     "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
     "sofia_sc_normalise", "sofia_sc_normalise_grid", "sofia_sc_link",
+    "sofia_sc_param_defaults", "sofia_sc_parameterise",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
 ]
@@ -108,6 +110,22 @@ class Cube(ctypes.Structure):
                 ("nz", ctypes.c_int64), ("mask", ctypes.c_void_p)]
 
 
+class ParamOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("channel_width", ctypes.c_double), ("beam_major_px", ctypes.c_double),
+                ("beam_minor_px", ctypes.c_double), ("sigma_rms", ctypes.c_double),
+                ("rel_scale", ctypes.c_double), ("rel_threshold", ctypes.c_double),
+                ("snr_threshold", ctypes.c_double)]
+
+
+# sofia_sc_source as a NumPy record (field names follow the parameter names
+# the oracle uses: count = n_vox).
+SOURCE_DTYPE = np.dtype([("count", "<i8"), ("sum", "<f8"), ("peak", "<f8"), ("min", "<f8"),
+                         ("mean", "<f8"), ("x", "<f8"), ("y", "<f8"), ("z", "<f8"),
+                         ("flux", "<f8"), ("flux_err", "<f8"), ("snr", "<f8"),
+                         ("reliability", "<f8"), ("kept", "<i4"), ("pad", "<i4")])
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
@@ -160,6 +178,11 @@ def load():
                                        vp, vp, vp]
     lib.sofia_sc_link.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, i32, i32, vp,
                                   ctypes.POINTER(i64), vp, i64, vp]
+    lib.sofia_sc_param_defaults.argtypes = [ctypes.POINTER(ParamOptions)]
+    lib.sofia_sc_param_defaults.restype = None
+    lib.sofia_sc_parameterise.argtypes = [vp, vp, vp, i64, i64, i64, i64,
+                                          ctypes.POINTER(ParamOptions), vp,
+                                          ctypes.POINTER(i64), vp]
     lib.sofia_sc_normalise_grid.argtypes = [i64, i64, i64, i32, i32, i32, i32,
                                             ctypes.POINTER(i64), ctypes.POINTER(i64),
                                             ctypes.POINTER(i64)]
@@ -179,7 +202,7 @@ def load():
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
                  "sofia_sc_normalise", "sofia_sc_normalise_grid", "sofia_sc_link",
-                 "sofia_sc_profile_read"):
+                 "sofia_sc_parameterise", "sofia_sc_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -563,6 +586,47 @@ class SofiaSC:
         if rc != OK:
             self._raise(rc, "sofia_sc_link")
         return labels, n.value, (None if out is None else out[:n.value].copy())
+
+    def parameterise(self, cube, labels, n: int, channel_width: float = 1.0,
+                     beam=(0.0, 0.0), sigma_rms: float = 1.0, scale: float = 0.4,
+                     rel_threshold: float = 0.9, snr_threshold: float = 2.8, out=None,
+                     stream=None):
+        """Parameters and reliability of detections 1..n (Sect. 4.4, 4.5).
+        Returns (dict of per-detection NumPy arrays keyed like SOURCE_DTYPE's
+        fields, number kept); out, if given, is a uint8 CUDA tensor of at
+        least n * SOURCE_DTYPE.itemsize bytes that receives the records."""
+        import torch
+        if not (isinstance(cube, torch.Tensor) and cube.is_cuda and cube.dtype == torch.float32
+                and cube.dim() == 3 and cube.is_contiguous()):
+            raise ValueError("cube must be a contiguous 3-D float32 CUDA tensor [nz][ny][nx]")
+        if not (isinstance(labels, torch.Tensor) and labels.dtype == torch.int32
+                and labels.is_contiguous() and labels.shape == cube.shape
+                and labels.device == cube.device):
+            raise ValueError("labels must be a contiguous int32 tensor shaped like the cube")
+        n = int(n)
+        nz, ny, nx = cube.shape
+        size = max(n, 1) * SOURCE_DTYPE.itemsize
+        if out is None:
+            out = torch.empty(size, dtype=torch.uint8, device=cube.device)
+        elif not (out.dtype == torch.uint8 and out.is_contiguous() and out.numel() >= size
+                  and out.device == cube.device):
+            raise ValueError("out must be a contiguous uint8 tensor of n records")
+        o = ParamOptions()
+        self.lib.sofia_sc_param_defaults(ctypes.byref(o))
+        o.channel_width = float(channel_width)
+        o.beam_major_px, o.beam_minor_px = float(beam[0]), float(beam[1])
+        o.sigma_rms = float(sigma_rms)
+        o.rel_scale = float(scale)
+        o.rel_threshold = float(rel_threshold)
+        o.snr_threshold = float(snr_threshold)
+        kept = ctypes.c_int64()
+        rc = self.lib.sofia_sc_parameterise(self.h, cube.data_ptr(), labels.data_ptr(), nx, ny,
+                                            nz, n, ctypes.byref(o), out.data_ptr(),
+                                            ctypes.byref(kept), _stream_ptr(stream))
+        if rc != OK:
+            self._raise(rc, "sofia_sc_parameterise")
+        rec = out[:n * SOURCE_DTYPE.itemsize].cpu().numpy().view(SOURCE_DTYPE)
+        return {k: rec[k].copy() for k in SOURCE_DTYPE.names if k != "pad"}, kept.value
 
     def quantize(self, cube, scale: float, storage: str = "f16", out=None, stream=None):
         """The 16-bit noise-scaled copy a F16/BF16 run stores (uint16 bit patterns)."""

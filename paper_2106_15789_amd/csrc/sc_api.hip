@@ -24,14 +24,14 @@ enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
     F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
-    F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_COUNT
+    F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_PARAM, F_RELIABILITY, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
     "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide",
-    "link_union", "link_number", "link_label"};
+    "link_union", "link_number", "link_label", "parameterise", "reliability"};
 
 struct LaunchRec {
     int fam;
@@ -162,6 +162,16 @@ struct sofia_sc {
     size_t lk_kcounts_cap = 0;
     long long *lk_out = nullptr;
     size_t lk_out_cap = 0;
+    // parameterisation workspace: accumulators, signs, parameter vectors,
+    // reliability state (inverse covariance, flag, kept count)
+    SrcAcc *pm_acc = nullptr;
+    size_t pm_acc_cap = 0;
+    int *pm_sign = nullptr;
+    size_t pm_sign_cap = 0;
+    double *pm_vec = nullptr;
+    size_t pm_vec_cap = 0;
+    double *pm_state = nullptr;
+    size_t pm_state_cap = 0;
 };
 
 namespace {
@@ -1398,6 +1408,78 @@ int link_impl(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t 
     return SOFIA_SC_OK;
 }
 
+// ---- parameterisation and reliability (Sect. 4.4, 4.5)
+
+int param_impl(sofia_sc *h, const float *cube, const int32_t *labels, int64_t nx, int64_t ny,
+               int64_t nz, int64_t n, const sofia_sc_param_options *opt, sofia_sc_source *out,
+               int64_t *n_kept, void *stream) {
+    if (!h) return SOFIA_SC_EINVAL;
+    h->err[0] = 0;
+    if (n_kept) *n_kept = -1;
+    if (!cube || !labels || !opt || !n_kept || (n > 0 && !out))
+        return fail(h, SOFIA_SC_EINVAL, "NULL argument");
+    if (opt->struct_size != (int32_t)sizeof(sofia_sc_param_options))
+        return fail(h, SOFIA_SC_EINVAL, "sofia_sc_param_options.struct_size mismatch");
+    int rc;
+    if ((rc = check_dims(h, nx, ny, nz))) return rc;
+    if (n < 0 || n > 0x7fffffffLL)
+        return fail(h, SOFIA_SC_EINVAL, "n_sources must be 0..2^31-1");
+    if (!(opt->channel_width > 0.0) || !std::isfinite(opt->channel_width) ||
+        !(opt->sigma_rms >= 0.0) || !std::isfinite(opt->sigma_rms) ||
+        !(opt->rel_scale > 0.0) || !std::isfinite(opt->rel_scale) ||
+        std::isnan(opt->rel_threshold) || std::isnan(opt->snr_threshold) ||
+        std::isnan(opt->beam_major_px) || std::isnan(opt->beam_minor_px))
+        return fail(h, SOFIA_SC_EINVAL,
+                    "channel width and scale must be > 0, sigma_rms >= 0, thresholds numbers");
+    DeviceGuard dg(h->device);
+    if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        *n_kept = 0;
+        return SOFIA_SC_OK;
+    }
+    const double a_fw = opt->beam_major_px, b_fw = opt->beam_minor_px;
+    ParamArgs a{};
+    a.cube = cube;
+    a.labels = labels;
+    a.nx = nx; a.ny = ny; a.nz = nz;
+    a.n = n;
+    a.channel_width = opt->channel_width;
+    a.omega = (a_fw > 0.0 && b_fw > 0.0) ? std::acos(-1.0) * a_fw * b_fw / (4.0 * std::log(2.0)) : 1.0;
+    a.sigma_rms = opt->sigma_rms;
+    a.scale = opt->rel_scale;
+    a.rel_threshold = opt->rel_threshold;
+    a.snr_threshold = opt->snr_threshold;
+    a.vec4 = ((uintptr_t)labels & 15u) == 0;
+    if ((rc = grow(h, h->pm_acc, h->pm_acc_cap, (size_t)n, "source accumulators", nullptr)) ||
+        (rc = grow(h, h->pm_sign, h->pm_sign_cap, (size_t)n, "source signs", nullptr)) ||
+        (rc = grow(h, h->pm_vec, h->pm_vec_cap, (size_t)n * 3, "source vectors", nullptr)) ||
+        (rc = grow(h, h->pm_state, h->pm_state_cap, (size_t)16, "reliability state", nullptr)))
+        return rc;
+    a.acc = h->pm_acc;
+    a.sign = h->pm_sign;
+    a.vec = h->pm_vec;
+    a.rel_state = h->pm_state;
+    a.n_kept = reinterpret_cast<unsigned long long *>(h->pm_state + 12);
+    a.out = out;
+    const double N = (double)(nx * ny * nz), nd = (double)n;
+    SC_TRACE("parameterise %lldx%lldx%lld, %lld detections", (long long)nx, (long long)ny,
+             (long long)nz, (long long)n);
+    // algorithmic bytes: the label cube; the per-detection records
+    rc = launch(h, s, F_PARAM, 4.0 * N + nd * (double)sizeof(sofia_sc_source), N,
+                [&] { return launch_parameterise(a, s); });
+    if (!rc) rc = launch(h, s, F_RELIABILITY, 0.0, nd * nd,
+                         [&] { return launch_reliability(a, s); });
+    if (rc) return rc;
+    unsigned long long kept = 0;
+    hipError_t e = hipMemcpyAsync(&kept, a.n_kept, sizeof(kept), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "count of kept detections");
+    if (h->prof) collect_profile(h);
+    *n_kept = (int64_t)kept;
+    return SOFIA_SC_OK;
+}
+
 // ---- the entry point that allocates nothing (sofia_sc_run_noalloc)
 //
 // Its workspace is carved out of `scratch`, a file-scope device array of
@@ -1598,7 +1680,8 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->bst) (void)hipFree(h->bst);
         if (h->bst_host) (void)hipHostFree(h->bst_host);
         if (h->nn_sigma) (void)hipFree(h->nn_sigma);
-        void *lk[] = {h->lk_counts, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out};
+        void *lk[] = {h->lk_counts, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out,
+                      h->pm_acc, h->pm_sign, h->pm_vec, h->pm_state};
         for (void *p : lk)
             if (p) (void)hipFree(p);
         for (int l = 0; l < kBatchLanes; ++l) {
@@ -1819,6 +1902,26 @@ int sofia_sc_link(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int6
                   int64_t *boxes, int64_t box_capacity, void *stream) {
     return link_impl(h, mask, nx, ny, nz, radius_xy, radius_z, min_size_xy, min_size_z,
                      max_size_xy, max_size_z, labels, n_sources, boxes, box_capacity, stream);
+}
+
+void sofia_sc_param_defaults(sofia_sc_param_options *opt) {
+    if (!opt) return;
+    *opt = sofia_sc_param_options{};
+    opt->struct_size = (int32_t)sizeof(sofia_sc_param_options);
+    opt->channel_width = 1.0;
+    opt->beam_major_px = 0.0;
+    opt->beam_minor_px = 0.0;
+    opt->sigma_rms = 1.0;
+    opt->rel_scale = 0.4;
+    opt->rel_threshold = 0.9;
+    opt->snr_threshold = 2.8;
+}
+
+int sofia_sc_parameterise(sofia_sc *h, const float *cube, const int32_t *labels, int64_t nx,
+                          int64_t ny, int64_t nz, int64_t n_sources,
+                          const sofia_sc_param_options *opt, sofia_sc_source *out,
+                          int64_t *n_kept, void *stream) {
+    return param_impl(h, cube, labels, nx, ny, nz, n_sources, opt, out, n_kept, stream);
 }
 
 int sofia_sc_normalise_grid(int64_t nx, int64_t ny, int64_t nz, int32_t window_xy,

@@ -202,6 +202,33 @@ hipError_t launch_link_resolve(const LinkArgs &a, int64_t nc, hipStream_t s);
 hipError_t launch_link_label(const LinkArgs &a, hipStream_t s);
 hipError_t launch_link_boxes_out(const LinkArgs &a, int64_t nc, long long *out, hipStream_t s);
 
+// Parameterisation and reliability (sc_param.hip). Per-detection
+// accumulators: voxel count, FP64 sums of the value and of value x position,
+// and the order-keeping integer images of the largest and smallest value.
+struct SrcAcc {
+    unsigned long long count;
+    double sum, sx, sy, sz;
+    int peak, mn;
+};
+struct ParamArgs {
+    const float *cube;
+    const int *labels;
+    int64_t nx, ny, nz;
+    int64_t n;                       // detections 1..n
+    double channel_width, omega, sigma_rms;
+    double scale, rel_threshold, snr_threshold;
+    SrcAcc *acc;                     // [n]
+    int *sign;                       // [n]: +1 / -1 / 0 by the sign of the sum
+    double *vec;                     // [n][3]: log10 parameter vectors
+    double *rel_state;               // [10]: inverse covariance, valid flag
+    unsigned long long *n_kept;      // count of kept detections
+    sofia_sc_source *out;            // [n]
+    int vec4;                        // labels 16-byte aligned: 4 voxels per load
+};
+
+hipError_t launch_parameterise(const ParamArgs &a, hipStream_t s);
+hipError_t launch_reliability(const ParamArgs &a, hipStream_t s);
+
 // ---- launchers (sc_kernels.hip). Each returns the launch's hipError_t.
 hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
                             int64_t n, hipStream_t s);

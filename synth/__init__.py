@@ -218,3 +218,29 @@ def workload(name: str) -> Workload:
             _pairs([0, 5, 10], [0, 3, 7, 15]), 3.5, "mad", "negative",
             notes="shape and kernels of the paper's laptop speed test (Sect. 5)")
     raise KeyError(name)
+
+
+def random_labels(shape: Tuple[int, int, int], n: int, seed: int,
+                  extent_xy: Tuple[int, int] = (4, 16), extent_z: Tuple[int, int] = (3, 24),
+                  fill: float = 0.85) -> np.ndarray:
+    """An int32 label cube [nz][ny][nx] of n seeded detections 1..n: each is a
+    box of extents uniform in extent_xy (x and y) and extent_z (z) at a
+    uniform position, of which each voxel is kept with probability `fill`
+    (ragged shapes). Later boxes overwrite earlier ones where they overlap, so
+    some labels may end up with few or no voxels. Stands in for a linker's
+    output with the size mix of detections of at least 8 px and 5 channels."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    lab = np.zeros(shape, dtype=np.int32)
+    for i in range(1, n + 1):
+        ex = int(rng.integers(extent_xy[0], extent_xy[1] + 1))
+        ey = int(rng.integers(extent_xy[0], extent_xy[1] + 1))
+        ez = int(rng.integers(extent_z[0], extent_z[1] + 1))
+        ex, ey, ez = min(ex, nx), min(ey, ny), min(ez, nz)
+        x0 = int(rng.integers(0, nx - ex + 1))
+        y0 = int(rng.integers(0, ny - ey + 1))
+        z0 = int(rng.integers(0, nz - ez + 1))
+        keep = rng.random((ez, ey, ex)) < fill
+        view = lab[z0:z0 + ez, y0:y0 + ey, x0:x0 + ex]
+        view[keep] = i
+    return lab

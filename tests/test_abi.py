@@ -90,3 +90,29 @@ def test_binding_has_no_compute_fallback():
     """The binding only marshals: it must not import the oracle or numpy math."""
     src = open(os.path.join(os.path.dirname(sc.__file__), "__init__.py")).read()
     assert "import oracle" not in src and "from oracle" not in src
+
+
+def test_param_layouts_and_defaults():
+    """sofia_sc_source: int64 count, eleven doubles, two int32 (104 bytes) in
+    header order; sofia_sc_param_options: two int32, seven doubles (64 bytes);
+    defaults of the mock-galaxy run (Sect. 6)."""
+    assert sc.SOURCE_DTYPE.itemsize == 104
+    text = open(sc.HEADER).read()
+    body = text[text.index("typedef struct {\n    int64_t n_vox;"):]
+    body = body[:body.index("} sofia_sc_source;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)[,;]", body)
+    assert names == ["n_vox", "sum", "peak", "min", "mean", "x", "y", "z", "flux", "flux_err",
+                     "snr", "reliability", "kept", "pad"]
+    assert list(sc.SOURCE_DTYPE.names) == ["count"] + names[1:]
+    assert ctypes.sizeof(sc.ParamOptions) == 64
+    o = sc.ParamOptions()
+    lib = sc.load()
+    lib.sofia_sc_param_defaults(ctypes.byref(o))
+    assert o.struct_size == 64
+    assert (o.channel_width, o.sigma_rms, o.rel_scale, o.rel_threshold, o.snr_threshold) == \
+        (1.0, 1.0, 0.4, 0.9, 2.8)
+    assert (o.beam_major_px, o.beam_minor_px) == (0.0, 0.0)
+    n = ctypes.c_int64(5)
+    assert lib.sofia_sc_parameterise(None, None, None, 1, 1, 1, 1, ctypes.byref(o), None,
+                                     ctypes.byref(n), None) == sc.EINVAL

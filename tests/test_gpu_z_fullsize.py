@@ -184,3 +184,30 @@ def test_fullsize_linker_bit_exact(h, cfg2, xd_full):
         say(f"full-size linker {filt}: {n} detections from {int(mask.sum())} voxels, "
             f"equal to the oracle")
         del lab, lab_ref
+
+
+def test_fullsize_parameterisation_and_reliability(h, cfg2, xd_full):
+    """Parameters and reliability of 24576 seeded ragged-box detections (about
+    the catalogue size of the mock run, Sect. 6) in the 1024^3 cube: every
+    detection's parameters against the oracle over the labelled voxels, the
+    reliability and kept flag at 512 sampled positive detections (the
+    oracle's densities there run over all detections)."""
+    from test_gpu_param import _term_scales, compare
+    param = oracle.param_module()
+    wl, x, s0, m1, band1 = cfg2
+    n = 24576
+    labels = synth.random_labels(x.shape, n, 77)
+    ld = torch.from_numpy(labels).cuda()
+    g, kept = h.parameterise(xd_full, ld, n, sigma_rms=s0)
+    del ld
+    idx = np.flatnonzero(labels)
+    lab = labels.ravel()[idx]
+    del labels
+    vals = x.ravel()[idx]
+    p = param.parameterise_voxels(idx, vals, lab, x.shape, n, sigma_rms=s0)
+    rng = np.random.default_rng(5)
+    at = np.sort(rng.choice(np.flatnonzero(p["sum"] > 0), 512, replace=False))
+    o = param.finish(p, at=at)
+    say(f"full-size parameterisation: {n} detections over {idx.size} voxels, "
+        f"{int((o['sum'] > 0).sum())} positive, {int((o['sum'] < 0).sum())} negative")
+    compare(g, o, _term_scales(idx, vals, lab, x.shape, n), n, kept, at=at)

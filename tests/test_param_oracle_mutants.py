@@ -24,7 +24,7 @@ MUTANTS = {
                           "cov = np.cov(vn.T, ddof=1) * scale"),
     "negative_vector_uses_peak": ("return np.log10(np.stack([-p[\"min\"], -p[\"sum\"], -p[\"mean\"]], axis=1))",
                                   "return np.log10(np.stack([-p[\"peak\"], -p[\"sum\"], -p[\"mean\"]], axis=1))"),
-    "reliability_not_clipped": ("R[pos] = np.maximum(0.0, (P - N) / P)", "R[pos] = (P - N) / P"),
+    "reliability_not_clipped": ("R[ev] = np.maximum(0.0, (P - N) / P)", "R[ev] = (P - N) / P"),
     "snr_threshold_strict": ("(p[\"snr\"] >= snr_threshold)", "(p[\"snr\"] > snr_threshold)"),
     "centroid_unweighted": ("sx = np.bincount(lab, weights=v * px, minlength=n + 1)[1:]",
                             "sx = np.bincount(lab, weights=px * 1.0, minlength=n + 1)[1:]"),

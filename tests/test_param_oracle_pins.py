@@ -161,3 +161,24 @@ def test_reliability_is_zero_where_negatives_outnumber_positives():
     mn = [0.01] + [-pk[0]] * 3 + list(-pk)
     R = param.reliability(_params(peak, ssum, mean, mn), 0.4)
     assert R[0] == 0.0
+
+
+def test_voxel_subset_and_sampled_reliability_agree_with_the_whole():
+    """parameterise_voxels over the labelled voxels of a cube gives what
+    parameterise gives over the whole cube; reliability at sampled detections
+    equals the whole-catalogue reliability there."""
+    rng = np.random.default_rng(11)
+    cube = rng.normal(size=(9, 10, 11)).astype(np.float32)
+    cube[0, 0, :3] = np.nan
+    labels = rng.integers(0, 25, size=cube.shape).astype(np.int32)
+    labels[rng.random(cube.shape) < 0.5] = 0
+    whole = param.parameterise(cube, labels, 20)
+    idx = np.flatnonzero(labels)
+    sub = param.parameterise_voxels(idx, cube.ravel()[idx], labels.ravel()[idx], cube.shape, 20)
+    for k in whole:
+        np.testing.assert_array_equal(sub[k], whole[k], err_msg=k)
+    R = param.reliability(whole, 0.4)
+    at = [0, 3, 7, 19]
+    Ra = param.reliability(whole, 0.4, at)
+    np.testing.assert_array_equal(Ra[at], R[at])
+    assert np.isnan(np.delete(Ra, at)).all()
