@@ -108,14 +108,15 @@ def _bind(lib):
     lib.sco_step.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, dbl,
                              i32, i32, vp, ctypes.POINTER(dbl), vp,
                              ctypes.POINTER(i64)]
-    lib.sco_run.argtypes = [vp, i64, i64, i64, vp, vp, i32, dbl, i32, i32,
+    lib.sco_run.argtypes = [vp, i64, i64, i64, vp, vp, vp, i32, dbl, i32, i32,
                             dbl, vp, vp, ctypes.POINTER(dbl), vp, vp]
-    fns = [lib.sco_plan, lib.sco_smooth, lib.sco_noise, lib.sco_step, lib.sco_run]
-    if hasattr(lib, "sco_step_sub"):
-        lib.sco_step_sub.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, dbl, i32, i32,
-                                     i32, dbl, vp, ctypes.POINTER(dbl), vp,
-                                     ctypes.POINTER(i64)]
-        fns.append(lib.sco_step_sub)
+    lib.sco_step_sub.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, i32, dbl, i32,
+                                 i32, i32, dbl, vp, ctypes.POINTER(dbl), vp,
+                                 ctypes.POINTER(i64)]
+    lib.sco_smooth_kind.argtypes = [vp, i64, i64, i64, vp, dbl, dbl, dbl, i32, i32, vp]
+    lib.sco_gauss_taps.argtypes = [dbl, vp, i32, ctypes.POINTER(i32)]
+    fns = [lib.sco_plan, lib.sco_smooth, lib.sco_noise, lib.sco_step, lib.sco_run,
+           lib.sco_step_sub, lib.sco_smooth_kind, lib.sco_gauss_taps]
     for f in fns:
         f.restype = ctypes.c_int
     _lib = lib
@@ -146,18 +147,29 @@ def plan(fwhm: float) -> Tuple[int, int]:
     return n.value, r.value
 
 
+def gauss_taps(fwhm: float) -> np.ndarray:
+    """Taps of the sampled, truncated, normalised Gaussian (reading G1)."""
+    cap = 4096
+    h = np.empty(cap, dtype=np.float64)
+    n = ctypes.c_int32()
+    if _load().sco_gauss_taps(float(fwhm), h.ctypes.data, cap, ctypes.byref(n)) != 0:
+        raise ValueError("bad FWHM %r" % fwhm)
+    return h[:n.value].copy()
+
+
 def smooth(cube: np.ndarray, fwhm: float, width: int,
            mask_prev: Optional[np.ndarray] = None, repl: float = -1.0,
-           sigma0: float = float("nan")) -> np.ndarray:
-    """Smoothed cube s (FP64, NaN where the input is blanked)."""
+           sigma0: float = float("nan"), kind: int = 0) -> np.ndarray:
+    """Smoothed cube s (FP64, NaN where the input is blanked); kind 0 = the
+    boxcar cascade (R1), 1 = the sampled Gaussian (G1)."""
     x = _cube(cube)
     m = _mask_in(mask_prev, x.shape)
     out = np.empty(x.shape, dtype=np.float64)
     nz, ny, nx = x.shape
-    rc = _load().sco_smooth(x.ctypes.data, nx, ny, nz,
-                            None if m is None else m.ctypes.data,
-                            float(repl), float(sigma0), float(fwhm), int(width),
-                            out.ctypes.data)
+    rc = _load().sco_smooth_kind(x.ctypes.data, nx, ny, nz,
+                                 None if m is None else m.ctypes.data,
+                                 float(repl), float(sigma0), float(fwhm), int(width),
+                                 int(kind), out.ctypes.data)
     if rc != 0:
         raise ValueError("sco_smooth failed (%d)" % rc)
     return out
@@ -186,22 +198,24 @@ class StepResult:
 def step(cube: np.ndarray, fwhm: float, width: int, threshold: float,
          mode: str, flux_range: str, mask_prev: Optional[np.ndarray] = None,
          repl: float = -1.0, sigma0: float = float("nan"), plane_stride: int = 1,
-         sigma_given: float = float("nan")) -> StepResult:
+         sigma_given: float = float("nan"), kind: int = 0) -> StepResult:
     """One S+C iteration (teacher-forcing unit): mask_prev OR new detections.
 
     plane_stride > 1 measures the noise on every plane_stride-th plane only;
     a finite sigma_given replaces the measurement (clip of a slab with the
-    noise of the whole cube)."""
+    noise of the whole cube); kind 1 takes the sampled Gaussian (G1) as the
+    spatial kernel."""
     x = _cube(cube)
     m = _mask_in(mask_prev, x.shape)
     nz, ny, nx = x.shape
     out = np.empty(x.shape, dtype=np.uint8)
     band = np.zeros(x.shape, dtype=np.uint8)
     sig, nb = ctypes.c_double(), ctypes.c_int64()
-    if plane_stride != 1 or not np.isnan(sigma_given):
+    if plane_stride != 1 or not np.isnan(sigma_given) or kind != 0:
         rc = _load().sco_step_sub(x.ctypes.data, nx, ny, nz,
                                   None if m is None else m.ctypes.data, float(repl),
-                                  float(sigma0), float(fwhm), int(width), float(threshold),
+                                  float(sigma0), float(fwhm), int(width), int(kind),
+                                  float(threshold),
                                   NOISE[mode], RANGE[flux_range], int(plane_stride),
                                   float(sigma_given), out.ctypes.data, ctypes.byref(sig),
                                   band.ctypes.data, ctypes.byref(nb))
@@ -228,19 +242,21 @@ class RunResult:
 
 def run(cube: np.ndarray, kernels: Sequence[Tuple[float, int]], threshold: float,
         mode: str, flux_range: str, repl: float = 2.0) -> RunResult:
-    """Whole S+C run over the kernel list, in list order."""
+    """Whole S+C run over the kernel list, in list order. A kernel is
+    (FWHM, width) or (FWHM, width, kind) with kind 1 = sampled Gaussian."""
     x = _cube(cube)
     nz, ny, nx = x.shape
     K = len(kernels)
     f = np.array([k[0] for k in kernels], dtype=np.float64)
     w = np.array([k[1] for k in kernels], dtype=np.int32)
+    kd = np.array([k[2] if len(k) > 2 else 0 for k in kernels], dtype=np.int32)
     mask = np.empty(x.shape, dtype=np.uint8)
     band = np.empty(x.shape, dtype=np.uint8)
     sig = np.full(K, np.nan)
     bc = np.zeros(K, dtype=np.int64)
     s0 = ctypes.c_double()
     rc = _load().sco_run(x.ctypes.data, nx, ny, nz, f.ctypes.data, w.ctypes.data,
-                         K, float(threshold), NOISE[mode], RANGE[flux_range],
+                         kd.ctypes.data, K, float(threshold), NOISE[mode], RANGE[flux_range],
                          float(repl), mask.ctypes.data, sig.ctypes.data,
                          ctypes.byref(s0), band.ctypes.data, bc.ctypes.data)
     if rc not in (0, ENOSTAT):

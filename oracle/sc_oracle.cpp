@@ -30,6 +30,10 @@
  *     sigma_g = FWHM / (2 sqrt(2 ln 2)); FWHM 0 = no spatial smoothing.
  *  R2 every boxcar pass treats voxels outside the cube as 0 and divides by
  *     the full width.
+ *  G1 (variant, spatial kind 1) spatial Gaussian = sampled, truncated,
+ *     normalised Gaussian: taps exp(-k^2 / (2 sigma_g^2)) for |k| <= R with
+ *     R = floor(4 sigma_g + 1/2), divided by their sum; applied along x, then
+ *     along y, voxels outside the cube 0 (as R2). R = 0 = no smoothing.
  *  R3 non-finite voxels are blanked: 0 in the smoothing, excluded from the
  *     noise, never detected.
  *  R4 spectral width 0 or 1 = no spectral smoothing; odd widths >= 3 are
@@ -194,15 +198,69 @@ bool valid_common(int64_t nx, int64_t ny, int64_t nz, int mode, int range) {
     return true;
 }
 
+// G1: taps of the sampled, truncated, normalised Gaussian (length 2R + 1).
+int gauss_taps(double fwhm, std::vector<double> &h) {
+    if (!std::isfinite(fwhm) || fwhm < 0.0) return -1;
+    h.assign(1, 1.0);
+    if (fwhm == 0.0) return 0;
+    const double sigma_g = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const int64_t R = (int64_t)std::floor(4.0 * sigma_g + 0.5);
+    h.assign((size_t)(2 * R + 1), 0.0);
+    double sum = 0.0;
+    for (int64_t k = -R; k <= R; ++k) {
+        const double v = std::exp(-(double)(k * k) / (2.0 * sigma_g * sigma_g));
+        h[(size_t)(k + R)] = v;
+        sum += v;
+    }
+    for (double &v : h) v /= sum;
+    return 0;
+}
+
+// Correlate one line with the taps h (centre at index R), outside = 0.
+void taps_line(const double *in, double *out, int64_t len, const std::vector<double> &h) {
+    const int64_t R = ((int64_t)h.size() - 1) / 2;
+    for (int64_t i = 0; i < len; ++i) {
+        double acc = 0.0;
+        for (int64_t j = -R; j <= R; ++j) {
+            const int64_t k = i + j;
+            if (k >= 0 && k < len) acc += h[(size_t)(j + R)] * in[k];
+        }
+        out[i] = acc;
+    }
+}
+
+// Apply the taps along axis 0 (x) or 1 (y) of Y [nz][ny][nx].
+void taps_axis(std::vector<double> &Y, int64_t nx, int64_t ny, int64_t nz, int axis,
+               const std::vector<double> &h) {
+    const int64_t len = axis == 0 ? nx : ny;
+    const int64_t stride = axis == 0 ? 1 : nx;
+    const int64_t n_lines = axis == 0 ? ny * nz : nx * nz;
+#pragma omp parallel
+    {
+        std::vector<double> a((size_t)len), b((size_t)len);
+#pragma omp for schedule(static)
+        for (int64_t l = 0; l < n_lines; ++l) {
+            const int64_t base = axis == 0 ? l * nx : (l / nx) * nx * ny + (l % nx);
+            for (int64_t i = 0; i < len; ++i) a[i] = Y[base + i * stride];
+            taps_line(a.data(), b.data(), len, h);
+            for (int64_t i = 0; i < len; ++i) Y[base + i * stride] = b[i];
+        }
+    }
+}
+
 bool valid_width(int32_t w) { return w == 0 || w == 1 || (w >= 3 && (w & 1)); }
 
 // Steps a-e: replaced, blanked, smoothed cube S (NaN where the input is
 // non-finite).
+// kind 0: spatial cascade (R1); kind 1: sampled Gaussian (G1).
 int smooth(const float *X, int64_t nx, int64_t ny, int64_t nz,
            const uint8_t *mask_prev, double repl, double sigma0, double fwhm,
-           int32_t width, std::vector<double> &S) {
+           int32_t width, std::vector<double> &S, int32_t kind = 0) {
     int32_t n_it, r;
     if (plan(fwhm, &n_it, &r) != 0 || !valid_width(width)) return -1;
+    if (kind != 0 && kind != 1) return -1;
+    std::vector<double> taps;
+    if (kind == 1 && gauss_taps(fwhm, taps) != 0) return -1;
     const int64_t N = nx * ny * nz;
     S.assign((size_t)N, 0.0);
     const bool replace = repl >= 0.0 && mask_prev != nullptr;
@@ -216,9 +274,13 @@ int smooth(const float *X, int64_t nx, int64_t ny, int64_t nz,
         else y = d;
         S[i] = y;
     }
-    if (n_it > 0) {
+    if (kind == 0 && n_it > 0) {
         smooth_axis(S, nx, ny, nz, 0, n_it, r);
         smooth_axis(S, nx, ny, nz, 1, n_it, r);
+    }
+    if (kind == 1 && taps.size() > 1) {
+        taps_axis(S, nx, ny, nz, 0, taps);
+        taps_axis(S, nx, ny, nz, 1, taps);
     }
     if (width >= 3) smooth_axis(S, nx, ny, nz, 2, 1, (width - 1) / 2);
 #pragma omp parallel for schedule(static)
@@ -261,17 +323,37 @@ int sco_plan(double fwhm, int32_t *n_iter, int32_t *radius) {
     return plan(fwhm, n_iter, radius);
 }
 
-// Smoothed cube s for one kernel (steps a-e), FP64, NaN at blanked voxels.
+// Reading G1: taps of the sampled Gaussian for a spatial FWHM; *len = 2R + 1
+// (1 for FWHM 0). Fails if cap < 2R + 1.
+int sco_gauss_taps(double fwhm, double *taps, int32_t cap, int32_t *len) {
+    if (!taps || !len) return -1;
+    std::vector<double> h;
+    if (gauss_taps(fwhm, h) != 0) return -1;
+    *len = (int32_t)h.size();
+    if ((int64_t)h.size() > cap) return -1;
+    std::memcpy(taps, h.data(), h.size() * sizeof(double));
+    return 0;
+}
+
+// Smoothed cube s for one kernel (steps a-e), FP64, NaN at blanked voxels,
+// with the spatial kernel of the given kind (0: cascade R1, 1: Gaussian G1).
 // mask_prev may be NULL (no replacement).
-int sco_smooth(const float *X, int64_t nx, int64_t ny, int64_t nz,
-               const uint8_t *mask_prev, double repl, double sigma0,
-               double fwhm, int32_t width, double *out) {
+int sco_smooth_kind(const float *X, int64_t nx, int64_t ny, int64_t nz,
+                    const uint8_t *mask_prev, double repl, double sigma0,
+                    double fwhm, int32_t width, int32_t kind, double *out) {
     if (!X || !out || nx < 1 || ny < 1 || nz < 1) return -1;
     std::vector<double> S;
-    const int rc = smooth(X, nx, ny, nz, mask_prev, repl, sigma0, fwhm, width, S);
+    const int rc = smooth(X, nx, ny, nz, mask_prev, repl, sigma0, fwhm, width, S, kind);
     if (rc != 0) return rc;
     std::memcpy(out, S.data(), S.size() * sizeof(double));
     return 0;
+}
+
+// As sco_smooth_kind with the cascade (kind 0).
+int sco_smooth(const float *X, int64_t nx, int64_t ny, int64_t nz,
+               const uint8_t *mask_prev, double repl, double sigma0,
+               double fwhm, int32_t width, double *out) {
+    return sco_smooth_kind(X, nx, ny, nz, mask_prev, repl, sigma0, fwhm, width, 0, out);
 }
 
 // Noise of an arbitrary FP64 array (NaN = blanked), step f.
@@ -314,17 +396,18 @@ int sco_step(const float *X, int64_t nx, int64_t ny, int64_t nz,
 //    step g with a noise measured elsewhere, e.g. on the whole of a larger
 //    cube of which X is a slab).
 // Otherwise as sco_step.
+// kind selects the spatial kernel (0: cascade R1, 1: Gaussian G1).
 int sco_step_sub(const float *X, int64_t nx, int64_t ny, int64_t nz,
                  const uint8_t *mask_prev, double repl, double sigma0, double fwhm,
-                 int32_t width, double t, int32_t mode, int32_t range, int32_t plane_stride,
-                 double sigma_given, uint8_t *mask_out, double *sigma_k, uint8_t *band,
-                 int64_t *band_count) {
+                 int32_t width, int32_t kind, double t, int32_t mode, int32_t range,
+                 int32_t plane_stride, double sigma_given, uint8_t *mask_out,
+                 double *sigma_k, uint8_t *band, int64_t *band_count) {
     if (!X || !mask_out || !sigma_k || !valid_common(nx, ny, nz, mode, range))
         return -1;
     if (!std::isfinite(t) || t <= 0.0 || plane_stride < 1) return -1;
     const int64_t N = nx * ny * nz, ncol = nx * ny;
     std::vector<double> S;
-    int rc = smooth(X, nx, ny, nz, mask_prev, repl, sigma0, fwhm, width, S);
+    int rc = smooth(X, nx, ny, nz, mask_prev, repl, sigma0, fwhm, width, S, kind);
     if (rc != 0) return rc;
     if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);
     else std::memset(mask_out, 0, (size_t)N);
@@ -358,9 +441,11 @@ int sco_step_sub(const float *X, int64_t nx, int64_t ny, int64_t nz,
 // Whole S+C run over K kernels in list order. sigma0 gets the noise of the
 // unsmoothed input (NaN if replacement is off). band (optional, N bytes) is
 // the OR over k of the per-kernel boundary bands; band_count[k] its size.
+// kind (may be NULL = all 0) gives each kernel's spatial kind (0: cascade
+// R1, 1: Gaussian G1).
 int sco_run(const float *X, int64_t nx, int64_t ny, int64_t nz,
-            const double *fwhm, const int32_t *width, int32_t K, double t,
-            int32_t mode, int32_t range, double repl, uint8_t *mask,
+            const double *fwhm, const int32_t *width, const int32_t *kind, int32_t K,
+            double t, int32_t mode, int32_t range, double repl, uint8_t *mask,
             double *sigma, double *sigma0_out, uint8_t *band,
             int64_t *band_count) {
     if (!X || !fwhm || !width || !mask || !sigma || K < 1 ||
@@ -370,6 +455,7 @@ int sco_run(const float *X, int64_t nx, int64_t ny, int64_t nz,
     for (int32_t k = 0; k < K; ++k) {
         int32_t a, b;
         if (plan(fwhm[k], &a, &b) != 0 || !valid_width(width[k])) return -1;
+        if (kind && kind[k] != 0 && kind[k] != 1) return -1;
         sigma[k] = NAN;
     }
     const int64_t N = nx * ny * nz;
@@ -392,7 +478,7 @@ int sco_run(const float *X, int64_t nx, int64_t ny, int64_t nz,
     }
     for (int32_t k = 0; k < K; ++k) {
         int rc = smooth(X, nx, ny, nz, repl >= 0.0 ? mask : nullptr, repl,
-                        sigma0, fwhm[k], width[k], S);
+                        sigma0, fwhm[k], width[k], S, kind ? kind[k] : 0);
         if (rc != 0) return rc;
         int64_t nb = 0;
         rc = noise_and_clip(S, N, t, mode, range, mask, &sigma[k], band, &nb);

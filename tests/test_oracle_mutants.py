@@ -16,6 +16,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "sc_oracle.cpp")
 
 MUTANTS = {
+    "gauss_radius_floor": ("(int64_t)std::floor(4.0 * sigma_g + 0.5);",
+                           "(int64_t)std::floor(4.0 * sigma_g);"),
+    "gauss_unnormalised": ("for (double &v : h) v /= sum;", "for (double &v : h) v /= 1.0;"),
+    "gauss_variance_factor": ("std::exp(-(double)(k * k) / (2.0 * sigma_g * sigma_g));",
+                              "std::exp(-(double)(k * k) / (sigma_g * sigma_g));"),
+    "gauss_y_pass_dropped": ("        taps_axis(S, nx, ny, nz, 1, taps);\n", ""),
+    "gauss_edge_replicated": ("if (k >= 0 && k < len) acc += h[(size_t)(j + R)] * in[k];",
+                              "acc += h[(size_t)(j + R)] * in[k < 0 ? 0 : (k >= len ? len - 1 : k)];"),
     "divisor_2r": ("const double width = (double)(2 * r + 1);",
                    "const double width = (double)(2 * r);"),
     "window_off_by_one": ("for (int64_t j = -r; j <= r; ++j) {",
@@ -43,8 +51,10 @@ MUTANTS = {
                              "if (!std::isfinite(X[i])) S[i] = S[i];"),
     "plan_tie_to_smaller_n": ("(d == best_d && (n > best_n ||",
                               "(d == best_d && (n < best_n ||"),
-    "fwhm_factor": ("fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)))",
-                    "fwhm / std::sqrt(2.0 * std::log(2.0))"),
+    "fwhm_factor": ("fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));\n    const double target",
+                    "fwhm / std::sqrt(2.0 * std::log(2.0));\n    const double target"),
+    "gauss_fwhm_factor": ("fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));\n    const int64_t R",
+                          "fwhm / std::sqrt(2.0 * std::log(2.0));\n    const int64_t R"),
     "union_dropped": ("if (mask_prev) std::memcpy(mask_out, mask_prev, (size_t)N);\n"
                       "    else std::memset(mask_out, 0, (size_t)N);\n    return noise_and_clip(",
                       "if (false) std::memcpy(mask_out, mask_prev, (size_t)N);\n"

@@ -455,3 +455,78 @@ def test_given_noise_clip_is_strict_and_banded():
     assert st.band_count == x.size and st.mask.sum() == 0
     st = oracle.step(x * np.float32(64), 0.0, 0, 1.0 + 2e-5, "std", "all", sigma_given=128.0)
     assert st.band_count == 0
+
+
+# ------------------------------------------ sampled Gaussian (reading G1)
+
+def _sigma_g(fwhm):
+    return fwhm / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+
+
+@pytest.mark.parametrize("fwhm", [0.6, 1.0, 3.0, 4.7, 5.0, 6.0, 9.0, 10.0, 13.3])
+def test_gauss_taps_match_scipy_impulse_and_closed_forms(fwhm):
+    """The taps are scipy.ndimage.gaussian_filter1d's response to a delta
+    (truncate = 4: radius floor(4 sigma + 1/2), normalised, zero outside);
+    they sum to 1, are symmetric, and their sum of squares and variance are
+    those of the continuous Gaussian up to sampling and truncation."""
+    from scipy.ndimage import gaussian_filter1d
+    h = oracle.gauss_taps(fwhm)
+    s = _sigma_g(fwhm)
+    R = int(np.floor(4.0 * s + 0.5))
+    assert h.size == 2 * R + 1
+    d = np.zeros(2 * R + 41)
+    d[R + 20] = 1.0
+    ref = gaussian_filter1d(d, s, mode="constant", cval=0.0, truncate=4.0)
+    np.testing.assert_allclose(h, ref[20:20 + 2 * R + 1], rtol=0, atol=1e-15)
+    assert abs(h.sum() - 1.0) < 1e-14
+    np.testing.assert_array_equal(h, h[::-1])
+    if s >= 1.0:
+        k = np.arange(-R, R + 1)
+        assert abs((h * h).sum() * 2.0 * np.sqrt(np.pi) * s - 1.0) < 1e-3
+        assert abs((k * k * h).sum() / (s * s) - 1.0) < 2e-3
+
+
+def test_gauss_identity_for_zero_and_tiny_fwhm():
+    x = np.random.default_rng(3).normal(size=(4, 9, 11)).astype(np.float32)
+    for f in (0.0, 0.2):
+        np.testing.assert_array_equal(oracle.gauss_taps(f), [1.0])
+        np.testing.assert_array_equal(oracle.smooth(x, f, 0, kind=1), x.astype(np.float64))
+    with pytest.raises(ValueError):
+        oracle.gauss_taps(-1.0)
+
+
+@pytest.mark.parametrize("fwhm,width", [(3.0, 0), (6.0, 7), (10.0, 3)])
+def test_gauss_smoothing_matches_scipy_per_plane(fwhm, width):
+    """Spatial part: scipy.ndimage.gaussian_filter over each plane (both axes,
+    zero outside) of the blanked cube; spectral part: the plain boxcar; NaN
+    restored at blanked voxels."""
+    from scipy.ndimage import gaussian_filter, uniform_filter1d
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(12, 45, 38)).astype(np.float32)
+    x[3, 10, 5:9] = np.nan
+    x[:, 0, 0] = np.inf
+    s = _sigma_g(fwhm)
+    b = np.where(np.isfinite(x), x, 0.0).astype(np.float64)
+    ref = np.stack([gaussian_filter(p, s, mode="constant", cval=0.0, truncate=4.0) for p in b])
+    if width >= 3:
+        ref = uniform_filter1d(ref, width, axis=0, mode="constant", cval=0.0)
+    ref[~np.isfinite(x)] = np.nan
+    g = oracle.smooth(x, fwhm, width, kind=1)
+    np.testing.assert_allclose(g, ref, rtol=0, atol=1e-13, equal_nan=True)
+
+
+def test_gauss_kind_in_steps_and_runs():
+    """Kernel kinds mix in one run; the run equals the chained steps with the
+    same kinds, and a Gaussian kernel differs from the cascade one."""
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=(20, 30, 33)).astype(np.float32)
+    kernels = [(0.0, 0), (3.0, 0, 1), (6.0, 3, 1), (6.0, 3, 0)]
+    r = oracle.run(x, kernels, 3.0, "mad", "negative", 2.0)
+    m = None
+    for k, kern in enumerate(kernels):
+        st = oracle.step(x, kern[0], kern[1], 3.0, "mad", "negative", m, 2.0, r.sigma0,
+                         kind=kern[2] if len(kern) > 2 else 0)
+        assert st.sigma == r.sigma[k]
+        m = st.mask
+    np.testing.assert_array_equal(m, r.mask)
+    assert r.sigma[2] != r.sigma[3]
