@@ -28,6 +28,7 @@ HIP events on the launch stream; `cpu_baseline` times the FP64 oracle on a
 slab of the same cube on the host cores (and on one core).
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -229,6 +230,18 @@ def extras(sc, torch, synth, stream, large_x=None, large_wl=None):
             "whole_step_hbm_frac": alg / (dt / 10) / 1e9 / HBM_PEAK_GBS,
             "kernel_gbs": family_gbs(stats), "mask_voxels": count_set(m, torch)}
         say(f"1024^3 f32: {dt * 100:.1f} ms/step")
+        # the same run with the sampled-Gaussian spatial kernel (variant G1)
+        wlg = dataclasses.replace(wl, name=wl.name + "_gauss", kernels=[
+            (f, w, "gauss") if f > 0 else (f, w) for f, w in wl.kernels])
+        dt, noise, s0, stats = time_runs(h, wlg, [x], [m], 10, 2, "f32", False, stream, torch)
+        out["plain_1024cube_gauss"] = {
+            "ms_per_step": dt * 100, "value": x.numel() * 10 / dt, "unit": "voxels/s",
+            "kernels": wlg.kernels, "kernel_gbs": family_gbs(stats),
+            "family_ms": {s["name"]: s["total_ms"] / s["launches"] for s in stats},
+            "noise": [float(v) for v in noise]}
+        say(f"1024^3 f32, sampled Gaussian: {dt * 100:.1f} ms/step")
+        h.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range, wl.replacement,
+              mask=m, stream=stream)
         y = torch.empty_like(x)
         h.normalise(x, 31, 31, 16, 16, "mad", "negative", out=y, grid=False)
         h.profile(True)

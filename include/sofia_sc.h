@@ -39,13 +39,24 @@ extern "C" {
 
 typedef struct sofia_sc sofia_sc;
 
-/* One smoothing kernel. spatial_fwhm_px = 0 means no spatial smoothing;
- * otherwise the Gaussian is built as a cascade of n boxcars of width 2r+1
- * along x and then along y (see sofia_sc_plan). spectral_width_ch = 0 or 1
- * means no spectral smoothing; other widths must be odd and >= 3. */
+/* One smoothing kernel. spatial_fwhm_px = 0 means no spatial smoothing.
+ * Otherwise the spatial Gaussian (Fig. 9 caption, Sect. 5) is built as set
+ * by spatial_kind:
+ *  SOFIA_SC_SPATIAL_CASCADE (0): a cascade of n boxcars of width 2r+1 along
+ *    x and then along y (see sofia_sc_plan), halo n r <= SOFIA_SC_MAX_HALO;
+ *  SOFIA_SC_SPATIAL_GAUSS (1): the Gaussian sampled at integer offsets
+ *    |k| <= R = floor(4 sigma + 1/2), sigma = FWHM / (2 sqrt(2 ln 2)),
+ *    normalised to sum 1, along x and then along y, zero outside the cube;
+ *    R <= SOFIA_SC_GAUSS_MAX_RADIUS (FWHM up to about 14 px); R = 0 means
+ *    no spatial smoothing.
+ * spectral_width_ch = 0 or 1 means no spectral smoothing; other widths must
+ * be odd and >= 3. Zero-initialise the struct: spatial_kind must be 0 or 1. */
+enum { SOFIA_SC_SPATIAL_CASCADE = 0, SOFIA_SC_SPATIAL_GAUSS = 1 };
+#define SOFIA_SC_GAUSS_MAX_RADIUS 24
 typedef struct {
     double spatial_fwhm_px;
     int32_t spectral_width_ch;
+    int32_t spatial_kind;
 } sofia_sc_kernel;
 
 enum { SOFIA_SC_NOISE_STD = 0, SOFIA_SC_NOISE_MAD = 1 };
@@ -305,8 +316,7 @@ int sofia_sc_quantize(sofia_sc *h, const float *cube, int64_t n, double scale,
  * non-finite voxels, and every voxel of a block whose noise is not finite
  * and > 0 (no voxel selected, or zero noise), become NaN (blanked).
  *  cube        device, float32 [nz][ny][nx], read only (unless out == cube).
- *  window_xy, window_z  odd window sizes, 1..SOFIA_SC_NORM_MAX_WINDOW; with
- *              MAD noise window_xy^2 * window_z <= SOFIA_SC_NORM_MAX_MAD_VOXELS.
+ *  window_xy, window_z  odd window sizes, 1..SOFIA_SC_NORM_MAX_WINDOW.
  *  grid_xy, grid_z  block sizes; 0 = (window + 1) / 2 (windows of adjacent
  *              blocks then overlap by about half).
  *  out         device, float32 [nz][ny][nx] or NULL (noise grid only); may
@@ -316,7 +326,6 @@ int sofia_sc_quantize(sofia_sc *h, const float *cube, int64_t n, double scale,
  * Returns after the work has completed. EINVAL for NULL cube, both outputs
  * NULL, bad dimensions, windows, grid steps or enums. */
 #define SOFIA_SC_NORM_MAX_WINDOW 255
-#define SOFIA_SC_NORM_MAX_MAD_VOXELS 32768
 int sofia_sc_normalise(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
                        int32_t window_xy, int32_t window_z, int32_t grid_xy, int32_t grid_z,
                        int32_t noise_mode, int32_t flux_range, float *out, double *noise_grid,

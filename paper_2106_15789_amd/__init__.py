@@ -22,7 +22,7 @@ SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
     "sc_kernels.hip", "sc_spatial_n3.hip", "sc_spatial_n4.hip", "sc_spatial_n5.hip",
     "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip", "sc_col_selclip.hip",
     "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_link.hip", "sc_param.hip",
-    "sc_api.hip")]
+    "sc_gauss_a.hip", "sc_gauss_b.hip", "sc_gauss_c.hip", "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
 NOISE = {"std": 0, "mad": 1}
@@ -82,7 +82,11 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 class Kernel(ctypes.Structure):
     _fields_ = [("spatial_fwhm_px", ctypes.c_double),
-                ("spectral_width_ch", ctypes.c_int32)]
+                ("spectral_width_ch", ctypes.c_int32),
+                ("spatial_kind", ctypes.c_int32)]
+
+
+SPATIAL = {"cascade": 0, "gauss": 1}
 
 
 class Options(ctypes.Structure):
@@ -228,11 +232,18 @@ def plan(fwhm: float) -> Tuple[int, int]:
     return n.value, r.value
 
 
+def _kernel(k) -> "Kernel":
+    """A kernel from (FWHM, width) or (FWHM, width, kind); kind 0 / "cascade"
+    = boxcar cascade, 1 / "gauss" = sampled Gaussian."""
+    kind = k[2] if len(k) > 2 else 0
+    kind = SPATIAL[kind] if isinstance(kind, str) else int(kind)
+    return Kernel(float(k[0]), int(k[1]), kind)
+
+
 def _kernels(kernels: Sequence[Tuple[float, int]]):
     arr = (Kernel * len(kernels))()
-    for i, (f, w) in enumerate(kernels):
-        arr[i].spatial_fwhm_px = float(f)
-        arr[i].spectral_width_ch = int(w)
+    for i, k in enumerate(kernels):
+        arr[i] = _kernel(k)
     return arr
 
 
@@ -469,7 +480,7 @@ class SofiaSC:
         if mask_out is None:
             mask_out = torch.empty(cube.shape, dtype=torch.uint8, device=cube.device)
         noise = ctypes.c_double()
-        k = Kernel(float(kernel[0]), int(kernel[1]))
+        k = _kernel(kernel)
         rc = self.lib.sofia_sc_step(self.h, cube.data_ptr(), nx, ny, nz, k,
                                     float(threshold), NOISE[noise_mode],
                                     RANGE[flux_range], float(replacement), float(sigma0),
@@ -499,7 +510,7 @@ class SofiaSC:
         opt.storage = STORAGE[storage]
         opt.noise_plane_stride = int(noise_plane_stride)
         opt.stream = _stream_ptr(stream)
-        k = Kernel(float(kernel[0]), int(kernel[1]))
+        k = _kernel(kernel)
         rc = self.lib.sofia_sc_step_ex(self.h, cube.data_ptr(), nx, ny, nz, k,
                                        float(threshold), NOISE[noise_mode], RANGE[flux_range],
                                        None if mask_in is None else mask_in.data_ptr(),
@@ -518,7 +529,7 @@ class SofiaSC:
         _check_like(out, cube, torch.float32, "out")
         if out is None:
             out = torch.empty(cube.shape, dtype=torch.float32, device=cube.device)
-        k = Kernel(float(kernel[0]), int(kernel[1]))
+        k = _kernel(kernel)
         rc = self.lib.sofia_sc_smooth(self.h, cube.data_ptr(), nx, ny, nz, k,
                                       float(replacement), float(sigma0),
                                       None if mask_in is None else mask_in.data_ptr(),

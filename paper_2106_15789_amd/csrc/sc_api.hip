@@ -24,14 +24,16 @@ enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
     F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
-    F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_PARAM, F_RELIABILITY, F_COUNT
+    F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_PARAM, F_RELIABILITY, F_SPATIAL_GAUSS,
+    F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
     "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide",
-    "link_union", "link_number", "link_label", "parameterise", "reliability"};
+    "link_union", "link_number", "link_label", "parameterise", "reliability",
+    "spatial_gauss"};
 
 struct LaunchRec {
     int fam;
@@ -47,7 +49,9 @@ struct Agg {
 
 struct Plan {
     int n_iter, radius, width;   // spatial cascade; spectral width (1 = none)
-    bool spatial() const { return n_iter > 0; }
+    int gauss_r = 0;             // sampled Gaussian of radius gauss_r (> 0) instead
+    double fwhm = 0.0;
+    bool spatial() const { return n_iter > 0 || gauss_r > 0; }
     bool spectral() const { return width >= 3; }
     bool identity() const { return !spatial() && !spectral(); }
 };
@@ -285,8 +289,19 @@ int make_plan(sofia_sc *h, const sofia_sc_kernel &k, Plan *p) {
     int32_t n, r;
     if (plan_cascade(k.spatial_fwhm_px, &n, &r) != SOFIA_SC_OK)
         return fail(h, SOFIA_SC_EINVAL, "spatial FWHM must be finite and >= 0");
-    if (n * r > SOFIA_SC_MAX_HALO)
+    if (k.spatial_kind != SOFIA_SC_SPATIAL_CASCADE && k.spatial_kind != SOFIA_SC_SPATIAL_GAUSS)
+        return fail(h, SOFIA_SC_EINVAL, "spatial_kind must be 0 (cascade) or 1 (Gaussian)");
+    p->gauss_r = 0;
+    p->fwhm = k.spatial_fwhm_px;
+    if (k.spatial_kind == SOFIA_SC_SPATIAL_GAUSS) {
+        n = r = 0;
+        if (k.spatial_fwhm_px > 0.0) p->gauss_r = gauss_radius(k.spatial_fwhm_px);
+        if (p->gauss_r > kGaussMaxR)
+            return fail(h, SOFIA_SC_EINVAL,
+                        "spatial FWHM too large (Gaussian radius above SOFIA_SC_GAUSS_MAX_RADIUS)");
+    } else if (n * r > SOFIA_SC_MAX_HALO) {
         return fail(h, SOFIA_SC_EINVAL, "spatial FWHM too large (cascade halo above limit)");
+    }
     if (!valid_width(k.spectral_width_ch))
         return fail(h, SOFIA_SC_EINVAL, "spectral width must be 0, 1 or odd in 3..63");
     p->n_iter = n;
@@ -528,7 +543,30 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     const ColGrid g = col_grid(d.ncol, d.nz, w.sh);
     if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
         return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
-    if (spatial) {
+    if (spatial && j.pl.gauss_r > 0) {
+        GaussArgs a{};
+        a.x = j.xtype == ST_F32 ? j.x : nullptr;
+        a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
+        a.wpp = det_words_per_plane(d.ncol);
+        a.det = nullptr;
+        if (j.repl_active) {
+            if (!j.det_live || w.det_cap < (size_t)(d.nz * a.wpp))
+                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
+            a.det = w.det;
+        }
+        a.p = w.p;
+        a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
+        gauss_setup(a, j.pl.fwhm, w.sh.strip_rows);
+        if (a.tiles > 0x7fffffffLL)
+            return fail(h, SOFIA_SC_EINVAL, "cube too large for the spatial grid");
+        a.repl_n = j.repl_n;
+        a.st = w.st;
+        const double bytes = N * (bx + (j.repl_active ? 0.125 : 0.0) + 4.0);
+        rc = launch(h, s, F_SPATIAL_GAUSS, bytes, N, [&] {
+            return launch_gauss(j.pl.gauss_r, j.xtype, j.repl_active, a, s);
+        });
+        if (rc) return rc;
+    } else if (spatial) {
         StripArgs a{};
         a.x = j.xtype == ST_F32 ? j.x : nullptr;
         a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
@@ -958,7 +996,8 @@ bool same_key(const BatchKey &a, const BatchKey &b) {
     for (size_t k = 0; k < a.kernels.size(); ++k)
         if (std::memcmp(&a.kernels[k].spatial_fwhm_px, &b.kernels[k].spatial_fwhm_px,
                         sizeof(double)) != 0 ||
-            a.kernels[k].spectral_width_ch != b.kernels[k].spectral_width_ch)
+            a.kernels[k].spectral_width_ch != b.kernels[k].spectral_width_ch ||
+            a.kernels[k].spatial_kind != b.kernels[k].spatial_kind)
             return false;
     return a.t == b.t && a.repl == b.repl && a.sigma0_bits == b.sigma0_bits &&
            a.mode == b.mode && a.range == b.range && a.storage == b.storage &&
@@ -1257,9 +1296,6 @@ int normalise_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64
     if (gz == 0) gz = (wz + 1) / 2;
     if (gxy < 1 || gz < 1 || gxy > 65536 || gz > 65536)
         return fail(h, SOFIA_SC_EINVAL, "grid steps must be 0 (default) or 1..65536");
-    if (mode == SOFIA_SC_NOISE_MAD && (int64_t)wxy * wxy * wz > kNormMaxWindow)
-        return fail(h, SOFIA_SC_EINVAL,
-                    "MAD window larger than SOFIA_SC_NORM_MAX_MAD_VOXELS voxels");
     NormArgs a{};
     a.x = cube;
     a.y = out;
@@ -1443,6 +1479,7 @@ int param_impl(sofia_sc *h, const float *cube, const int32_t *labels, int64_t nx
     a.cube = cube;
     a.labels = labels;
     a.nx = nx; a.ny = ny; a.nz = nz;
+    a.plane = nx * ny;
     a.n = n;
     a.channel_width = opt->channel_width;
     a.omega = (a_fw > 0.0 && b_fw > 0.0) ? std::acos(-1.0) * a_fw * b_fw / (4.0 * std::log(2.0)) : 1.0;

@@ -150,6 +150,33 @@ struct StripArgs {
     const DevState *st;
 };
 
+// Arguments of the sampled-Gaussian spatial kernel (sc_gauss.h): strips of
+// kGaussCols output columns, chunks of `rows` rows. tf / td hold the taps at
+// distance 0..R (the kernel is symmetric) in FP32 (x pass) and FP64 (y pass).
+constexpr int kGaussMaxR = SOFIA_SC_GAUSS_MAX_RADIUS;
+constexpr int kGaussCols = 256;      // output columns per strip = threads per workgroup
+struct GaussArgs {
+    const float *x;              // raw cube (ST_F32)
+    const uint16_t *xq;          // raw cube stored as 16 bits (ST_F16 / ST_BF16)
+    const uint64_t *det;         // packed detection bits (replacement only)
+    int64_t wpp;                 // 64-bit words per plane of det
+    float *p;                    // output: spatially smoothed cube
+    int64_t nx, ny, nz;
+    int32_t nstrips, rows, nchunks, pad;
+    int64_t tiles;               // workgroups: nstrips * nchunks * nz
+    double repl_n;               // n of +-n sigma_0
+    const DevState *st;
+    float tf[kGaussMaxR + 1];
+    double td[kGaussMaxR + 1];
+};
+
+// Taps (distance 0..R, normalised over -R..R) and grid of a sampled Gaussian.
+int gauss_radius(double fwhm);
+void gauss_setup(GaussArgs &a, double fwhm, int rows_max);
+hipError_t launch_gauss(int radius, int xtype, bool repl, const GaussArgs &a, hipStream_t s);
+template <int R>
+hipError_t launch_gauss_r(const GaussArgs &a, int xtype, bool repl, hipStream_t s);
+
 // Arguments of the local noise normalisation (sc_norm.hip). The noise is
 // measured per block of a grid (gxy x gxy x gz voxels) in a window of
 // wxy x wxy x wz voxels around the block's centre; every voxel of a block is
@@ -165,9 +192,9 @@ struct NormArgs {
     int32_t range;               // -1 negative, 0 all, +1 positive
 };
 
-// Largest window (voxels) whose keys the exact-median kernel stages in LDS.
-constexpr int kNormMaxWindow = SOFIA_SC_NORM_MAX_MAD_VOXELS;
-constexpr int kNormThreads = 1024;
+// Threads of the windowed-noise kernel.
+constexpr int kNormThreads = 512;
+constexpr int kNormStage = 4096;     // keys of the median's level-1 bin staged in LDS
 
 hipError_t launch_window_noise(int mode, const NormArgs &a, hipStream_t s);
 hipError_t launch_norm_divide(const NormArgs &a, hipStream_t s);
@@ -214,6 +241,7 @@ struct ParamArgs {
     const float *cube;
     const int *labels;
     int64_t nx, ny, nz;
+    int64_t plane;                   // nx * ny
     int64_t n;                       // detections 1..n
     double channel_width, omega, sigma_rms;
     double scale, rel_threshold, snr_threshold;

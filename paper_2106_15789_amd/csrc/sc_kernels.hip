@@ -22,6 +22,8 @@
 //    on the device, so a run never waits on the host between launches.
 #include <math.h>
 
+#include <cmath>
+
 #include "sc_device.h"
 
 namespace sc {
@@ -544,6 +546,44 @@ hipError_t launch_spatial(int n_iter, int radius, int xtype, bool repl,
     SC_SP(5, 1) SC_SP(5, 2) SC_SP(5, 3)
     SC_SP(6, 1) SC_SP(6, 2)
 #undef SC_SP
+    return hipErrorInvalidValue;
+}
+
+int gauss_radius(double fwhm) {
+    const double sigma = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    return (int)std::floor(4.0 * sigma + 0.5);
+}
+
+void gauss_setup(GaussArgs &a, double fwhm, int rows_max) {
+    const double sigma = fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const int R = gauss_radius(fwhm);
+    double h[kGaussMaxR + 1] = {};
+    double sum = 0.0;
+    for (int k = 0; k <= R && k <= kGaussMaxR; ++k) {
+        h[k] = std::exp(-(double)k * (double)k / (2.0 * sigma * sigma));
+        sum += k == 0 ? h[k] : 2.0 * h[k];
+    }
+    for (int k = 0; k <= kGaussMaxR; ++k) {
+        a.td[k] = k <= R ? h[k] / sum : 0.0;
+        a.tf[k] = (float)a.td[k];
+    }
+    a.nstrips = (int32_t)((a.nx + kGaussCols - 1) / kGaussCols);
+    int64_t rows = rows_max;
+    while (rows > 32 && (int64_t)a.nstrips * ((a.ny + rows - 1) / rows) * a.nz < 16384) rows /= 2;
+    if (rows > a.ny) rows = a.ny;
+    a.rows = (int32_t)rows;
+    a.nchunks = (int32_t)((a.ny + rows - 1) / rows);
+    a.tiles = (int64_t)a.nstrips * a.nchunks * a.nz;
+}
+
+hipError_t launch_gauss(int radius, int xtype, bool repl, const GaussArgs &a, hipStream_t s) {
+    switch (radius) {
+#define SC_G(R) case R: return launch_gauss_r<R>(a, xtype, repl, s);
+        SC_G(1) SC_G(2) SC_G(3) SC_G(4) SC_G(5) SC_G(6) SC_G(7) SC_G(8)
+        SC_G(9) SC_G(10) SC_G(11) SC_G(12) SC_G(13) SC_G(14) SC_G(15) SC_G(16)
+        SC_G(17) SC_G(18) SC_G(19) SC_G(20) SC_G(21) SC_G(22) SC_G(23) SC_G(24)
+#undef SC_G
+    }
     return hipErrorInvalidValue;
 }
 

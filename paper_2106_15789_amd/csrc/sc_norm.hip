@@ -94,8 +94,8 @@ __device__ void find_rank(const uint32_t *hist, int nbins, uint32_t rank, uint32
 
 template <bool MAD>
 __global__ __launch_bounds__(kNormThreads) void k_window_noise(NormArgs a) {
-    extern __shared__ uint32_t lds[];
-    // MAD: keys [wxy * wxy * wz] | histogram [2048]; RMS: nothing dynamic
+    __shared__ uint32_t hist[MAD ? 2048 : 1];
+    __shared__ uint32_t stage[MAD ? kNormStage : 1];
     __shared__ uint32_t scan[kNormThreads / 64];
     __shared__ uint32_t res[8];
     __shared__ double psum[kNormThreads / 64];
@@ -116,65 +116,60 @@ __global__ __launch_bounds__(kNormThreads) void k_window_noise(NormArgs a) {
     const bool two = wx <= 32;
     const int slot = two ? lane >> 5 : 0, sl = two ? lane & 31 : lane;
     const int step_x = two ? 32 : 64, slots = nwaves * (two ? 2 : 1);
-
-    uint32_t *keys = lds;
-    uint32_t *hist = lds + (int64_t)a.wxy * a.wxy * a.wz;   // after the largest window's keys
-    if (MAD) {
-        for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0u;
-        if (tid == 0) res[0] = 0u;   // keys staged
-        __syncthreads();
-    }
     const bool all_range = a.range == 0;
     const float rsgn = (float)a.range;
-    double acc = 0.0;
-    unsigned long long cnt = 0;
-    // items: (row, 32- or 64-column piece of it); every slot takes every
-    // slots-th item, four at a time so that four loads are in flight
+
+    // Stream the window: row slot q (0 .. slots-1) takes the rows q,
+    // q + slots, ..., UN of them at a time so that UN loads are in flight,
+    // each row in pieces of step_x columns; a row's (y, z) offset inside the
+    // window advances incrementally (no division per item). visit(v, sel) is
+    // called for every item, selected (finite, in the flux range) or not.
     const int pieces = (wx + step_x - 1) / step_x;
-    const int items = nrows * pieces;
-    constexpr int UN = 4;
-    for (int i0 = wave * (two ? 2 : 1) + slot; i0 < items; i0 += UN * slots) {
-        float v[UN];
-        bool sel[UN];
+    const int q = wave * (two ? 2 : 1) + slot;
+    const int dz_step = slots / wy, dy_step = slots - dz_step * wy;
+    auto stream = [&](auto &&visit) {
+        constexpr int UN = 4;
+        int cy = q % wy, cz = q / wy;
+        for (int r0 = q; r0 < nrows; r0 += UN * slots) {
+            int64_t rowoff[UN];
+            bool rin[UN];
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-            const int it = i0 + u * slots;
-            const int r = it / pieces, xx = (it - r * pieces) * step_x + sl;
-            v[u] = 0.f;
-            if (it < items && xx < wx) {
-                const int64_t yy = y0 + r % wy, zz = z0 + r / wy;
-                v[u] = a.x[(zz * a.ny + yy) * a.nx + x0 + xx];
-                sel[u] = isfinite(v[u]) && (all_range || v[u] * rsgn > 0.f);
-            } else {
-                sel[u] = false;
+            for (int u = 0; u < UN; ++u) {
+                rin[u] = r0 + u * slots < nrows;
+                rowoff[u] = ((z0 + cz) * a.ny + y0 + cy) * a.nx + x0;
+                cy += dy_step;
+                cz += dz_step;
+                if (cy >= wy) { cy -= wy; ++cz; }
+            }
+            for (int p = 0; p < pieces; ++p) {
+                const int xx = p * step_x + sl;
+                const bool xin = xx < wx;
+                float v[UN];
+                bool sel[UN];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    v[u] = 0.f;
+                    sel[u] = false;
+                    if (rin[u] && xin) {
+                        v[u] = a.x[rowoff[u] + xx];
+                        sel[u] = isfinite(v[u]) && (all_range || v[u] * rsgn > 0.f);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UN; ++u) visit(v[u], sel[u]);
             }
         }
-#pragma unroll
-        for (int u = 0; u < UN; ++u) {
-            if (MAD) {
-                // append the keys of this wave's selected voxels
-                const unsigned long long bal = __ballot(sel[u]);
-                const int nsel = __popcll(bal);
-                uint32_t base = 0;
-                const int leader = __ffsll((long long)(bal | 1ull)) - 1;
-                if (nsel && lane == leader) base = atomicAdd(&res[0], (uint32_t)nsel);
-                base = __shfl(base, leader);
-                if (sel[u]) {
-                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    const uint32_t key = __float_as_uint(fabsf(v[u]));
-                    keys[base + below] = key;
-                    atomicAdd(&hist[key >> 20], 1u);
-                }
-            } else if (sel[u]) {
-                acc += (double)v[u] * (double)v[u];
+    };
+
+    if (!MAD) {
+        double acc = 0.0;
+        unsigned long long cnt = 0;
+        stream([&](float v, bool sel) {
+            if (sel) {
+                acc += (double)v * (double)v;
                 cnt += 1;
             }
-        }
-    }
-
-    double sigma;
-    if (!MAD) {
+        });
         // fixed-order reduction: waves, then the wave totals
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -187,11 +182,25 @@ __global__ __launch_bounds__(kNormThreads) void k_window_noise(NormArgs a) {
         double s = 0.0;
         unsigned long long m = 0;
         for (int w = 0; w < nwaves; ++w) { s += psum[w]; m += pcnt[w]; }
-        sigma = m ? sqrt(s / (double)m) : (double)NAN;
-        a.sigma[b] = sigma;
+        a.sigma[b] = m ? sqrt(s / (double)m) : (double)NAN;
         return;
     }
 
+    // MAD. Keys are the bit patterns of |v| (they order like the values).
+    // Pass 1: level-1 histogram of bits 30..20 and the number of keys m.
+    for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0u;
+    if (tid == 0) { res[0] = 0u; res[5] = 0u; res[6] = 0xffffffffu; }
+    __syncthreads();
+    uint32_t mine = 0;
+    stream([&](float v, bool sel) {
+        if (sel) {
+            atomicAdd(&hist[__float_as_uint(fabsf(v)) >> 20], 1u);
+            ++mine;
+        }
+    });
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_down(mine, off);
+    if (lane == 0) atomicAdd(&res[0], mine);
     __syncthreads();
     const uint32_t m = res[0];
     if (m == 0) {
@@ -199,16 +208,62 @@ __global__ __launch_bounds__(kNormThreads) void k_window_noise(NormArgs a) {
         return;
     }
     const uint32_t r_lo = (m - 1) / 2, r_hi = m / 2;
-    // level 1: bits 30..20
     find_rank(hist, 2048, r_lo, scan, res + 1);
     const uint32_t b1 = res[1], below1 = res[2];
+    const uint32_t in_b1 = hist[b1];
+    // the upper order statistic lies in a higher bin when the lower one is
+    // the last key of bin b1: it is then the smallest key above bin b1
+    const bool hi_above = r_hi >= below1 + in_b1;
+    const bool staged = in_b1 <= (uint32_t)kNormStage;
+    __syncthreads();
+
+    // Pass 2: the keys of bin b1 into LDS (when they fit), and the smallest
+    // key above bin b1.
+    uint32_t above = 0xffffffffu;
+    stream([&](float v, bool sel) {
+        const uint32_t key = __float_as_uint(fabsf(v));
+        const bool in = sel && (key >> 20) == b1;
+        if (hi_above && sel && (key >> 20) > b1 && key < above) above = key;
+        if (staged) {
+            const unsigned long long bal = __ballot(in);
+            const int nsel = __popcll(bal);
+            uint32_t base = 0;
+            const int leader = __ffsll((long long)(bal | 1ull)) - 1;
+            if (nsel && lane == leader) base = atomicAdd(&res[5], (uint32_t)nsel);
+            base = __shfl(base, leader);
+            if (in) {
+                const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                stage[base + below] = key;
+            }
+        }
+    });
+    if (hi_above) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t t = __shfl_down(above, off);
+            above = t < above ? t : above;
+        }
+        if (lane == 0) atomicMin(&res[6], above);
+    }
+    __syncthreads();
+    const uint32_t k_above = res[6];
+
+    // the keys of bin b1, from LDS or (when they did not fit) from HBM again
+    auto for_bin_keys = [&](auto &&f) {
+        if (staged) {
+            for (uint32_t i = tid; i < in_b1; i += blockDim.x) f(stage[i]);
+        } else {
+            stream([&](float v, bool sel) {
+                const uint32_t key = __float_as_uint(fabsf(v));
+                if (sel && (key >> 20) == b1) f(key);
+            });
+        }
+    };
     // level 2: bits 19..10 of the keys in bin b1
     for (int i = tid; i < 1024; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
-    for (uint32_t i = tid; i < m; i += blockDim.x) {
-        const uint32_t k = keys[i];
-        if ((k >> 20) == b1) atomicAdd(&hist[(k >> 10) & 1023u], 1u);
-    }
+    for_bin_keys([&](uint32_t k) { atomicAdd(&hist[(k >> 10) & 1023u], 1u); });
     __syncthreads();
     find_rank(hist, 1024, r_lo - below1, scan, res + 1);
     const uint32_t b2 = res[1], below2 = res[2];
@@ -216,10 +271,9 @@ __global__ __launch_bounds__(kNormThreads) void k_window_noise(NormArgs a) {
     for (int i = tid; i < 1024; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
     const uint32_t pre = (b1 << 10) | b2;
-    for (uint32_t i = tid; i < m; i += blockDim.x) {
-        const uint32_t k = keys[i];
+    for_bin_keys([&](uint32_t k) {
         if ((k >> 10) == pre) atomicAdd(&hist[k & 1023u], 1u);
-    }
+    });
     __syncthreads();
     find_rank(hist, 1024, r_lo - below1 - below2, scan, res + 1);
     const uint32_t b3 = res[1], below3 = res[2];
@@ -227,15 +281,16 @@ __global__ __launch_bounds__(kNormThreads) void k_window_noise(NormArgs a) {
     // keys at or below k_lo
     const uint32_t le = below1 + below2 + below3 + hist[b3];
     uint32_t k_hi = k_lo;
-    if (r_hi >= le) {
-        // the next larger key: a min-reduction over the keys above k_lo
+    if (hi_above) {
+        k_hi = k_above;
+    } else if (r_hi >= le) {
+        // the next larger key inside bin b1: a min-reduction
         if (tid == 0) res[4] = 0xffffffffu;
         __syncthreads();
         uint32_t mn = 0xffffffffu;
-        for (uint32_t i = tid; i < m; i += blockDim.x) {
-            const uint32_t k = keys[i];
+        for_bin_keys([&](uint32_t k) {
             if (k > k_lo && k < mn) mn = k;
-        }
+        });
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const uint32_t t = __shfl_down(mn, off);
@@ -277,16 +332,10 @@ __global__ __launch_bounds__(256) void k_norm_divide(NormArgs a, int64_t chunks,
 hipError_t launch_window_noise(int mode, const NormArgs &a, hipStream_t s) {
     const int64_t nb = (int64_t)a.nbx * a.nby * a.nbz;
     if (nb < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (mode == SOFIA_SC_NOISE_MAD) {
-        const int64_t vol = (int64_t)a.wxy * a.wxy * a.wz;
-        if (vol > kNormMaxWindow) return hipErrorInvalidValue;
-        const size_t lds = (size_t)(vol + 2048) * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_window_noise<true>, dim3((unsigned)nb), dim3(kNormThreads), lds, s,
-                           a);
-    } else {
-        hipLaunchKernelGGL(k_window_noise<false>, dim3((unsigned)nb), dim3(kNormThreads), 0, s,
-                           a);
-    }
+    if (mode == SOFIA_SC_NOISE_MAD)
+        hipLaunchKernelGGL(k_window_noise<true>, dim3((unsigned)nb), dim3(kNormThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_window_noise<false>, dim3((unsigned)nb), dim3(kNormThreads), 0, s, a);
     return hipGetLastError();
 }
 

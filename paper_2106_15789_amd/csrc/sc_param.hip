@@ -19,6 +19,7 @@
 //    the positive (P) and negative (N) detections around it, tiled through
 //    LDS; R = max(0, (P - N) / P); a detection is kept when positive with
 //    R >= the reliability threshold and SNR >= the SNR threshold.
+#include <climits>
 #include <math.h>
 
 #include "sc_internal.h"
@@ -66,26 +67,167 @@ __device__ __forceinline__ void add_voxel(const ParamArgs &a, int64_t i, int l) 
     atomicMin(&s->mn, k);
 }
 
+// Wave-wide reductions (every lane of the wave takes part).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+// One record per lane (valid: it holds voxels of detection l in 1..n): its
+// voxel count, sums of v, v x, v y, v z and the order keys of its largest
+// and smallest value. The lanes that share a label are reduced across the
+// wave first, and one lane per label updates that detection's
+// accumulators: neighbouring voxels mostly carry the same label, so this
+// replaces up to 64 contended atomics by one.
+struct Rec {
+    int cnt;
+    double s, sx, sy, sz;
+    int kmax, kmin;
+};
+
+__device__ __forceinline__ void rec_add(Rec &r, float v, int64_t x, int64_t y, int64_t z) {
+    const double d = (double)v;
+    r.cnt += 1;
+    r.s += d;
+    r.sx += d * (double)x;
+    r.sy += d * (double)y;
+    r.sz += d * (double)z;
+    const int k = order_key(v);
+    r.kmax = max(r.kmax, k);
+    r.kmin = min(r.kmin, k);
+}
+
+__device__ __forceinline__ Rec rec_empty() {
+    Rec r;
+    r.cnt = 0;
+    r.s = r.sx = r.sy = r.sz = 0.0;
+    r.kmax = INT_MIN;
+    r.kmin = INT_MAX;
+    return r;
+}
+
+__device__ __forceinline__ void add_records_wave(const ParamArgs &a, bool valid, int l,
+                                                 const Rec &r) {
+    uint64_t pending = __ballot(valid);
+    const int lane = threadIdx.x & 63;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int lab = __shfl(l, leader);
+        const bool mine = valid && l == lab;
+        const uint64_t m = __ballot(mine);
+        const double s = wave_sum(mine ? r.s : 0.0);
+        const double sx = wave_sum(mine ? r.sx : 0.0);
+        const double sy = wave_sum(mine ? r.sy : 0.0);
+        const double sz = wave_sum(mine ? r.sz : 0.0);
+        int c = mine ? r.cnt : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+        const int pk = wave_max(mine ? r.kmax : INT_MIN);
+        const int mn = wave_min(mine ? r.kmin : INT_MAX);
+        if (lane == leader) {
+            SrcAcc *p = a.acc + (lab - 1);
+            atomicAdd(&p->count, (unsigned long long)c);
+            atomicAdd(&p->sum, s);
+            atomicAdd(&p->sx, sx);
+            atomicAdd(&p->sy, sy);
+            atomicAdd(&p->sz, sz);
+            atomicMax(&p->peak, pk);
+            atomicMin(&p->mn, mn);
+        }
+        pending &= ~m;
+    }
+}
+
 // The label cube is read whole (four labels per load when aligned); the
-// cube's values only where a label is set.
+// cube's values only where a label is set. Waves step through the cube
+// together, so the wave-wide reductions see every lane.
 template <int V>
 __global__ __launch_bounds__(256) void k_param_accum(ParamArgs a) {
     const int64_t N = a.nx * a.ny * a.nz;
     const int64_t nq = N / V;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t q = t; q < nq; q += stride) {
+    const int64_t wbase = t - (threadIdx.x & 63);
+    for (int64_t qb = wbase; qb < nq; qb += stride) {
+        const int64_t q = qb + (threadIdx.x & 63);
         int lab[V];
-        if constexpr (V == 4) {
-            const int4 l4 = reinterpret_cast<const int4 *>(a.labels)[q];
-            lab[0] = l4.x; lab[1] = l4.y; lab[2] = l4.z; lab[3] = l4.w;
+        if (q < nq) {
+            if constexpr (V == 4) {
+                const int4 l4 = reinterpret_cast<const int4 *>(a.labels)[q];
+                lab[0] = l4.x; lab[1] = l4.y; lab[2] = l4.z; lab[3] = l4.w;
+            } else {
+                lab[0] = a.labels[q];
+            }
         } else {
-            lab[0] = a.labels[q];
-        }
 #pragma unroll
-        for (int k = 0; k < V; ++k)
-            if (lab[k] > 0 && lab[k] <= a.n) add_voxel(a, q * V + k, lab[k]);
+            for (int k = 0; k < V; ++k) lab[k] = 0;
+        }
+        // position of voxel q V (only for lanes holding a label): one
+        // division by the plane size, then 32-bit arithmetic (planes hold
+        // < 2^28 voxels)
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < V; ++k) any |= lab[k] > 0 && lab[k] <= a.n;
+        int64_t x0 = 0, y0 = 0, z0 = 0;
+        if (any) {
+            const int64_t i0 = q * V;
+            z0 = i0 / a.plane;
+            const uint32_t rem = (uint32_t)(i0 - z0 * a.plane);
+            y0 = rem / (uint32_t)a.nx;
+            x0 = rem - (uint32_t)y0 * (uint32_t)a.nx;
+        }
+        // the lane's voxels as one record when they all carry one label
+        // (the usual case), else one record per voxel
+        int L = 0;
+        bool mixed = false;
+        float v[V];
+        int64_t px[V], py[V], pz[V];
+        {
+            int64_t x = x0, y = y0, z = z0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                px[k] = x; py[k] = y; pz[k] = z;
+                const bool in = lab[k] > 0 && lab[k] <= a.n;
+                v[k] = in ? a.cube[q * V + k] : 0.f;
+                if (!(in && isfinite(v[k]))) lab[k] = 0;
+                if (lab[k]) {
+                    if (L == 0) L = lab[k];
+                    else if (lab[k] != L) mixed = true;
+                }
+                if (++x == a.nx) {
+                    x = 0;
+                    if (++y == a.ny) { y = 0; ++z; }
+                }
+            }
+        }
+        Rec r = rec_empty();
+        if (L && !mixed) {
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (lab[k]) rec_add(r, v[k], px[k], py[k], pz[k]);
+        }
+        add_records_wave(a, L != 0 && !mixed, L, r);
+        if (__ballot(mixed)) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                Rec rk = rec_empty();
+                if (mixed && lab[k]) rec_add(rk, v[k], px[k], py[k], pz[k]);
+                add_records_wave(a, mixed && lab[k] != 0, lab[k], rk);
+            }
+        }
     }
+    // the last N mod V voxels, one thread each
     for (int64_t i = nq * V + t; i < N; i += stride) {
         const int l = a.labels[i];
         if (l > 0 && l <= a.n) add_voxel(a, i, l);

@@ -32,6 +32,14 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def sc_kind(kernel) -> int:
+    """Spatial kind of a kernel tuple: 0 cascade, 1 sampled Gaussian."""
+    if len(kernel) < 3:
+        return 0
+    k = kernel[2]
+    return {"cascade": 0, "gauss": 1}[k] if isinstance(k, str) else int(k)
+
+
 def forced_chain(h, xd, x, kernels, t, mode, rng_, repl, what="", storage="f32",
                  sigma0=float("nan"), x_oracle=None, full=None, sigma_ok=None,
                  plane_stride=1):
@@ -63,7 +71,9 @@ def forced_chain(h, xd, x, kernels, t, mode, rng_, repl, what="", storage="f32",
     s0_oracle = 1.0 if q16 else fs0
     prev = None
     worst, bands = 0.0, 0
-    for k, (f, w) in enumerate(kernels):
+    for k, kern in enumerate(kernels):
+        f, w = kern[0], kern[1]
+        kind = sc_kind(kern)
         if k == len(kernels) - 1:
             m_k, n_k = fm, fn
         else:
@@ -74,7 +84,8 @@ def forced_chain(h, xd, x, kernels, t, mode, rng_, repl, what="", storage="f32",
             assert (np.isnan(s_k) and np.isnan(fs0)) or s_k == fs0, f"{what}: cut run sigma_0"
         torch.cuda.synchronize()
         g = m_k.cpu().numpy()
-        ref = oracle.step(xo, f, w, t, mode, rng_, prev, repl, s0_oracle, plane_stride=ps)
+        ref = oracle.step(xo, f, w, t, mode, rng_, prev, repl, s0_oracle, plane_stride=ps,
+                          kind=kind)
         rel = abs(n_k[k] / unit / ref.sigma - 1)
         diff = g != ref.mask
         out = int((diff & (ref.band == 0)).sum())

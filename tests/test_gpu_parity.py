@@ -168,6 +168,15 @@ def test_run_cfg2_like_end_to_end(h):
                            what="cfg2-like 200x170x160")
 
 
+def test_replacement_level_1_5_forced_chain(h):
+    """Replacement at +-1.5 sigma_0, the alternative level the paper studies
+    for the integrated flux (Sect. 6.2.4), every iteration checked from the
+    GPU's own previous state."""
+    x = cfg2_like(160, 150, 120, seed=9, n_gal=10)
+    gpu_chain.forced_chain(h, dev(x), x, KERNELS_CFG2, 3.5, "mad", "negative", 1.5,
+                           what="replacement 1.5")
+
+
 def test_replacement_off_matches(h):
     x = cfg2_like(96, 80, 90, seed=8, n_gal=5)
     kernels = [(0.0, 3), (3.0, 0), (6.0, 7)]

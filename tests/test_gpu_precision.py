@@ -180,8 +180,8 @@ def _sigma_ok(q, kernels, mode, rng_, tag):
         rel = abs(gpu_sigma / ref_sigma - 1)
         if rel <= 1e-6:
             return True
-        f, w = kernels[k]
-        s_ref = oracle.smooth(q, f, w, mask_prev, 2.0, 1.0)
+        f, w = kernels[k][0], kernels[k][1]
+        s_ref = oracle.smooth(q, f, w, mask_prev, 2.0, 1.0, kind=gpu_chain.sc_kind(kernels[k]))
         lo, hi = _noise_interval(s_ref, mode, rng_)
         say(f"{tag} step {k} ({f}, {w}): sigma rel {rel:.2e}, smoothing-bar interval "
             f"[{lo / ref_sigma - 1:.2e}, {hi / ref_sigma - 1:.2e}]")
