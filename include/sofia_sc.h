@@ -102,6 +102,16 @@ typedef struct {
                                z = 0, s, 2s, ... only; every voxel is still
                                smoothed and clipped. 0 or 1 (default): every
                                plane, the whole cube */
+    int32_t fuse_widths;    /* 1: with replacement off (replacement < 0) the
+                               pairs are independent; the pairs that share a
+                               spatial kernel then share their passes: one
+                               pass computes every spectral width's smoothed
+                               values and RMS partials, one finaliser, one
+                               pass clips every width (ORed into the mask).
+                               Same results as 0 up to the summation order of
+                               the noise. Needs RMS noise and FP32 storage
+                               (sofia_sc_run / _run_ex only; EINVAL
+                               otherwise). 0 (default): one pair at a time */
     void *stream;           /* hipStream_t to run on; NULL = null stream */
 } sofia_sc_options;
 
@@ -420,6 +430,14 @@ int sofia_sc_parameterise(sofia_sc *h, const float *cube, const int32_t *labels,
                           int64_t ny, int64_t nz, int64_t n_sources,
                           const sofia_sc_param_options *opt, sofia_sc_source *out,
                           int64_t *n_kept, void *stream);
+
+/* The argument checks of sofia_sc_run_ex (the same code, run before any
+ * device work) for a cube of nx x ny x nz voxels, a kernel list, threshold,
+ * modes and options: SOFIA_SC_OK or the code the run would return (EINVAL).
+ * Needs no handle, no device and no buffers. */
+int sofia_sc_check_run(int64_t nx, int64_t ny, int64_t nz, const sofia_sc_kernel *kernels,
+                       int32_t n_kernels, double threshold, int32_t noise_mode,
+                       int32_t flux_range, const sofia_sc_options *opt);
 
 /* Spatial cascade for a FWHM: n_iter boxcars of radius r per axis, chosen to
  * match the Gaussian variance, sigma_g^2 = (FWHM / 2 sqrt(2 ln 2))^2, with

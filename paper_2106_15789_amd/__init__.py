@@ -22,7 +22,7 @@ SOURCES = [os.path.join(_HERE, "csrc", n) for n in (
     "sc_kernels.hip", "sc_spatial_n3.hip", "sc_spatial_n4.hip", "sc_spatial_n5.hip",
     "sc_spatial_n6.hip", "sc_col_std.hip", "sc_col_hist.hip", "sc_col_select.hip", "sc_col_selclip.hip",
     "sc_col_clip.hip", "sc_col_write.hip", "sc_norm.hip", "sc_link.hip", "sc_param.hip",
-    "sc_gauss_a.hip", "sc_gauss_b.hip", "sc_gauss_c.hip", "sc_api.hip")]
+    "sc_gauss_a.hip", "sc_gauss_b.hip", "sc_gauss_c.hip", "sc_multi.hip", "sc_api.hip")]
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOSTAT = 0, -1, -2, -3, -4
 NOISE = {"std": 0, "mad": 1}
@@ -36,7 +36,7 @@ EXPORTS = [
     "sofia_sc_step", "sofia_sc_step_ex",
     "sofia_sc_smooth",
     "sofia_sc_normalise", "sofia_sc_normalise_grid", "sofia_sc_link",
-    "sofia_sc_param_defaults", "sofia_sc_parameterise",
+    "sofia_sc_param_defaults", "sofia_sc_parameterise", "sofia_sc_check_run",
     "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile", "sofia_sc_profile_read",
     "sofia_sc_last_error", "sofia_sc_strerror",
 ]
@@ -96,6 +96,7 @@ class Options(ctypes.Structure):
                 ("storage", ctypes.c_int32),
                 ("keep_input_mask", ctypes.c_int32),
                 ("noise_plane_stride", ctypes.c_int32),
+                ("fuse_widths", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -182,6 +183,8 @@ def load():
                                        vp, vp, vp]
     lib.sofia_sc_link.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, i32, i32, vp,
                                   ctypes.POINTER(i64), vp, i64, vp]
+    lib.sofia_sc_check_run.argtypes = [i64, i64, i64, ctypes.POINTER(Kernel), i32, dbl, i32, i32,
+                                       ctypes.POINTER(Options)]
     lib.sofia_sc_param_defaults.argtypes = [ctypes.POINTER(ParamOptions)]
     lib.sofia_sc_param_defaults.restype = None
     lib.sofia_sc_parameterise.argtypes = [vp, vp, vp, i64, i64, i64, i64,
@@ -206,7 +209,7 @@ def load():
                  "sofia_sc_step_ex",
                  "sofia_sc_smooth", "sofia_sc_plan", "sofia_sc_quantize", "sofia_sc_profile",
                  "sofia_sc_normalise", "sofia_sc_normalise_grid", "sofia_sc_link",
-                 "sofia_sc_parameterise", "sofia_sc_profile_read"):
+                 "sofia_sc_parameterise", "sofia_sc_check_run", "sofia_sc_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -304,12 +307,13 @@ class SofiaSC:
             flux_range: str = "negative", replacement: float = 2.0, mask=None,
             stream=None, allow_nostat: bool = False, storage: str = "f32",
             sigma0: float = float("nan"), keep_input_mask: bool = False,
-            noise_plane_stride: int = 0):
+            noise_plane_stride: int = 0, fuse_widths: bool = False):
         """Whole S+C run. Returns (mask uint8 tensor, noise[K] ndarray, sigma0).
 
         keep_input_mask: OR the detections into the given mask instead of
         overwriting it. noise_plane_stride: measure every noise on every n-th
-        plane only."""
+        plane only. fuse_widths: with replacement off and RMS noise, the pairs
+        sharing a spatial kernel share their passes."""
         import torch
         nx, ny, nz = _check_cube(cube)
         _check_like(mask, cube, torch.uint8, "mask")
@@ -325,6 +329,7 @@ class SofiaSC:
         opt.storage = STORAGE[storage]
         opt.keep_input_mask = 1 if keep_input_mask else 0
         opt.noise_plane_stride = int(noise_plane_stride)
+        opt.fuse_widths = 1 if fuse_widths else 0
         opt.stream = _stream_ptr(stream)
         rc = self.lib.sofia_sc_run_ex(self.h, cube.data_ptr(), nx, ny, nz,
                                       _kernels(kernels), K, float(threshold),

@@ -25,7 +25,7 @@ enum Family {
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
     F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
     F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_PARAM, F_RELIABILITY, F_SPATIAL_GAUSS,
-    F_COUNT
+    F_MULTI_STATS, F_MULTI_CLIP, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
@@ -33,7 +33,7 @@ const char *kFamilyName[F_COUNT] = {
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
     "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide",
     "link_union", "link_number", "link_label", "parameterise", "reliability",
-    "spatial_gauss"};
+    "spatial_gauss", "fused_stats", "fused_clip"};
 
 struct LaunchRec {
     int fam;
@@ -176,6 +176,11 @@ struct sofia_sc {
     size_t pm_vec_cap = 0;
     double *pm_state = nullptr;
     size_t pm_state_cap = 0;
+    // partials of the fused spectral-widths passes
+    double *mu_sum = nullptr;
+    size_t mu_sum_cap = 0;
+    unsigned long long *mu_cnt = nullptr;
+    size_t mu_cnt_cap = 0;
 };
 
 namespace {
@@ -529,21 +534,14 @@ struct PairJob {
     int zstride = 1;        // the noise is measured on every zstride-th plane
 };
 
-int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
+// The spatial pass of a kernel pair: the raw cube (with replacement and
+// blanking) smoothed spatially into w.p.
+int spatial_pass(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     const Dims &d = j.d;
     const double N = (double)d.N;
-    int rc;
-    const bool spatial = j.pl.spatial();
-    const bool spec = j.pl.spectral();
-    const bool has_wm = j.wm_in != nullptr;
     const double bx = j.xtype != ST_F32 ? 2.0 : 4.0;   // bytes per raw voxel
-    if ((spatial || spec) && !has_wm)
-        return fail(h, SOFIA_SC_EINVAL, "internal: smoothing without working mask");
-
-    const ColGrid g = col_grid(d.ncol, d.nz, w.sh);
-    if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
-        return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
-    if (spatial && j.pl.gauss_r > 0) {
+    int rc;
+    if (j.pl.gauss_r > 0) {
         GaussArgs a{};
         a.x = j.xtype == ST_F32 ? j.x : nullptr;
         a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
@@ -566,7 +564,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
             return launch_gauss(j.pl.gauss_r, j.xtype, j.repl_active, a, s);
         });
         if (rc) return rc;
-    } else if (spatial) {
+    } else {
         StripArgs a{};
         a.x = j.xtype == ST_F32 ? j.x : nullptr;
         a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
@@ -592,6 +590,25 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         });
         if (rc) return rc;
     }
+
+    return SOFIA_SC_OK;
+}
+
+int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
+    const Dims &d = j.d;
+    const double N = (double)d.N;
+    int rc;
+    const bool spatial = j.pl.spatial();
+    const bool spec = j.pl.spectral();
+    const bool has_wm = j.wm_in != nullptr;
+    const double bx = j.xtype != ST_F32 ? 2.0 : 4.0;   // bytes per raw voxel
+    if ((spatial || spec) && !has_wm)
+        return fail(h, SOFIA_SC_EINVAL, "internal: smoothing without working mask");
+
+    const ColGrid g = col_grid(d.ncol, d.nz, w.sh);
+    if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
+        return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
+    if (spatial && (rc = spatial_pass(h, s, w, j))) return rc;
 
     ColArgs c{};
     c.x = j.x;
@@ -847,6 +864,8 @@ int check_options(sofia_sc *h, const sofia_sc_options *opt) {
         return fail(h, SOFIA_SC_EINVAL, "sigma0 must be NaN (measure) or finite and > 0");
     if (opt->noise_plane_stride < 0 || opt->noise_plane_stride > (1 << 30))
         return fail(h, SOFIA_SC_EINVAL, "noise_plane_stride must be 0..2^30");
+    if (opt->fuse_widths != 0 && opt->fuse_widths != 1)
+        return fail(h, SOFIA_SC_EINVAL, "fuse_widths must be 0 or 1");
     return SOFIA_SC_OK;
 }
 
@@ -935,6 +954,95 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     return SOFIA_SC_OK;
 }
 
+// Replacement off: the kernel pairs are independent, and the pairs that
+// share a spatial kernel share their passes. Per spatial kernel (in order of
+// first appearance) and up to kMultiMax of its spectral widths: the spatial
+// pass (if any), one pass accumulating every width's RMS partials, one
+// finaliser, one clip pass ORing every width's detections into the mask.
+int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
+    int rc;
+    const Dims &d = r.d;
+    const double N = (double)d.N;
+    const bool any_spatial = r.any_spatial();
+    rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_set_sigma0(w.st, NAN, s); });
+    if (rc) return rc;
+    if (any_spatial) {
+        rc = launch(h, s, F_INIT, 5.0 * N, N, [&] {
+            return launch_init_mask(r.cube, nullptr, w.wm[0], d.N, s);
+        });
+        if (rc) return rc;
+    }
+    const ColGrid g = col_grid(d.ncol, d.nz, w.sh);
+    if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
+        return fail(h, SOFIA_SC_EINVAL, "cube too large for the column grid");
+    const size_t parts = (size_t)g.blocks() * kMultiMax;
+    if ((rc = grow(h, h->mu_sum, h->mu_sum_cap, parts, "fused partials", nullptr)) ||
+        (rc = grow(h, h->mu_cnt, h->mu_cnt_cap, parts, "fused counts", nullptr)))
+        return rc;
+    // groups of kernels with the same spatial kernel, in order of first use
+    std::vector<int> done((size_t)r.K, 0);
+    bool first = true;
+    for (int k0 = 0; k0 < r.K; ++k0) {
+        if (done[k0]) continue;
+        const Plan &sp = r.plans[k0];
+        std::vector<int> ks;
+        for (int k = k0; k < r.K; ++k) {
+            const Plan &q = r.plans[k];
+            if (!done[k] && q.n_iter == sp.n_iter && q.radius == sp.radius &&
+                q.gauss_r == sp.gauss_r && (q.gauss_r == 0 || q.fwhm == sp.fwhm)) {
+                ks.push_back(k);
+                done[k] = 1;
+            }
+        }
+        const bool spatial = sp.spatial();
+        if (spatial) {
+            PairJob j{r.cube, nullptr, ST_F32, d, sp, k0, false, 0.0, r.mode, r.range, r.t,
+                      w.wm[0], nullptr, false, false, nullptr};
+            if ((rc = spatial_pass(h, s, w, j))) return rc;
+        }
+        for (size_t c0 = 0; c0 < ks.size(); c0 += kMultiMax) {
+            MultiArgs m{};
+            m.src = spatial ? w.p : r.cube;
+            m.wm = spatial ? w.wm[0] : nullptr;
+            m.mask = r.mask;
+            m.st = w.st;
+            m.part_sum = h->mu_sum;
+            m.part_cnt = h->mu_cnt;
+            m.ncol = d.ncol;
+            m.nz = d.nz;
+            m.ncb = g.ncb;
+            m.zchunk = g.zchunk;
+            m.nparts = g.blocks();
+            m.range = r.range;
+            m.zstride = r.zstride;
+            m.t = r.t;
+            m.hmax = 0;
+            for (size_t i = c0; i < ks.size() && m.nw < kMultiMax; ++i) {
+                const int wd = r.plans[ks[i]].width;
+                m.w[m.nw] = wd;
+                m.h[m.nw] = (wd - 1) / 2;
+                m.k[m.nw] = ks[i];
+                m.hmax = std::max(m.hmax, m.h[m.nw]);
+                ++m.nw;
+            }
+            m.or_mask = (!first || r.keep) ? 1 : 0;
+            const int src = spatial ? SRC_P : SRC_X;
+            // algorithmic bytes: the source once (+ the blank bits) per pass;
+            // the clip's mask write (and read when ORing)
+            const double in_b = 4.0 + (spatial ? 1.0 : 0.0);
+            rc = launch(h, s, F_MULTI_STATS, in_b * N, N * m.nw,
+                        [&] { return launch_multi(src, MOP_STATS, m, g.blocks(), s); });
+            if (!rc) rc = launch(h, s, F_FINALIZE, 0, 0,
+                                 [&] { return launch_multi_finalize(m, s); });
+            if (!rc) rc = launch(h, s, F_MULTI_CLIP, (in_b + 1.0 + m.or_mask) * N, N * m.nw,
+                                 [&] { return launch_multi(src, MOP_CLIP, m, g.blocks(), s); });
+            if (rc) return rc;
+            first = false;
+        }
+    }
+    return SOFIA_SC_OK;
+}
+
 // Noise values of a finished run in cube units, and its sigma_0 output.
 int read_run(sofia_sc *h, const DevState &hs, const RunSpec &r, double *noise,
              double *sigma0_out) {
@@ -948,6 +1056,31 @@ int read_run(sofia_sc *h, const DevState &hs, const RunSpec &r, double *noise,
     return SOFIA_SC_OK;
 }
 
+// The argument checks of a whole run (sofia_sc_run, _run_ex and
+// sofia_sc_check_run; per cube in a batch), before any device work. h may be
+// NULL (no error text). plans (optional) receives the kernels' plans.
+int validate_run(sofia_sc *h, int64_t nx, int64_t ny, int64_t nz, const sofia_sc_kernel *kernels,
+                 int32_t K, double t, int32_t mode, int32_t range, const sofia_sc_options *opt,
+                 std::vector<Plan> *plans) {
+    if (!kernels) return fail(h, SOFIA_SC_EINVAL, "NULL argument");
+    if (K < 1 || K > SOFIA_SC_MAX_KERNELS)
+        return fail(h, SOFIA_SC_EINVAL, "number of kernels must be 1..64");
+    int rc;
+    if ((rc = check_options(h, opt))) return rc;
+    if ((rc = check_dims(h, nx, ny, nz))) return rc;
+    if ((rc = check_modes(h, t, mode, range))) return rc;
+    std::vector<Plan> local((size_t)K);
+    for (int k = 0; k < K; ++k)
+        if ((rc = make_plan(h, kernels[k], &local[k]))) return rc;
+    if (opt->fuse_widths &&
+        !(opt->replacement < 0.0 && mode == SOFIA_SC_NOISE_STD &&
+          opt->storage == SOFIA_SC_STORE_F32))
+        return fail(h, SOFIA_SC_EINVAL,
+                    "fuse_widths needs replacement off, RMS noise and FP32 storage");
+    if (plans) *plans = std::move(local);
+    return SOFIA_SC_OK;
+}
+
 int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
              const sofia_sc_kernel *kernels, int32_t K, double t, int32_t mode,
              int32_t range, uint8_t *mask, double *noise, const sofia_sc_options *opt,
@@ -958,15 +1091,9 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
     if (sigma0_out) *sigma0_out = NAN;
     if (!cube || !kernels || !mask || !noise)
         return fail(h, SOFIA_SC_EINVAL, "NULL argument");
-    if (K < 1 || K > SOFIA_SC_MAX_KERNELS)
-        return fail(h, SOFIA_SC_EINVAL, "number of kernels must be 1..64");
     int rc;
-    if ((rc = check_options(h, opt))) return rc;
-    if ((rc = check_dims(h, nx, ny, nz))) return rc;
-    if ((rc = check_modes(h, t, mode, range))) return rc;
-    std::vector<Plan> plans((size_t)K);
-    for (int k = 0; k < K; ++k)
-        if ((rc = make_plan(h, kernels[k], &plans[k]))) return rc;
+    std::vector<Plan> plans;
+    if ((rc = validate_run(h, nx, ny, nz, kernels, K, t, mode, range, opt, &plans))) return rc;
     DeviceGuard dg(h->device);
     if (dg.err != hipSuccess) return hip_fail(h, dg.err, "hipSetDevice");
     hipStream_t s = (hipStream_t)opt->stream;
@@ -979,7 +1106,8 @@ int run_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t nz,
              (long long)nx, (long long)ny, (long long)nz, K, opt->storage, h->w.sh.col_blocks,
              h->w.sh.strip_rows);
     if ((rc = ensure_for(h, h->w, r))) return rc;
-    if ((rc = enqueue_run(h, s, h->w, r))) return rc;
+    if ((rc = (opt->fuse_widths ? enqueue_fused(h, s, h->w, r) : enqueue_run(h, s, h->w, r))))
+        return rc;
     if ((rc = finish(h, s, h->st_host, h->w.st))) return rc;
     return read_run(h, *h->st_host, r, noise, sigma0_out);
 }
@@ -1104,6 +1232,8 @@ int batch_impl(sofia_sc *h, const sofia_sc_cube *cubes, int32_t n,
         return fail(h, SOFIA_SC_EINVAL, "number of cubes must be 1..4096 and of kernels 1..64");
     int rc;
     if ((rc = check_options(h, opt))) return rc;
+    if (opt->fuse_widths)
+        return fail(h, SOFIA_SC_EINVAL, "fuse_widths is for sofia_sc_run / _run_ex only");
     if ((rc = check_modes(h, t, mode, range))) return rc;
     std::vector<Plan> plans((size_t)K);
     for (int k = 0; k < K; ++k)
@@ -1374,6 +1504,7 @@ int link_impl(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t 
                 if (!in) continue;
                 if (a.n_off == kLinkMaxOffsets)
                     return fail(h, SOFIA_SC_EINVAL, "linker radii give too many offsets");
+                a.delta[a.n_off] = (int32_t)(((int64_t)dz * ny + dy) * nx + dx);
                 a.off[a.n_off++] = (dx + 128) | ((dy + 128) << 8) | ((dz + 128) << 16);
             }
     DeviceGuard dg(h->device);
@@ -1607,6 +1738,8 @@ int noalloc_impl(sofia_sc *h, const float *cube, int64_t nx, int64_t ny, int64_t
         return fail(h, SOFIA_SC_EINVAL, "number of kernels must be 1..64");
     int rc;
     if ((rc = check_options(h, opt))) return rc;
+    if (opt->fuse_widths)
+        return fail(h, SOFIA_SC_EINVAL, "fuse_widths is for sofia_sc_run / _run_ex only");
     if ((rc = check_dims(h, nx, ny, nz))) return rc;
     if ((rc = check_modes(h, t, mode, range))) return rc;
     if (nx * ny * nz > SOFIA_SC_NOALLOC_MAX_VOXELS)
@@ -1718,7 +1851,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->bst_host) (void)hipHostFree(h->bst_host);
         if (h->nn_sigma) (void)hipFree(h->nn_sigma);
         void *lk[] = {h->lk_counts, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out,
-                      h->pm_acc, h->pm_sign, h->pm_vec, h->pm_state};
+                      h->pm_acc, h->pm_sign, h->pm_vec, h->pm_state, h->mu_sum, h->mu_cnt};
         for (void *p : lk)
             if (p) (void)hipFree(p);
         for (int l = 0; l < kBatchLanes; ++l) {
@@ -1910,6 +2043,8 @@ int sofia_sc_step_ex(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
         return fail(h, SOFIA_SC_EINVAL, "keep_input_mask must be 0 for a single step");
     if (opt->noise_plane_stride < 0 || opt->noise_plane_stride > (1 << 30))
         return fail(h, SOFIA_SC_EINVAL, "noise_plane_stride must be 0..2^30");
+    if (opt->fuse_widths)
+        return fail(h, SOFIA_SC_EINVAL, "fuse_widths is for sofia_sc_run / _run_ex only");
     return single_kernel(h, cube, nx, ny, nz, kernel, threshold, noise_mode, flux_range,
                          opt->replacement, opt->sigma0, mask_in, mask_out, noise, nullptr,
                          opt->storage, opt->stream, plane_stride(opt));
@@ -1939,6 +2074,13 @@ int sofia_sc_link(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int6
                   int64_t *boxes, int64_t box_capacity, void *stream) {
     return link_impl(h, mask, nx, ny, nz, radius_xy, radius_z, min_size_xy, min_size_z,
                      max_size_xy, max_size_z, labels, n_sources, boxes, box_capacity, stream);
+}
+
+int sofia_sc_check_run(int64_t nx, int64_t ny, int64_t nz, const sofia_sc_kernel *kernels,
+                       int32_t n_kernels, double threshold, int32_t noise_mode,
+                       int32_t flux_range, const sofia_sc_options *opt) {
+    return validate_run(nullptr, nx, ny, nz, kernels, n_kernels, threshold, noise_mode,
+                        flux_range, opt, nullptr);
 }
 
 void sofia_sc_param_defaults(sofia_sc_param_options *opt) {

@@ -150,6 +150,28 @@ struct StripArgs {
     const DevState *st;
 };
 
+// Arguments of the fused spectral-widths passes (sc_multi.hip): the widths
+// w[i] (half-widths h[i], kernel indices k[i]) that share one source: the raw
+// cube (SRC_X) or one spatial kernel's smoothed cube (SRC_P).
+constexpr int kMultiMax = 8;
+enum MultiOp { MOP_STATS = 0, MOP_CLIP = 1 };
+struct MultiArgs {
+    const float *src;
+    const uint8_t *wm;               // working mask (blank bits), SRC_P
+    uint8_t *mask;                   // caller's 0/1 mask (CLIP)
+    DevState *st;
+    double *part_sum;                // [nw][nparts]
+    unsigned long long *part_cnt;    // [nw][nparts]
+    int64_t ncol, nz;
+    int32_t ncb, zchunk, nparts;
+    int32_t nw, hmax, range, zstride, or_mask;
+    double t;
+    int32_t w[kMultiMax], h[kMultiMax], k[kMultiMax];
+};
+
+hipError_t launch_multi(int src, int mop, const MultiArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_multi_finalize(const MultiArgs &a, hipStream_t s);
+
 // Arguments of the sampled-Gaussian spatial kernel (sc_gauss.h): strips of
 // kGaussCols output columns, chunks of `rows` rows. tf / td hold the taps at
 // distance 0..R (the kernel is symmetric) in FP32 (x pass) and FP64 (y pass).
@@ -212,6 +234,7 @@ struct LinkArgs {
     int32_t min_xy, min_z, max_xy, max_z;
     int32_t n_off;
     int32_t off[kLinkMaxOffsets];
+    int32_t delta[kLinkMaxOffsets];   // index difference of each offset
 };
 
 hipError_t launch_link_init(const uint8_t *mask, int *L, int64_t n, hipStream_t s);

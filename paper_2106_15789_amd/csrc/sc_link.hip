@@ -110,19 +110,33 @@ __global__ __launch_bounds__(256) void k_link_init(const uint8_t *__restrict__ m
         L[i] = mask[i] ? (int)i : -1;
 }
 
+// Position of voxel i (the linker's cubes hold fewer than 2^31 voxels, so
+// 32-bit divisions suffice).
+__device__ __forceinline__ void pos_of(const LinkArgs &a, uint32_t i, int &x, int &y, int &z) {
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+    const uint32_t r = i / nx;
+    x = (int)(i - r * nx);
+    z = (int)(r / ny);
+    y = (int)(r - (uint32_t)z * ny);
+}
+
 __global__ __launch_bounds__(256) void k_link_union(LinkArgs a) {
-    const int64_t n = a.nx * a.ny * a.nz;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int n = (int)(a.nx * a.ny * a.nz);
+    const int stride = (int)(gridDim.x * blockDim.x);
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
         if (!a.mask[i]) continue;
-        const int64_t x = i % a.nx, y = (i / a.nx) % a.ny, z = i / (a.nx * a.ny);
+        int x, y, z;
+        pos_of(a, (uint32_t)i, x, y, z);
         for (int k = 0; k < a.n_off; ++k) {
             int dx, dy, dz;
             decode_off(a.off[k], dx, dy, dz);
-            const int64_t xx = x + dx, yy = y + dy, zz = z + dz;
+            const int xx = x + dx, yy = y + dy, zz = z + dz;
             if (xx < 0 || xx >= a.nx || yy < 0 || yy >= a.ny || zz < 0 || zz >= a.nz) continue;
-            const int64_t j = (zz * a.ny + yy) * a.nx + xx;
-            if (a.mask[j]) unite(a.L, (int)i, (int)j);
+            const int j = i + a.delta[k];
+            if (!a.mask[j]) continue;
+            // already in one tree when both link to the same voxel
+            if (ld_link(a.L, i) == ld_link(a.L, j)) continue;
+            unite(a.L, i, j);
         }
     }
 }
@@ -219,23 +233,57 @@ __global__ __launch_bounds__(256) void k_link_box_init(int *box, int64_t nc) {
     }
 }
 
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
 // Every detected voxel: its detection's number (from its root) and its share
-// of the detection's bounding box and voxel count.
+// of the detection's bounding box and voxel count. The lanes of a wave that
+// belong to one detection are reduced first, and one of them updates the
+// box: neighbouring voxels mostly share a detection. Waves step through the
+// cube together, so every lane takes part in the reductions.
 __global__ __launch_bounds__(256) void k_link_resolve(LinkArgs a) {
-    const int64_t n = a.nx * a.ny * a.nz;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int p = a.L[i];
-        if (p == -1) continue;
-        const int code = p >= 0 ? a.L[p] : p;   // a non-root points at its root
-        const int c = -2 - code;
-        if (p >= 0) a.L[i] = code;
-        const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / (a.nx * a.ny));
-        int *b = a.box + 8 * (int64_t)c;
-        atomicMin(b + 0, x); atomicMax(b + 1, x);
-        atomicMin(b + 2, y); atomicMax(b + 3, y);
-        atomicMin(b + 4, z); atomicMax(b + 5, z);
-        atomicAdd(b + 6, 1);
+    const int n = (int)(a.nx * a.ny * a.nz);
+    const int stride = (int)(gridDim.x * blockDim.x);
+    const int lane = threadIdx.x & 63;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    for (int ib = t - lane; ib < n; ib += stride) {
+        const int i = ib + lane;
+        int c = -1, x = 0, y = 0, z = 0;
+        if (i < n) {
+            const int p = a.L[i];
+            if (p != -1) {
+                const int code = p >= 0 ? a.L[p] : p;   // a non-root points at its root
+                c = -2 - code;
+                if (p >= 0) a.L[i] = code;
+                pos_of(a, (uint32_t)i, x, y, z);
+            }
+        }
+        unsigned long long pending = __ballot(c >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int cl = __shfl(c, leader);
+            const bool mine = c == cl;
+            const unsigned long long m = __ballot(mine);
+            const int x0 = wave_min_i(mine ? x : INT_MAX), x1 = wave_max_i(mine ? x : -1);
+            const int y0 = wave_min_i(mine ? y : INT_MAX), y1 = wave_max_i(mine ? y : -1);
+            const int z0 = wave_min_i(mine ? z : INT_MAX), z1 = wave_max_i(mine ? z : -1);
+            if (lane == leader) {
+                int *b = a.box + 8 * (int64_t)cl;
+                atomicMin(b + 0, x0); atomicMax(b + 1, x1);
+                atomicMin(b + 2, y0); atomicMax(b + 3, y1);
+                atomicMin(b + 4, z0); atomicMax(b + 5, z1);
+                atomicAdd(b + 6, __popcll(m));
+            }
+            pending &= ~m;
+        }
     }
 }
 

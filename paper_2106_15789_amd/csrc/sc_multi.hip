@@ -1,0 +1,214 @@
+// Replacement off: the kernel pairs of a run no longer depend on each other
+// (replacement of earlier detections, Sect. 6.2.4, is what chains them), so
+// the pairs that share a spatial kernel can share their passes. For one
+// spatial kernel (or none) and up to kMultiMax spectral widths:
+//  * k_multi<SRC, STATS>: one stream over the columns computes every width's
+//    smoothed value per voxel from one LDS ring of the last 2 hmax + 2 input
+//    planes (hmax = the largest half-width) and accumulates each width's sum
+//    of s^2 and count over the selected voxels (RMS noise about zero);
+//  * k_multi_finalize: sigma of every width from the per-block partials in a
+//    fixed order;
+//  * k_multi<SRC, CLIP>: the same stream, every voxel detected when any
+//    width's |s| exceeds t sigma of that width, written (or ORed) into the
+//    caller's mask.
+// Every width's running sum is an FP64 sum of the same float inputs as the
+// per-pair column pass, re-anchored from the ring every 32 planes; the
+// windows of all widths are centred on the same output plane.
+#include <math.h>
+
+#include "sc_device.h"
+
+namespace sc {
+
+template <int SRC, int MOP, int NW>
+__global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
+    extern __shared__ float mring[];
+    constexpr int B = kColThreads;
+    const int tid = threadIdx.x;
+    const int cb = (int)(blockIdx.x % (unsigned)a.ncb);
+    const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
+    const int64_t ncol = a.ncol;
+    const int64_t col0 = (int64_t)cb * B;
+    const bool active = col0 + tid < ncol;
+    const int nz = (int)a.nz;
+    const int z0 = zc * a.zchunk;
+    const int z1 = min(nz, z0 + a.zchunk);
+    constexpr int nw = NW;
+    const int hm = a.hmax, RW = 2 * a.hmax + 2;
+    const bool all_range = a.range == 0;
+    const double rsgn = (double)a.range;
+
+    double S[NW], inv_w[NW], T[NW], acc[NW];
+    unsigned cnt[NW];
+    int hw[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        S[i] = 0.0;
+        acc[i] = 0.0;
+        cnt[i] = 0u;
+        hw[i] = a.h[i];
+        inv_w[i] = 1.0 / (double)a.w[i];
+        T[i] = MOP == MOP_CLIP ? a.t * a.st->sigma[a.k[i]] : 0.0;
+    }
+    auto fin = [](float v) { return isfinite(v) ? v : 0.f; };
+    // ring slot of the plane d planes before the newest one (0 <= d < RW)
+    int si = RW - 1;     // slot of the newest plane
+    auto back = [&](int d) -> float & {
+        const int r = si - d;
+        return mring[(r < 0 ? r + RW : r) * B + tid];
+    };
+
+    // planes z0 - hm .. z1 + hm - 1 stream through; outputs z0 .. z1 - 1
+    const int zs = z0 - hm, ze = z1 + hm;
+    constexpr int G = 8;
+    float cur[G], nxt[G];
+    uint8_t bcur[G], bnxt[G];   // SRC_P: working-mask byte of the output plane
+    auto load_group = [&](int zb, float *v, uint8_t *bb) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int zi = zb + j;
+            v[j] = 0.f;
+            bb[j] = 0;
+            if (active && zi < ze && zi >= 0 && zi < nz)
+                v[j] = buf_f32(plane_rsrc(a.src + (int64_t)zi * ncol + col0), 4u * (uint32_t)tid, 0u);
+            if (SRC == SRC_P) {
+                const int zo = zi - hm;
+                if (active && zi < ze && zo >= z0)
+                    bb[j] = buf_u8(plane_rsrc(a.wm + (int64_t)zo * ncol + col0), (uint32_t)tid, 0u);
+            }
+        }
+    };
+    int steps = 0;
+    load_group(zs, cur, bcur);
+    for (int zb = zs; zb < ze; zb += G) {
+        if (zb + G < ze) load_group(zb + G, nxt, bnxt);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int zi = zb + j;
+            if (zi >= ze) break;
+            si = si + 1 == RW ? 0 : si + 1;
+            back(0) = cur[j];    // raw (SRC_X: NaN kept for the blank test)
+            // output plane zo = zi - hm is back(hm); plane zo + e is back(hm - e)
+            const int zo = zi - hm;
+            if (zo < z0) continue;
+            if (zo == z0 || (++steps & 31) == 0) {
+                // (re-)anchor every width's window sum directly from the ring
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    double s = 0.0;
+                    for (int d = hm - hw[i]; d <= hm + hw[i]; ++d) s += (double)fin(back(d));
+                    S[i] = s;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NW; ++i)
+                    S[i] += (double)fin(back(hm - hw[i])) - (double)fin(back(hm + hw[i] + 1));
+            }
+            // columns past the plane's end take no part
+            const bool blank = !active || (SRC == SRC_X ? !isfinite(back(hm))
+                                                      : (bcur[j] & kBlank) != 0);
+            const bool zsel = a.zstride <= 1 || zo % a.zstride == 0;
+            if (MOP == MOP_STATS) {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const double s = S[i] * inv_w[i];
+                    const bool sel = !blank & zsel & (all_range | (s * rsgn > 0.0));
+                    acc[i] += sel ? s * s : 0.0;
+                    cnt[i] += sel ? 1u : 0u;
+                }
+            } else {
+                bool det = false;
+#pragma unroll
+                for (int i = 0; i < NW; ++i)
+                    det |= !blank & (fabs(S[i] * inv_w[i]) > T[i]);
+                if (active) {
+                    const __amdgpu_buffer_rsrc_t mr = plane_rsrc(a.mask + (int64_t)zo * ncol + col0);
+                    uint8_t out = det ? 1 : 0;
+                    if (a.or_mask) out |= buf_u8(mr, (uint32_t)tid, 0u);
+                    buf_st_u8(out, mr, (uint32_t)tid, 0u);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) { cur[j] = nxt[j]; bcur[j] = bnxt[j]; }
+    }
+
+    if (MOP == MOP_STATS) {
+        // block reduction per width in a fixed order: deterministic partials
+        __shared__ double rs[B];
+        __shared__ unsigned long long rc[B];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            rs[tid] = acc[i];
+            rc[tid] = cnt[i];
+            __syncthreads();
+            for (int off = B / 2; off > 0; off >>= 1) {
+                if (tid < off) { rs[tid] += rs[tid + off]; rc[tid] += rc[tid + off]; }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                a.part_sum[(int64_t)i * a.nparts + blockIdx.x] = rs[0];
+                a.part_cnt[(int64_t)i * a.nparts + blockIdx.x] = rc[0];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// sigma of every width: RMS about zero of its selected voxels; none selected
+// -> NaN and the run's status flag.
+__global__ __launch_bounds__(256) void k_multi_finalize(MultiArgs a) {
+    __shared__ double ss[256];
+    __shared__ unsigned long long sc[256];
+    const int tid = threadIdx.x;
+    for (int i = 0; i < a.nw; ++i) {
+        double v = 0.0;
+        unsigned long long c = 0;
+        for (int p = tid; p < a.nparts; p += 256) {
+            v += a.part_sum[(int64_t)i * a.nparts + p];
+            c += a.part_cnt[(int64_t)i * a.nparts + p];
+        }
+        ss[tid] = v;
+        sc[tid] = c;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (tid < off) { ss[tid] += ss[tid + off]; sc[tid] += sc[tid + off]; }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double sig = NAN;
+            if (sc[0] > 0) sig = sqrt(ss[0] / (double)sc[0]);
+            else a.st->status |= 1;
+            a.st->sigma[a.k[i]] = sig;
+        }
+        __syncthreads();
+    }
+}
+
+template <int SRC, int MOP>
+hipError_t launch_multi_t(const MultiArgs &a, int nblocks, size_t lds, hipStream_t s) {
+    const dim3 grid((unsigned)nblocks), block(kColThreads);
+    switch (a.nw) {
+#define SC_M(N) case N: hipLaunchKernelGGL((k_multi<SRC, MOP, N>), grid, block, lds, s, a); break;
+        SC_M(1) SC_M(2) SC_M(3) SC_M(4) SC_M(5) SC_M(6) SC_M(7) SC_M(8)
+#undef SC_M
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_multi(int src, int mop, const MultiArgs &a, int nblocks, hipStream_t s) {
+    const size_t lds = (size_t)(2 * a.hmax + 2) * kColThreads * sizeof(float);
+    if (src == SRC_X)
+        return mop == MOP_STATS ? launch_multi_t<SRC_X, MOP_STATS>(a, nblocks, lds, s)
+                                : launch_multi_t<SRC_X, MOP_CLIP>(a, nblocks, lds, s);
+    return mop == MOP_STATS ? launch_multi_t<SRC_P, MOP_STATS>(a, nblocks, lds, s)
+                            : launch_multi_t<SRC_P, MOP_CLIP>(a, nblocks, lds, s);
+}
+
+hipError_t launch_multi_finalize(const MultiArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_finalize, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sc

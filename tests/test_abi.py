@@ -116,3 +116,39 @@ def test_param_layouts_and_defaults():
     n = ctypes.c_int64(5)
     assert lib.sofia_sc_parameterise(None, None, None, 1, 1, 1, 1, ctypes.byref(o), None,
                                      ctypes.byref(n), None) == sc.EINVAL
+
+
+def _check(nx, ny, nz, kernels=((0.0, 0),), t=3.0, mode=0, rng=0, **opt_fields):
+    """sofia_sc_check_run: the argument checks sofia_sc_run_ex runs before any
+    device work (the same code), with no handle, device or buffer."""
+    lib = sc.load()
+    opt = sc.Options()
+    lib.sofia_sc_default_options(ctypes.byref(opt))
+    for k, v in opt_fields.items():
+        setattr(opt, k, v)
+    return lib.sofia_sc_check_run(nx, ny, nz, sc._kernels(list(kernels)), len(kernels), t, mode,
+                                  rng, ctypes.byref(opt))
+
+
+def test_run_argument_checks_without_buffers():
+    assert _check(64, 64, 64) == sc.OK
+    assert _check(2048, 2048, 4096, [(9.0, 31), (14.0, 0, "gauss")]) == sc.OK
+    assert _check(1 << 14, 1 << 14, 1 << 12) == sc.OK              # 2^40 voxels
+    for dims in [(0, 4, 4), (4, 0, 4), (4, 4, 0), (-1, 4, 4),
+                 (16385, 16385, 1),                                # plane above 2^28
+                 (1 << 14, 1 << 14, 1 << 13)]:                     # 2^41 voxels
+        assert _check(*dims) == sc.EINVAL, dims
+    for kernels in [[(0.0, 4)], [(-1.0, 0)], [(40.0, 0)], [(0.0, 65)], [(float("nan"), 0)],
+                    [(3.0, 0, 2)], [(14.5, 0, "gauss")], []]:
+        assert _check(16, 16, 16, kernels or [(0.0, 0)] * 65) == sc.EINVAL, kernels
+    for t in (0.0, -1.0, float("nan"), float("inf")):
+        assert _check(16, 16, 16, t=t) == sc.EINVAL, t
+    assert _check(16, 16, 16, mode=2) == sc.EINVAL
+    assert _check(16, 16, 16, rng=3) == sc.EINVAL
+    for fields in [dict(struct_size=8), dict(keep_input_mask=2), dict(storage=7),
+                   dict(sigma0=-1.0), dict(noise_plane_stride=-1), dict(fuse_widths=2),
+                   dict(fuse_widths=1),                          # replacement on
+                   dict(fuse_widths=1, replacement=-1.0, storage=1)]:
+        assert _check(16, 16, 16, **fields) == sc.EINVAL, fields
+    assert _check(16, 16, 16, mode=1, fuse_widths=1, replacement=-1.0) == sc.EINVAL
+    assert _check(16, 16, 16, fuse_widths=1, replacement=-1.0) == sc.OK
