@@ -196,6 +196,33 @@ def cpu_baseline(workload, spec, n_kernels, planes, planes_1t):
     return out
 
 
+def extras_repl_off(h, x, m, wl, noise_mode, flux_range, name, stream, torch, out):
+    """Replacement off: the run one pair at a time and with fused widths."""
+    leg = {"kernels": wl.kernels, "noise": noise_mode, "flux_range": flux_range,
+           "replacement": None}
+    for fuse in (False, True):
+        def one():
+            return h.run(x, wl.kernels, wl.threshold, noise_mode, flux_range, -1.0, mask=m,
+                         stream=stream, fuse_widths=fuse)
+        one()
+        h.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            _, noise_f, _ = one()
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t0) / 5
+        h.profile(False)
+        st = h.profile_read()
+        key = "fused" if fuse else "per_pair"
+        leg[key] = {"ms": tf * 1e3, "value": x.numel() / tf, "unit": "voxels/s",
+                    "family_ms_per_run": {s["name"]: s["total_ms"] / 5 for s in st},
+                    "kernel_gbs": family_gbs(st),
+                    "noise": [float(v) for v in noise_f]}
+        say(f"1024^3 replacement off, {noise_mode}, {key}: {tf * 1e3:.1f} ms")
+    out[name] = leg
+
+
 def extras(sc, torch, synth, stream, large_x=None, large_wl=None):
     """Secondary figures measured in the same process."""
     out = {}
@@ -240,31 +267,12 @@ def extras(sc, torch, synth, stream, large_x=None, large_wl=None):
             "family_ms": {s["name"]: s["total_ms"] / s["launches"] for s in stats},
             "noise": [float(v) for v in noise]}
         say(f"1024^3 f32, sampled Gaussian: {dt * 100:.1f} ms/step")
-        # replacement off, RMS noise: one pair at a time, and with the pairs
-        # that share a spatial kernel fused into shared passes
-        leg = {"kernels": wl.kernels, "noise": "std", "flux_range": "all",
-               "replacement": None}
-        for fuse in (False, True):
-            def one():
-                return h.run(x, wl.kernels, wl.threshold, "std", "all", -1.0, mask=m,
-                             stream=stream, fuse_widths=fuse)
-            one()
-            h.profile(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(5):
-                _, noise_f, _ = one()
-            torch.cuda.synchronize()
-            tf = (time.perf_counter() - t0) / 5
-            h.profile(False)
-            st = h.profile_read()
-            key = "fused" if fuse else "per_pair"
-            leg[key] = {"ms": tf * 1e3, "value": x.numel() / tf, "unit": "voxels/s",
-                        "family_ms_per_run": {s["name"]: s["total_ms"] / 5 for s in st},
-                        "kernel_gbs": family_gbs(st),
-                        "noise": [float(v) for v in noise_f]}
-            say(f"1024^3 replacement off, std, {key}: {tf * 1e3:.1f} ms")
-        out["plain_1024cube_repl_off_std"] = leg
+        # replacement off: one pair at a time, and with the pairs that share a
+        # spatial kernel fused into shared passes; RMS noise over all voxels,
+        # and the workload's own MAD over the negative voxels
+        for nm, rg, name in (("std", "all", "plain_1024cube_repl_off_std"),
+                             (wl.noise_mode, wl.flux_range, "plain_1024cube_repl_off")):
+            extras_repl_off(h, x, m, wl, nm, rg, name, stream, torch, out)
         h.run(x, wl.kernels, wl.threshold, wl.noise_mode, wl.flux_range, wl.replacement,
               mask=m, stream=stream)
         y = torch.empty_like(x)

@@ -106,12 +106,15 @@ typedef struct {
                                pairs are independent; the pairs that share a
                                spatial kernel then share their passes: one
                                pass computes every spectral width's smoothed
-                               values and RMS partials, one finaliser, one
+                               values and its RMS partials (or, for MAD, its
+                               counts and captured keys around its predicted
+                               median), then every width's noise, then one
                                pass clips every width (ORed into the mask).
-                               Same results as 0 up to the summation order of
-                               the noise. Needs RMS noise and FP32 storage
-                               (sofia_sc_run / _run_ex only; EINVAL
-                               otherwise). 0 (default): one pair at a time */
+                               Same results as 0 up to the last bits of the
+                               smoothed values and the summation order of the
+                               RMS. Needs FP32 storage (sofia_sc_run / _run_ex
+                               only; EINVAL otherwise). 0 (default): one pair
+                               at a time */
     void *stream;           /* hipStream_t to run on; NULL = null stream */
 } sofia_sc_options;
 

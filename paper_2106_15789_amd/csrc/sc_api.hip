@@ -25,7 +25,7 @@ enum Family {
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
     F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
     F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_PARAM, F_RELIABILITY, F_SPATIAL_GAUSS,
-    F_MULTI_STATS, F_MULTI_CLIP, F_COUNT
+    F_MULTI_STATS, F_MULTI_CLIP, F_MULTI_SELECT, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
     "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
@@ -33,7 +33,7 @@ const char *kFamilyName[F_COUNT] = {
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
     "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide",
     "link_union", "link_number", "link_label", "parameterise", "reliability",
-    "spatial_gauss", "fused_stats", "fused_clip"};
+    "spatial_gauss", "fused_stats", "fused_clip", "fused_select"};
 
 struct LaunchRec {
     int fam;
@@ -181,6 +181,16 @@ struct sofia_sc {
     size_t mu_sum_cap = 0;
     unsigned long long *mu_cnt = nullptr;
     size_t mu_cnt_cap = 0;
+    // fused MAD: per-width states, histograms (+ capture counts), capture
+    // lists and selection counts
+    DevState *mu_st = nullptr;
+    size_t mu_st_cap = 0;
+    unsigned long long *mu_hist = nullptr;
+    size_t mu_hist_cap = 0;
+    uint32_t *mu_cap = nullptr;
+    size_t mu_cap_cap = 0;
+    unsigned long long *mu_sel = nullptr;
+    size_t mu_sel_cap = 0;
 };
 
 namespace {
@@ -954,6 +964,135 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     return SOFIA_SC_OK;
 }
 
+// MAD noise of the widths of one fused chunk: per width its own state,
+// histograms and capture list; the sample passes and the exact selection
+// from the captured keys (or the full histogram passes when the capture
+// misses) as for one pair, but one shared selection pass for every width.
+int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
+                    const ColGrid &g, MultiArgs &m, bool spatial, double in_b) {
+    int rc;
+    const Dims &d = r.d;
+    const double N = (double)d.N;
+    const size_t capcap = capture_capacity(d.N);
+    const size_t nparts = (size_t)g.blocks();
+    if ((rc = grow(h, h->mu_st, h->mu_st_cap, (size_t)kMultiMax, "fused states", nullptr)) ||
+        (rc = grow(h, h->mu_hist, h->mu_hist_cap, kHistWords * kMultiMax, "fused histograms",
+                   nullptr)) ||
+        (rc = grow(h, h->mu_cap, h->mu_cap_cap, capcap * kMultiMax, "fused capture lists",
+                   nullptr)) ||
+        (rc = grow(h, h->mu_sel, h->mu_sel_cap, 2 * nparts * kMultiMax, "fused counts",
+                   nullptr)))
+        return rc;
+    const int src = spatial ? SRC_P : SRC_X;
+    const uint8_t *wm = w.wm[0];   // the column passes' instantiations take a working mask
+    const int wb2 = (int)std::min<int64_t>(1024, std::max<int64_t>(8, d.N >> 18));
+    const int wb1 = std::min(512, wb2);
+    m.cap_capacity = (unsigned long long)capcap;
+    auto hist_of = [&](int i) { return h->mu_hist + (size_t)i * kHistWords; };
+    // ColArgs of width i (sample pass and the full histogram passes)
+    auto col_args = [&](int i) {
+        ColArgs c{};
+        c.x = r.cube;
+        c.p = w.p;
+        c.xtype = ST_F32;
+        c.wm_in = wm;
+        c.ncol = d.ncol;
+        c.nz = d.nz;
+        c.w = m.w[i];
+        c.h = m.h[i];
+        c.zchunk = g.zchunk;
+        c.ncb = g.ncb;
+        c.range = r.range;
+        c.st = m.sti[i];
+        c.hist1 = hist_of(i);
+        c.hist2 = hist_of(i) + kOffL2;
+        c.hist2c = hist_of(i) + kOffL2c;
+        c.cb_stride = 1;
+        c.zstride = r.zstride;
+        return c;
+    };
+    for (int i = 0; i < m.nw; ++i) {
+        m.sti[i] = h->mu_st + i;
+        m.cap[i] = h->mu_cap + (size_t)i * capcap;
+        m.cap_count[i] = hist_of(i) + kOffCapCount;
+        m.sel_part[i] = h->mu_sel + (size_t)i * 2 * nparts;
+        DevState *sti = m.sti[i];
+        unsigned long long *hi = hist_of(i);
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_set_sigma0(sti, NAN, s); });
+        if (!rc) rc = launch(h, s, F_FILL, 8.0 * kHistWords, 0, [&] {
+            return launch_fill_u64(hi, (int64_t)kHistWords, s);
+        });
+        if (rc) return rc;
+        // the sample pass of width i, as for one pair
+        ColArgs cs = col_args(i);
+        const int64_t nseg = (d.ncol + 63) / 64;
+        const int64_t stride =
+            nseg >= (int64_t)kSampleStride * 512 ? (nseg / 512) | 1 : kSampleStride;
+        cs.cb_stride = (int)stride;
+        const int64_t sampled = (nseg + stride - 1) / stride;
+        cs.ncb = (int)((sampled + kColThreads / 64 - 1) / (kColThreads / 64));
+        cs.hist1 = hi + kOffSample;
+        int nzc = (int)std::min<int64_t>((2048 + cs.ncb - 1) / cs.ncb,
+                                         std::max<int64_t>(1, d.nz / 32));
+        nzc = std::max(nzc, 1);
+        cs.zchunk = (int)((d.nz + nzc - 1) / nzc);
+        nzc = (int)((d.nz + cs.zchunk - 1) / cs.zchunk);
+        const int nb = cs.ncb * nzc;
+        const double frac = (double)sampled / (double)nseg;
+        const bool spec = m.w[i] >= 3;
+        rc = launch(h, s, F_COL_SAMPLE, in_b * N * frac, N * frac, [&] {
+            return launch_column(src, OP_HIST1, spec, wm != nullptr, cs, nb, s);
+        });
+        if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
+            return launch_finalize_predict(sti, hi + kOffSample, r.t, s);
+        });
+        if (rc) return rc;
+    }
+    // one selection pass for every width
+    rc = launch(h, s, F_MULTI_SELECT, in_b * N, N * m.nw,
+                [&] { return launch_multi(src, MOP_SELECT, m, g.blocks(), s); });
+    if (rc) return rc;
+    for (int i = 0; i < m.nw; ++i) {
+        DevState *sti = m.sti[i];
+        unsigned long long *hi = hist_of(i);
+        const int k = m.k[i];
+        const bool spec = m.w[i] >= 3;
+        ColArgs c = col_args(i);
+        rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
+            return launch_finalize_select(sti, m.sel_part[i], (int)nparts, m.cap_count[i],
+                                          (unsigned long long)capcap, k, nullptr, 0ull, s);
+        });
+        if (!rc) rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
+            return launch_capture_l1(sti, m.cap[i], m.cap_count[i], hi, wb1, s);
+        });
+        if (rc) return rc;
+        c.skip_if_captured = 1;
+        rc = launch(h, s, F_COL_HIST1, in_b * N, N, [&] {
+            return launch_column(src, OP_HIST1, spec, wm != nullptr, c, g.blocks(), s);
+        }, k);
+        if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
+            return launch_finalize_mad1(sti, hi, s);
+        });
+        if (!rc) rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
+            return launch_capture_coarse(sti, m.cap[i], m.cap_count[i], hi + kOffL2c, wb2, s);
+        });
+        if (!rc) rc = launch(h, s, F_COL_HIST2, in_b * N, N, [&] {
+            return launch_column(src, OP_HIST2, spec, wm != nullptr, c, g.blocks(), s);
+        }, k);
+        if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Coarse, 0, [&] {
+            return launch_finalize_mad2a(sti, hi + kOffL2c, s);
+        });
+        if (!rc) rc = launch(h, s, F_CAPTURE_SELECT, 0, 0, [&] {
+            return launch_capture_fine(sti, m.cap[i], m.cap_count[i], hi + kOffL2, wb2, s);
+        });
+        if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Fine, 0, [&] {
+            return launch_finalize_mad2b(sti, hi + kOffL2, k, r.t, 0, s);
+        });
+        if (rc) return rc;
+    }
+    return launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_multi_gather(m, s); });
+}
+
 // Replacement off: the kernel pairs are independent, and the pairs that
 // share a spatial kernel share their passes. Per spatial kernel (in order of
 // first appearance) and up to kMultiMax of its spectral widths: the spatial
@@ -966,7 +1105,9 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     const bool any_spatial = r.any_spatial();
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_set_sigma0(w.st, NAN, s); });
     if (rc) return rc;
-    if (any_spatial) {
+    // the blank bits: read by the passes over a spatially smoothed cube, and
+    // by the per-pair column passes of the MAD noise
+    if (any_spatial || r.mode != SOFIA_SC_NOISE_STD) {
         rc = launch(h, s, F_INIT, 5.0 * N, N, [&] {
             return launch_init_mask(r.cube, nullptr, w.wm[0], d.N, s);
         });
@@ -1030,10 +1171,14 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
             // algorithmic bytes: the source once (+ the blank bits) per pass;
             // the clip's mask write (and read when ORing)
             const double in_b = 4.0 + (spatial ? 1.0 : 0.0);
-            rc = launch(h, s, F_MULTI_STATS, in_b * N, N * m.nw,
-                        [&] { return launch_multi(src, MOP_STATS, m, g.blocks(), s); });
-            if (!rc) rc = launch(h, s, F_FINALIZE, 0, 0,
-                                 [&] { return launch_multi_finalize(m, s); });
+            if (r.mode == SOFIA_SC_NOISE_STD) {
+                rc = launch(h, s, F_MULTI_STATS, in_b * N, N * m.nw,
+                            [&] { return launch_multi(src, MOP_STATS, m, g.blocks(), s); });
+                if (!rc) rc = launch(h, s, F_FINALIZE, 0, 0,
+                                     [&] { return launch_multi_finalize(m, s); });
+            } else {
+                rc = fused_mad_noise(h, s, w, r, g, m, spatial, in_b);
+            }
             if (!rc) rc = launch(h, s, F_MULTI_CLIP, (in_b + 1.0 + m.or_mask) * N, N * m.nw,
                                  [&] { return launch_multi(src, MOP_CLIP, m, g.blocks(), s); });
             if (rc) return rc;
@@ -1072,11 +1217,8 @@ int validate_run(sofia_sc *h, int64_t nx, int64_t ny, int64_t nz, const sofia_sc
     std::vector<Plan> local((size_t)K);
     for (int k = 0; k < K; ++k)
         if ((rc = make_plan(h, kernels[k], &local[k]))) return rc;
-    if (opt->fuse_widths &&
-        !(opt->replacement < 0.0 && mode == SOFIA_SC_NOISE_STD &&
-          opt->storage == SOFIA_SC_STORE_F32))
-        return fail(h, SOFIA_SC_EINVAL,
-                    "fuse_widths needs replacement off, RMS noise and FP32 storage");
+    if (opt->fuse_widths && !(opt->replacement < 0.0 && opt->storage == SOFIA_SC_STORE_F32))
+        return fail(h, SOFIA_SC_EINVAL, "fuse_widths needs replacement off and FP32 storage");
     if (plans) *plans = std::move(local);
     return SOFIA_SC_OK;
 }
@@ -1851,7 +1993,8 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->bst_host) (void)hipHostFree(h->bst_host);
         if (h->nn_sigma) (void)hipFree(h->nn_sigma);
         void *lk[] = {h->lk_counts, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out,
-                      h->pm_acc, h->pm_sign, h->pm_vec, h->pm_state, h->mu_sum, h->mu_cnt};
+                      h->pm_acc, h->pm_sign, h->pm_vec, h->pm_state, h->mu_sum, h->mu_cnt,
+                      h->mu_st, h->mu_hist, h->mu_cap, h->mu_sel};
         for (void *p : lk)
             if (p) (void)hipFree(p);
         for (int l = 0; l < kBatchLanes; ++l) {

@@ -154,7 +154,8 @@ struct StripArgs {
 // w[i] (half-widths h[i], kernel indices k[i]) that share one source: the raw
 // cube (SRC_X) or one spatial kernel's smoothed cube (SRC_P).
 constexpr int kMultiMax = 8;
-enum MultiOp { MOP_STATS = 0, MOP_CLIP = 1 };
+constexpr int kMultiStage = 256;     // captured keys staged per wave and width (MAD)
+enum MultiOp { MOP_STATS = 0, MOP_CLIP = 1, MOP_SELECT = 2 };
 struct MultiArgs {
     const float *src;
     const uint8_t *wm;               // working mask (blank bits), SRC_P
@@ -167,10 +168,19 @@ struct MultiArgs {
     int32_t nw, hmax, range, zstride, or_mask;
     double t;
     int32_t w[kMultiMax], h[kMultiMax], k[kMultiMax];
+    // MOP_SELECT (MAD): every width's own state (its predicted key window),
+    // capture list and count, and per-block counts [nparts][2]
+    DevState *sti[kMultiMax];
+    uint32_t *cap[kMultiMax];
+    unsigned long long *cap_count[kMultiMax];
+    unsigned long long cap_capacity;
+    unsigned long long *sel_part[kMultiMax];
 };
 
 hipError_t launch_multi(int src, int mop, const MultiArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_multi_finalize(const MultiArgs &a, hipStream_t s);
+// Every width's noise (and status, fallback bits) from its own state into st.
+hipError_t launch_multi_gather(const MultiArgs &a, hipStream_t s);
 
 // Arguments of the sampled-Gaussian spatial kernel (sc_gauss.h): strips of
 // kGaussCols output columns, chunks of `rows` rows. tf / td hold the taps at

@@ -41,6 +41,12 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
     double S[NW], inv_w[NW], T[NW], acc[NW];
     unsigned cnt[NW];
     int hw[NW];
+    // MOP_SELECT: key windows, counts, and per-wave staging of captured keys
+    uint32_t klo[NW], khi[NW];
+    unsigned nbelow[NW];
+    int fill[NW];
+    uint32_t *stagew = reinterpret_cast<uint32_t *>(mring + (size_t)RW * B) +
+                       (size_t)(tid >> 6) * NW * kMultiStage;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         S[i] = 0.0;
@@ -49,7 +55,28 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
         hw[i] = a.h[i];
         inv_w[i] = 1.0 / (double)a.w[i];
         T[i] = MOP == MOP_CLIP ? a.t * a.st->sigma[a.k[i]] : 0.0;
+        klo[i] = MOP == MOP_SELECT ? a.sti[i]->klo : 1u;
+        khi[i] = MOP == MOP_SELECT ? a.sti[i]->khi : 0u;
+        nbelow[i] = 0u;
+        fill[i] = 0;
     }
+    const int wlane = tid & 63;
+    // this wave's staged keys of width i go to the width's capture list (one
+    // atomic per flush; entries past the capacity are dropped, the count
+    // still grows and sends the width to the full histogram passes)
+    auto flush = [&](int i) {
+        __builtin_amdgcn_wave_barrier();
+        unsigned long long base = 0;
+        if (wlane == 0) base = atomicAdd(a.cap_count[i], (unsigned long long)fill[i]);
+        const uint32_t lo32 = __shfl((uint32_t)base, 0);
+        const uint32_t hi32 = __shfl((uint32_t)(base >> 32), 0);
+        base = ((unsigned long long)hi32 << 32) | lo32;
+        const uint32_t *sw = stagew + (size_t)i * kMultiStage;
+        for (int e = wlane; e < fill[i]; e += 64)
+            if (base + e < a.cap_capacity) a.cap[i][base + e] = sw[e];
+        __builtin_amdgcn_wave_barrier();
+        fill[i] = 0;
+    };
     auto fin = [](float v) { return isfinite(v) ? v : 0.f; };
     // ring slot of the plane d planes before the newest one (0 <= d < RW)
     int si = RW - 1;     // slot of the newest plane
@@ -116,6 +143,27 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
                     acc[i] += sel ? s * s : 0.0;
                     cnt[i] += sel ? 1u : 0u;
                 }
+            } else if (MOP == MOP_SELECT) {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const double s = S[i] * inv_w[i];
+                    const bool sel = !blank & zsel & (all_range | (s * rsgn > 0.0));
+                    const uint32_t key = __float_as_uint(fabsf((float)s));
+                    cnt[i] += sel ? 1u : 0u;
+                    nbelow[i] += (sel & (key < klo[i])) ? 1u : 0u;
+                    const bool want = sel & (key >= klo[i]) & (key <= khi[i]);
+                    const unsigned long long bal = __ballot(want);
+                    if (bal) {
+                        if (want) {
+                            const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(bal >> 32),
+                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                            stagew[(size_t)i * kMultiStage + fill[i] + below] = key;
+                        }
+                        fill[i] += __popcll(bal);
+                        if (fill[i] > kMultiStage - 64) flush(i);
+                    }
+                }
             } else {
                 bool det = false;
 #pragma unroll
@@ -131,6 +179,32 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) { cur[j] = nxt[j]; bcur[j] = bnxt[j]; }
+    }
+
+    if (MOP == MOP_SELECT) {
+#pragma unroll
+        for (int i = 0; i < NW; ++i)
+            if (fill[i]) flush(i);
+        // per-block counts of every width: selected voxels, keys below the window
+        __shared__ unsigned long long rc2[2][B];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            rc2[0][tid] = cnt[i];
+            rc2[1][tid] = nbelow[i];
+            __syncthreads();
+            for (int off = B / 2; off > 0; off >>= 1) {
+                if (tid < off) {
+                    rc2[0][tid] += rc2[0][tid + off];
+                    rc2[1][tid] += rc2[1][tid + off];
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                a.sel_part[i][2 * blockIdx.x] = rc2[0][0];
+                a.sel_part[i][2 * blockIdx.x + 1] = rc2[1][0];
+            }
+            __syncthreads();
+        }
     }
 
     if (MOP == MOP_STATS) {
@@ -198,12 +272,33 @@ hipError_t launch_multi_t(const MultiArgs &a, int nblocks, size_t lds, hipStream
 }
 
 hipError_t launch_multi(int src, int mop, const MultiArgs &a, int nblocks, hipStream_t s) {
-    const size_t lds = (size_t)(2 * a.hmax + 2) * kColThreads * sizeof(float);
-    if (src == SRC_X)
-        return mop == MOP_STATS ? launch_multi_t<SRC_X, MOP_STATS>(a, nblocks, lds, s)
-                                : launch_multi_t<SRC_X, MOP_CLIP>(a, nblocks, lds, s);
-    return mop == MOP_STATS ? launch_multi_t<SRC_P, MOP_STATS>(a, nblocks, lds, s)
-                            : launch_multi_t<SRC_P, MOP_CLIP>(a, nblocks, lds, s);
+    size_t lds = (size_t)(2 * a.hmax + 2) * kColThreads * sizeof(float);
+    if (mop == MOP_SELECT)
+        lds += (size_t)(kColThreads / 64) * a.nw * kMultiStage * sizeof(uint32_t);
+    if (src == SRC_X) {
+        if (mop == MOP_STATS) return launch_multi_t<SRC_X, MOP_STATS>(a, nblocks, lds, s);
+        if (mop == MOP_SELECT) return launch_multi_t<SRC_X, MOP_SELECT>(a, nblocks, lds, s);
+        return launch_multi_t<SRC_X, MOP_CLIP>(a, nblocks, lds, s);
+    }
+    if (mop == MOP_STATS) return launch_multi_t<SRC_P, MOP_STATS>(a, nblocks, lds, s);
+    if (mop == MOP_SELECT) return launch_multi_t<SRC_P, MOP_SELECT>(a, nblocks, lds, s);
+    return launch_multi_t<SRC_P, MOP_CLIP>(a, nblocks, lds, s);
+}
+
+__global__ void k_multi_gather(MultiArgs a) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < a.nw; ++i) {
+        const DevState *si = a.sti[i];
+        a.st->sigma[a.k[i]] = si->sigma[a.k[i]];
+        a.st->status |= si->status;
+        a.st->fallback |= si->fallback;
+        a.st->clip_fallback |= si->clip_fallback;
+    }
+}
+
+hipError_t launch_multi_gather(const MultiArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_gather, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_multi_finalize(const MultiArgs &a, hipStream_t s) {

@@ -150,5 +150,5 @@ def test_run_argument_checks_without_buffers():
                    dict(fuse_widths=1),                          # replacement on
                    dict(fuse_widths=1, replacement=-1.0, storage=1)]:
         assert _check(16, 16, 16, **fields) == sc.EINVAL, fields
-    assert _check(16, 16, 16, mode=1, fuse_widths=1, replacement=-1.0) == sc.EINVAL
+    assert _check(16, 16, 16, mode=1, fuse_widths=1, replacement=-1.0) == sc.OK
     assert _check(16, 16, 16, fuse_widths=1, replacement=-1.0) == sc.OK

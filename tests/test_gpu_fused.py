@@ -43,9 +43,9 @@ def cube(nx, ny, nz, seed, n_gal=6, border=3):
 KERNELS_12 = [(float(f), w) for f in (0, 3, 6) for w in (0, 3, 7, 15)]
 
 
-def against_oracle(h, x, kernels, t, rng_, what, **kw):
-    ref = oracle.run(x, [(k[0], k[1], sc_kind(k)) for k in kernels], t, "std", rng_, -1.0)
-    m, noise, s0 = h.run(dev(x), kernels, t, "std", rng_, -1.0, fuse_widths=True, **kw)
+def against_oracle(h, x, kernels, t, rng_, what, mode="std", **kw):
+    ref = oracle.run(x, [(k[0], k[1], sc_kind(k)) for k in kernels], t, mode, rng_, -1.0)
+    m, noise, s0 = h.run(dev(x), kernels, t, mode, rng_, -1.0, fuse_widths=True, **kw)
     g = m.cpu().numpy()
     rel = np.abs(noise / ref.sigma - 1)
     diff = g != ref.mask
@@ -105,9 +105,70 @@ def test_fused_keep_input_mask_and_subsampling(h):
         assert abs(n2[k] / st.sigma - 1) <= SIGMA_RTOL, k
 
 
+@pytest.mark.parametrize("rng_", ["negative", "all"])
+def test_fused_mad_matches_oracle_12_pairs(h, rng_):
+    """MAD: per width its own sample, prediction and exact selection from the
+    keys one shared selection pass captured."""
+    x = cube(200, 170, 120, seed=55)
+    h.profile(True)
+    against_oracle(h, x, KERNELS_12, 3.5, rng_, f"fused MAD 12 pairs {rng_}", mode="mad")
+    h.profile(False)
+    fam = {s["name"]: s for s in h.profile_read()}
+    assert "fused_select" in fam and "column_hist2" not in fam, sorted(fam)
+
+
+def test_fused_mad_mixed_kinds_and_many_widths(h):
+    x = cube(150, 130, 140, seed=56)
+    kernels = [(3.0, 7), (0.0, 0), (6.0, 3, "gauss")] + \
+              [(0.0, w) for w in (3, 5, 7, 9, 11, 13, 15, 17, 21)] + [(3.0, 0)]
+    against_oracle(h, x, kernels, 3.5, "negative", "fused MAD mixed", mode="mad")
+
+
+def test_fused_mad_equals_per_pair_path(h):
+    x = cube(180, 160, 100, seed=57)
+    xd = dev(x)
+    m0, n0, _ = h.run(xd, KERNELS_12, 3.5, "mad", "negative", -1.0)
+    m1, n1, _ = h.run(xd, KERNELS_12, 3.5, "mad", "negative", -1.0, fuse_widths=True)
+    rel = np.abs(n1 / n0 - 1)
+    diff = int((m0 != m1).sum().item())
+    say(f"fused MAD vs per pair: noise max rel {rel.max():.2e}, mask diff {diff}")
+    assert rel.max() <= SIGMA_RTOL
+    assert diff <= 4
+
+
+def test_fused_mad_falls_back_when_sample_is_unrepresentative(h):
+    """Rows read by the sampling passes scaled 100x: every width's predicted
+    window misses and its full histogram passes run, still exact."""
+    nx, ny, nz = 256, 120, 90
+    rng = np.random.default_rng(58)
+    x = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    x[:, ::17, :] *= 100.0
+    kernels = [(0.0, 0), (0.0, 3), (0.0, 7), (3.0, 0)]
+    h.profile(True)
+    against_oracle(h, x, kernels, 3.5, "negative", "fused MAD fallback", mode="mad")
+    h.profile(False)
+    fam = {s["name"]: s for s in h.profile_read()}
+    assert fam.get("column_hist2", {}).get("launches", 0) >= 1, sorted(fam)
+
+
+def test_fused_mad_capture_overflow(h):
+    """Most voxels share one value: the captured keys exceed a width's list
+    and its full level-2 pass takes over."""
+    rng = np.random.default_rng(59)
+    x = np.full((128, 256, 256), -1.0, np.float32)
+    noisy = rng.random(x.shape) < 0.1
+    x[noisy] = rng.standard_normal(int(noisy.sum())).astype(np.float32)
+    h.profile(True)
+    against_oracle(h, x, [(0.0, 0), (0.0, 3)], 3.5, "negative", "fused MAD overflow",
+                   mode="mad")
+    h.profile(False)
+    fam = {s["name"]: s for s in h.profile_read()}
+    assert fam.get("column_hist2", {}).get("launches", 0) >= 1, sorted(fam)
+
+
 def test_fused_rejects_what_it_does_not_cover(h):
     xd = dev(np.random.default_rng(1).normal(size=(8, 16, 16)).astype(np.float32))
-    for kw in [dict(noise_mode="mad"), dict(replacement=2.0), dict(storage="f16")]:
+    for kw in [dict(replacement=2.0), dict(storage="f16")]:
         args = dict(noise_mode="std", replacement=-1.0)
         args.update(kw)
         with pytest.raises(sc.ScError) as e:
