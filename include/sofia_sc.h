@@ -123,8 +123,9 @@ typedef struct {
 void sofia_sc_default_options(sofia_sc_options *opt);
 
 /* Create a handle on a HIP device. The handle owns all device workspace
- * (working masks, smoothed-plane buffer, histograms); workspace grows on
- * demand and is released by sofia_sc_destroy. EINVAL for a bad ordinal. */
+ * (packed blank and detection bits, smoothed-plane buffer, histograms);
+ * workspace grows on demand and is released by sofia_sc_destroy. EINVAL for
+ * a bad ordinal. */
 int sofia_sc_create(sofia_sc **out, int device_ordinal);
 
 /* Release a handle and its workspace. NULL is a no-op. */

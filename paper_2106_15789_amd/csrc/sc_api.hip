@@ -23,15 +23,15 @@ namespace {
 enum Family {
     F_INIT = 0, F_FILL, F_SPATIAL, F_COL_STD, F_COL_SAMPLE, F_COL_SELECT, F_COL_HIST1,
     F_COL_HIST2, F_FALLBACK_SKIPPED, F_CAPTURE_SELECT, F_COL_CLIP, F_COL_WRITE, F_FINALIZE,
-    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OR, F_NORM_NOISE, F_NORM_DIVIDE,
+    F_QUANTIZE, F_COL_SELCLIP, F_CLIP_FIXUP, F_BATCH, F_MASK_OUT, F_NORM_NOISE, F_NORM_DIVIDE,
     F_LINK_UNION, F_LINK_NUMBER, F_LINK_LABEL, F_PARAM, F_RELIABILITY, F_SPATIAL_GAUSS,
     F_MULTI_STATS, F_MULTI_CLIP, F_MULTI_SELECT, F_COUNT
 };
 const char *kFamilyName[F_COUNT] = {
-    "init_mask", "fill", "spatial_cascade", "column_std", "column_sample",
+    "init_bits", "fill", "spatial_cascade", "column_std", "column_sample",
     "column_select", "column_hist1", "column_hist2", "fallback_skipped", "capture_select",
     "column_clip", "column_write", "finalize", "quantize", "column_select_clip",
-    "clip_fixup", "batch_graph", "mask_or", "norm_window_noise", "norm_divide",
+    "clip_fixup", "batch_graph", "mask_out", "norm_window_noise", "norm_divide",
     "link_union", "link_number", "link_label", "parameterise", "reliability",
     "spatial_gauss", "fused_stats", "fused_clip", "fused_select"};
 
@@ -56,14 +56,16 @@ struct Plan {
     bool identity() const { return !spatial() && !spectral(); }
 };
 
-// Device workspace of one S+C run at a time: working masks, the smoothed
-// plane buffer, histograms, partials, the capture and undecided-voxel lists,
-// the 16-bit cube and the packed detection bits. Grown on demand, never
-// shrunk. `st` is the run's device state; a batch points it at the state of
-// the cube being enqueued.
+// Device workspace of one S+C run at a time: the packed blank and detection
+// bits, the smoothed plane buffer, histograms, partials, the capture and
+// undecided-voxel lists and the 16-bit cube. Grown on demand, never shrunk.
+// `st` is the run's device state; a batch points it at the state of the cube
+// being enqueued.
 struct Work {
-    uint8_t *wm[2] = {nullptr, nullptr};
-    size_t wm_cap = 0;
+    uint64_t *blank = nullptr;       // blank bits (non-finite voxels)
+    uint64_t *det[2] = {nullptr, nullptr};   // detection bits: kernel k reads one, writes
+                                             // the other
+    size_t bits_cap = 0;             // words of each bit plane set
     float *p = nullptr;
     size_t p_cap = 0;
     DevState *st = nullptr;
@@ -75,8 +77,6 @@ struct Work {
     size_t cap_cap = 0;
     uint16_t *xq = nullptr;
     size_t xq_cap = 0;
-    uint64_t *det = nullptr;         // packed detection bits (spatial replacement)
-    size_t det_cap = 0;              // in words
     AmbEntry *amb = nullptr;         // undecided voxels of the fused clip
     size_t amb_cap = 0;
     Shapes sh;                       // launch shapes of the runs on this workspace
@@ -398,23 +398,28 @@ int grow(sofia_sc *h, T *&ptr, size_t &cap, size_t need, const char *what, bool 
     return SOFIA_SC_OK;
 }
 
-// Packed detection bits: words per plane of nx * ny voxels.
-int64_t det_words_per_plane(int64_t ncol) { return (ncol + 63) / 64; }
+struct Dims {
+    int64_t nx, ny, nz, ncol, N;
+};
 
-// Workspace for cubes of up to N voxels: `parts` column blocks, the
-// smoothed-plane buffer when a kernel is spatial, det_words packed words and
-// a 16-bit cube when q16. *moved is set when any buffer was reallocated.
-int ensure_work(sofia_sc *h, Work &w, int64_t N, bool need_p, size_t parts,
-                int64_t det_words, bool q16, bool *moved = nullptr) {
+// Packed bits: words per plane of nx * ny voxels, and per cube.
+int64_t det_words_per_plane(int64_t ncol) { return (ncol + 63) / 64; }
+int64_t bit_words(const Dims &d) { return d.nz * det_words_per_plane(d.ncol); }
+
+// Workspace for cubes of up to N voxels (bit planes of `words` words):
+// `parts` column blocks, the smoothed-plane buffer when a kernel is spatial
+// and a 16-bit cube when q16. *moved is set when any buffer was reallocated.
+int ensure_work(sofia_sc *h, Work &w, int64_t N, int64_t words, bool need_p, size_t parts,
+                bool q16, bool *moved = nullptr) {
     int rc;
     size_t one = w.hist ? kHistWords : 0;
     if ((rc = grow(h, w.hist, one, kHistWords, "histograms", moved))) return rc;
-    if ((rc = grow(h, w.det, w.det_cap, (size_t)det_words, "detection bits", moved))) return rc;
-    for (int i = 0; i < 2; ++i) {
-        size_t cap = w.wm_cap;
-        if ((rc = grow(h, w.wm[i], cap, (size_t)N, "working mask", moved))) return rc;
+    uint64_t **bits[3] = {&w.blank, &w.det[0], &w.det[1]};
+    for (int i = 0; i < 3; ++i) {
+        size_t cap = w.bits_cap;
+        if ((rc = grow(h, *bits[i], cap, (size_t)words, "bit planes", moved))) return rc;
     }
-    w.wm_cap = std::max(w.wm_cap, (size_t)N);
+    w.bits_cap = std::max(w.bits_cap, (size_t)words);
     if (need_p && (rc = grow(h, w.p, w.p_cap, (size_t)N, "plane buffer", moved))) return rc;
     if ((rc = grow(h, w.amb, w.amb_cap, amb_capacity(N), "undecided list", moved))) return rc;
     if ((rc = grow(h, w.cap_buf, w.cap_cap, capture_capacity(N), "capture buffer", moved)))
@@ -430,8 +435,8 @@ int ensure_work(sofia_sc *h, Work &w, int64_t N, bool need_p, size_t parts,
 }
 
 void free_work(Work &w) {
-    void *ps[] = {w.wm[0], w.wm[1], w.p, w.st, w.hist, w.part_sum, w.part_cnt, w.cap_buf,
-                  w.xq, w.det, w.amb};
+    void *ps[] = {w.blank, w.det[0], w.det[1], w.p, w.st, w.hist, w.part_sum, w.part_cnt,
+                  w.cap_buf, w.xq, w.amb};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     w = Work{};
@@ -513,34 +518,29 @@ void collect_profile(sofia_sc *h) {
     h->recs.clear();
 }
 
-struct Dims {
-    int64_t nx, ny, nz, ncol, N;
-};
-
 // One S+C iteration on the device. k >= 0 stores sigma_k; k = -1 measures
-// sigma_0 only. wm_in (may be null only for the first, unsmoothed kernel)
-// carries the detections so far and the blank bits. clip_out = null skips
-// the clip; write_out != null writes s instead of measuring the noise.
+// sigma_0 only. det_in: the detections so far (null: none yet); blank_in:
+// the blank bits (needed when the kernel is spatial). det_out = null skips
+// the clip; otherwise the clip writes det_in | this kernel's detections
+// there, and blank_out (may be null) receives the blank bits of a pass over
+// the raw cube. write_out != null writes s instead of measuring the noise.
 struct PairJob {
-    const float *x;
-    const uint16_t *xq;   // 16-bit noise-scaled cube (xtype != ST_F32)
-    int xtype;
-    Dims d;
-    Plan pl;
-    int k;
-    bool repl_active;
-    double repl_n;
-    int mode, range;
-    double t;
-    const uint8_t *wm_in;
-    uint8_t *clip_out;
-    bool out_user;
-    bool also_sigma0;
-    float *write_out;
-    bool det_live = false;  // this call sized h->det for the cube: the clip keeps
-                            // the packed detection bits, the spatial pass reads them
-    bool det_next = false;  // the next kernel is spatial with replacement: the
-                            // clip must write the packed bits
+    const float *x = nullptr;
+    const uint16_t *xq = nullptr;   // 16-bit noise-scaled cube (xtype != ST_F32)
+    int xtype = ST_F32;
+    Dims d{};
+    Plan pl{0, 0, 1};
+    int k = 0;
+    bool repl_active = false;
+    double repl_n = 0.0;
+    int mode = 0, range = 0;
+    double t = 0.0;
+    const uint64_t *det_in = nullptr;
+    const uint64_t *blank_in = nullptr;
+    uint64_t *det_out = nullptr;
+    uint64_t *blank_out = nullptr;
+    bool also_sigma0 = false;
+    float *write_out = nullptr;
     int zstride = 1;        // the noise is measured on every zstride-th plane
 };
 
@@ -556,12 +556,7 @@ int spatial_pass(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         a.x = j.xtype == ST_F32 ? j.x : nullptr;
         a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
         a.wpp = det_words_per_plane(d.ncol);
-        a.det = nullptr;
-        if (j.repl_active) {
-            if (!j.det_live || w.det_cap < (size_t)(d.nz * a.wpp))
-                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
-            a.det = w.det;
-        }
+        a.det = j.repl_active ? j.det_in : nullptr;
         a.p = w.p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
         gauss_setup(a, j.pl.fwhm, w.sh.strip_rows);
@@ -579,12 +574,7 @@ int spatial_pass(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         a.x = j.xtype == ST_F32 ? j.x : nullptr;
         a.xq = j.xtype != ST_F32 ? j.xq : nullptr;
         a.wpp = det_words_per_plane(d.ncol);
-        a.det = nullptr;
-        if (j.repl_active) {
-            if (!j.det_live || w.det_cap < (size_t)(d.nz * a.wpp))
-                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
-            a.det = w.det;
-        }
+        a.det = j.repl_active ? j.det_in : nullptr;
         a.p = w.p;
         a.nx = d.nx; a.ny = d.ny; a.nz = d.nz;
         spatial_strips(a, j.pl.n_iter, j.pl.radius, w.sh.strip_rows, w.sh.strip_waves);
@@ -610,10 +600,9 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     int rc;
     const bool spatial = j.pl.spatial();
     const bool spec = j.pl.spectral();
-    const bool has_wm = j.wm_in != nullptr;
     const double bx = j.xtype != ST_F32 ? 2.0 : 4.0;   // bytes per raw voxel
-    if ((spatial || spec) && !has_wm)
-        return fail(h, SOFIA_SC_EINVAL, "internal: smoothing without working mask");
+    if ((spatial && !j.blank_in) || (j.repl_active && !j.det_in))
+        return fail(h, SOFIA_SC_EINVAL, "internal: bit planes missing");
 
     const ColGrid g = col_grid(d.ncol, d.nz, w.sh);
     if ((int64_t)g.ncb * g.nzc > 0x7fffffffLL)
@@ -625,7 +614,9 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     c.xq = j.xq;
     c.xtype = j.xtype;
     c.p = w.p;
-    c.wm_in = j.wm_in;
+    c.det_in = j.det_in;
+    c.blank_in = spatial ? j.blank_in : nullptr;
+    c.wpp = det_words_per_plane(d.ncol);
     c.ncol = d.ncol;
     c.nz = d.nz;
     c.w = j.pl.width;
@@ -648,10 +639,12 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
     c.cap_capacity = (unsigned long long)w.cap_cap;
     c.sel_part = w.part_cnt;
     const int src = spatial ? SRC_P : SRC_X;
-    const double rd = N * ((spatial ? 4.0 : bx) + (has_wm ? 1.0 : 0.0));
+    // algorithmic bytes of a pass: the source and the bit planes it reads
+    const double rd = N * ((spatial ? 4.0 : bx) + (j.det_in ? 0.125 : 0.0) +
+                           (spatial ? 0.125 : 0.0));
     auto col = [&](int op, int fam, double bytes) {
         return launch(h, s, fam, bytes, N, [&] {
-            return launch_column(src, op, spec, has_wm, c, g.blocks(), s);
+            return launch_column(src, op, spec, c, g.blocks(), s);
         });
     };
 
@@ -660,25 +653,17 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         return col(OP_WRITE, F_COL_WRITE, rd + 4.0 * N);
     }
 
-    // Clip target: the next working mask (with the packed detection bits a
-    // later spatial kernel replaces from) or, for the last kernel, the
-    // caller's 0/1 mask.
+    // Clip target: the detection bits after this kernel (and the blank bits
+    // when this pass is the first over the raw cube).
     double clip_bytes = 0.0;
-    if (j.clip_out) {
-        c.mask_out = j.clip_out;
-        c.out_user = j.out_user ? 1 : 0;
-        c.wpp = det_words_per_plane(d.ncol);
-        c.det_bits = nullptr;
-        if (j.det_live && j.det_next && !j.out_user) {
-            if (w.det_cap < (size_t)(d.nz * c.wpp))
-                return fail(h, SOFIA_SC_EINVAL, "internal: detection bits not sized");
-            c.det_bits = w.det;
-        }
-        clip_bytes = N + (c.det_bits ? N / 8.0 : 0.0);
+    if (j.det_out) {
+        c.det_out = j.det_out;
+        c.blank_out = spatial ? nullptr : j.blank_out;
+        clip_bytes = N / 8.0 + (c.blank_out ? N / 8.0 : 0.0);
     }
     const int cond = j.k >= 0 ? j.k : 63;
     // With MAD noise the clip rides on the selection pass (see below).
-    const bool fused = j.clip_out && j.mode != SOFIA_SC_NOISE_STD;
+    const bool fused = j.det_out && j.mode != SOFIA_SC_NOISE_STD;
 
     if (j.mode == SOFIA_SC_NOISE_STD) {
         if ((rc = col(OP_STD, F_COL_STD, rd))) return rc;
@@ -719,7 +704,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
             const int nb = cs.ncb * nzc;
             const double frac = (double)sampled / (double)nseg;
             rc = launch(h, s, F_COL_SAMPLE, rd * frac, N * frac, [&] {
-                return launch_column(src, OP_HIST1, spec, has_wm, cs, nb, s);
+                return launch_column(src, OP_HIST1, spec, cs, nb, s);
             });
             if (rc) return rc;
         }
@@ -757,7 +742,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         if (rc) return rc;
         c.skip_if_captured = 1;
         rc = launch(h, s, F_COL_HIST1, rd, N, [&] {
-            return launch_column(src, OP_HIST1, spec, has_wm, c, g.blocks(), s);
+            return launch_column(src, OP_HIST1, spec, c, g.blocks(), s);
         }, cond);
         if (rc) return rc;
         rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
@@ -770,7 +755,7 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         });
         if (rc) return rc;
         rc = launch(h, s, F_COL_HIST2, rd, N, [&] {
-            return launch_column(src, OP_HIST2, spec, has_wm, c, g.blocks(), s);
+            return launch_column(src, OP_HIST2, spec, c, g.blocks(), s);
         }, cond);
         c.skip_if_captured = 0;
         if (rc) return rc;
@@ -794,17 +779,17 @@ int run_pair(sofia_sc *h, hipStream_t s, const Work &w, const PairJob &j) {
         // the median missed the window or the list overflowed
         rc = launch(h, s, F_CLIP_FIXUP, 0, 0, [&] {
             return launch_clip_fixup(w.st, w.amb, amb_count_of(w),
-                                     (unsigned long long)w.amb_cap, c.mask_out, c.out_user,
-                                     c.det_bits, d.ncol, c.wpp, s);
+                                     (unsigned long long)w.amb_cap, c.det_out, d.ncol, c.wpp,
+                                     s);
         });
         if (rc) return rc;
         c.skip_if_fused = 1;
         rc = launch(h, s, F_COL_CLIP, rd + clip_bytes, N, [&] {
-            return launch_column(src, OP_CLIP, spec, has_wm, c, g.blocks(), s);
+            return launch_column(src, OP_CLIP, spec, c, g.blocks(), s);
         }, 64 + cond);
         c.skip_if_fused = 0;
         if (rc) return rc;
-    } else if (j.clip_out) {
+    } else if (j.det_out) {
         if ((rc = col(OP_CLIP, F_COL_CLIP, rd + clip_bytes))) return rc;
     }
     return SOFIA_SC_OK;
@@ -888,8 +873,7 @@ int plane_stride(const sofia_sc_options *opt) {
 int ensure_for(sofia_sc *h, Work &w, const RunSpec &r, bool *moved = nullptr) {
     const bool sp = r.any_spatial();
     const ColGrid g = col_grid(r.d.ncol, r.d.nz, w.sh);
-    return ensure_work(h, w, r.d.N, sp, (size_t)g.blocks(),
-                       sp ? r.d.nz * det_words_per_plane(r.d.ncol) : 0,
+    return ensure_work(h, w, r.d.N, bit_words(r.d), sp, (size_t)g.blocks(),
                        r.storage != SOFIA_SC_STORE_F32, moved);
 }
 
@@ -905,24 +889,30 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     const bool any_spatial = r.any_spatial();
     const bool repl_on = r.repl >= 0.0;
     const bool first_identity = r.plans[0].identity();
+    const int64_t wpp = det_words_per_plane(d.ncol);
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
         return launch_set_sigma0(w.st, given0 ? r.sigma0 : NAN, s);
     });
     if (rc) return rc;
-    int cur = 0;
-    bool have_wm = false;
-    if (!first_identity) {
-        rc = launch(h, s, F_INIT, 5.0 * d.N, (double)d.N, [&] {
-            return launch_init_mask(r.cube, nullptr, w.wm[0], d.N, s);
+    // The blank bits are read by the passes over a spatially smoothed cube.
+    // An unsmoothed first kernel records them in its clip; otherwise one
+    // pass over the cube does.
+    if (any_spatial && !first_identity) {
+        rc = launch(h, s, F_INIT, 4.125 * d.N, (double)d.N, [&] {
+            return launch_init_bits(r.cube, nullptr, w.blank, nullptr, d.ncol, d.nz, wpp, s);
         });
         if (rc) return rc;
-        have_wm = true;
     }
     // sigma_0 on the FP32 cube when replacement or 16-bit scaling needs it and
     // it cannot come from kernel 1 (a (0, 0) kernel measured on FP32 data).
     if (!given0 && (q16 || (repl_on && !first_identity))) {
-        PairJob j{r.cube, nullptr, ST_F32, d, Plan{0, 0, 1}, -1, false, 0.0, r.mode, r.range,
-                  r.t, have_wm ? w.wm[cur] : nullptr, nullptr, false, false, nullptr};
+        PairJob j;
+        j.x = r.cube;
+        j.d = d;
+        j.k = -1;
+        j.mode = r.mode;
+        j.range = r.range;
+        j.t = r.t;
         j.zstride = r.zstride;
         if ((rc = run_pair(h, s, w, j))) return rc;
     }
@@ -936,32 +926,36 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
         rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(w.st, s); });
         if (rc) return rc;
     }
-    uint8_t *final_wm = nullptr;
+    // kernel k reads the detections of kernels 0 .. k-1 from one bit plane
+    // set and writes its own ORed in to the other
+    const uint64_t *din = nullptr;
     for (int k = 0; k < K; ++k) {
-        const bool last = k == K - 1;
-        // the last kernel clips straight into the caller's 0/1 mask, unless
-        // the detections are to be ORed into it afterwards
-        const bool to_user = last && !r.keep;
-        uint8_t *out = to_user ? r.mask : (have_wm ? w.wm[1 - cur] : w.wm[cur]);
-        if (last) final_wm = out;
-        PairJob j{r.cube, q16 ? w.xq : nullptr, xtype, d, r.plans[k], k, repl_on && k >= 1,
-                  r.repl, r.mode, r.range, r.t, have_wm ? w.wm[cur] : nullptr, out, to_user,
-                  k == 0 && first_identity && repl_on && !given0 && !q16, nullptr,
-                  any_spatial, !last && r.plans[k + 1].spatial() && repl_on};
+        PairJob j;
+        j.x = r.cube;
+        j.xq = q16 ? w.xq : nullptr;
+        j.xtype = xtype;
+        j.d = d;
+        j.pl = r.plans[k];
+        j.k = k;
+        j.repl_active = repl_on && k >= 1;
+        j.repl_n = r.repl;
+        j.mode = r.mode;
+        j.range = r.range;
+        j.t = r.t;
+        j.det_in = din;
+        j.blank_in = w.blank;
+        j.det_out = w.det[k & 1];
+        j.blank_out = k == 0 && first_identity && any_spatial ? w.blank : nullptr;
+        j.also_sigma0 = k == 0 && first_identity && repl_on && !given0 && !q16;
         j.zstride = r.zstride;
         if ((rc = run_pair(h, s, w, j))) return rc;
-        if (!last) {
-            if (have_wm) cur = 1 - cur;
-            have_wm = true;
-        }
+        din = j.det_out;
     }
-    if (r.keep) {
-        rc = launch(h, s, F_MASK_OR, 3.0 * d.N, (double)d.N, [&] {
-            return launch_or_mask(final_wm, r.mask, d.N, s);
-        });
-        if (rc) return rc;
-    }
-    return SOFIA_SC_OK;
+    // the caller's 0/1 mask from the final detection bits (ORed into it when
+    // the caller's mask is kept)
+    return launch(h, s, F_MASK_OUT, 0.125 * d.N + (r.keep ? 2.0 : 1.0) * d.N, (double)d.N,
+                  [&] { return launch_write_mask(din, r.mask, r.keep ? 1 : 0, d.ncol, d.nz,
+                                                 wpp, s); });
 }
 
 // MAD noise of the widths of one fused chunk: per width its own state,
@@ -984,7 +978,6 @@ int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
                    nullptr)))
         return rc;
     const int src = spatial ? SRC_P : SRC_X;
-    const uint8_t *wm = w.wm[0];   // the column passes' instantiations take a working mask
     const int wb2 = (int)std::min<int64_t>(1024, std::max<int64_t>(8, d.N >> 18));
     const int wb1 = std::min(512, wb2);
     m.cap_capacity = (unsigned long long)capcap;
@@ -995,7 +988,8 @@ int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
         c.x = r.cube;
         c.p = w.p;
         c.xtype = ST_F32;
-        c.wm_in = wm;
+        c.blank_in = spatial ? w.blank : nullptr;
+        c.wpp = det_words_per_plane(d.ncol);
         c.ncol = d.ncol;
         c.nz = d.nz;
         c.w = m.w[i];
@@ -1041,7 +1035,7 @@ int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
         const double frac = (double)sampled / (double)nseg;
         const bool spec = m.w[i] >= 3;
         rc = launch(h, s, F_COL_SAMPLE, in_b * N * frac, N * frac, [&] {
-            return launch_column(src, OP_HIST1, spec, wm != nullptr, cs, nb, s);
+            return launch_column(src, OP_HIST1, spec, cs, nb, s);
         });
         if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
             return launch_finalize_predict(sti, hi + kOffSample, r.t, s);
@@ -1068,7 +1062,7 @@ int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
         if (rc) return rc;
         c.skip_if_captured = 1;
         rc = launch(h, s, F_COL_HIST1, in_b * N, N, [&] {
-            return launch_column(src, OP_HIST1, spec, wm != nullptr, c, g.blocks(), s);
+            return launch_column(src, OP_HIST1, spec, c, g.blocks(), s);
         }, k);
         if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * kL1Bins, 0, [&] {
             return launch_finalize_mad1(sti, hi, s);
@@ -1077,7 +1071,7 @@ int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
             return launch_capture_coarse(sti, m.cap[i], m.cap_count[i], hi + kOffL2c, wb2, s);
         });
         if (!rc) rc = launch(h, s, F_COL_HIST2, in_b * N, N, [&] {
-            return launch_column(src, OP_HIST2, spec, wm != nullptr, c, g.blocks(), s);
+            return launch_column(src, OP_HIST2, spec, c, g.blocks(), s);
         }, k);
         if (!rc) rc = launch(h, s, F_FINALIZE, 8.0 * 2 * kL2Coarse, 0, [&] {
             return launch_finalize_mad2a(sti, hi + kOffL2c, s);
@@ -1096,8 +1090,9 @@ int fused_mad_noise(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r,
 // Replacement off: the kernel pairs are independent, and the pairs that
 // share a spatial kernel share their passes. Per spatial kernel (in order of
 // first appearance) and up to kMultiMax of its spectral widths: the spatial
-// pass (if any), one pass accumulating every width's RMS partials, one
-// finaliser, one clip pass ORing every width's detections into the mask.
+// pass (if any), the noise of every width (one pass for the RMS partials and
+// one finaliser, or the MAD steps above), one clip pass ORing every width's
+// detections into the run's detection bits; at the end the caller's mask.
 int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     int rc;
     const Dims &d = r.d;
@@ -1105,11 +1100,11 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     const bool any_spatial = r.any_spatial();
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_set_sigma0(w.st, NAN, s); });
     if (rc) return rc;
-    // the blank bits: read by the passes over a spatially smoothed cube, and
-    // by the per-pair column passes of the MAD noise
-    if (any_spatial || r.mode != SOFIA_SC_NOISE_STD) {
-        rc = launch(h, s, F_INIT, 5.0 * N, N, [&] {
-            return launch_init_mask(r.cube, nullptr, w.wm[0], d.N, s);
+    const int64_t wpp = det_words_per_plane(d.ncol);
+    // the blank bits: read by the passes over a spatially smoothed cube
+    if (any_spatial) {
+        rc = launch(h, s, F_INIT, 4.125 * N, N, [&] {
+            return launch_init_bits(r.cube, nullptr, w.blank, nullptr, d.ncol, d.nz, wpp, s);
         });
         if (rc) return rc;
     }
@@ -1137,15 +1132,21 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
         }
         const bool spatial = sp.spatial();
         if (spatial) {
-            PairJob j{r.cube, nullptr, ST_F32, d, sp, k0, false, 0.0, r.mode, r.range, r.t,
-                      w.wm[0], nullptr, false, false, nullptr};
+            PairJob j;
+            j.x = r.cube;
+            j.d = d;
+            j.pl = sp;
+            j.k = k0;
             if ((rc = spatial_pass(h, s, w, j))) return rc;
         }
         for (size_t c0 = 0; c0 < ks.size(); c0 += kMultiMax) {
             MultiArgs m{};
             m.src = spatial ? w.p : r.cube;
-            m.wm = spatial ? w.wm[0] : nullptr;
-            m.mask = r.mask;
+            m.blank = spatial ? w.blank : nullptr;
+            // every chunk ORs its detections into the same bits in place
+            m.det_in = first ? nullptr : w.det[0];
+            m.det_out = w.det[0];
+            m.wpp = wpp;
             m.st = w.st;
             m.part_sum = h->mu_sum;
             m.part_cnt = h->mu_cnt;
@@ -1166,11 +1167,10 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
                 m.hmax = std::max(m.hmax, m.h[m.nw]);
                 ++m.nw;
             }
-            m.or_mask = (!first || r.keep) ? 1 : 0;
             const int src = spatial ? SRC_P : SRC_X;
             // algorithmic bytes: the source once (+ the blank bits) per pass;
-            // the clip's mask write (and read when ORing)
-            const double in_b = 4.0 + (spatial ? 1.0 : 0.0);
+            // the clip's detection bits out (and in when ORing)
+            const double in_b = 4.0 + (spatial ? 0.125 : 0.0);
             if (r.mode == SOFIA_SC_NOISE_STD) {
                 rc = launch(h, s, F_MULTI_STATS, in_b * N, N * m.nw,
                             [&] { return launch_multi(src, MOP_STATS, m, g.blocks(), s); });
@@ -1179,13 +1179,16 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
             } else {
                 rc = fused_mad_noise(h, s, w, r, g, m, spatial, in_b);
             }
-            if (!rc) rc = launch(h, s, F_MULTI_CLIP, (in_b + 1.0 + m.or_mask) * N, N * m.nw,
+            if (!rc) rc = launch(h, s, F_MULTI_CLIP, (in_b + (first ? 0.125 : 0.25)) * N,
+                                 N * m.nw,
                                  [&] { return launch_multi(src, MOP_CLIP, m, g.blocks(), s); });
             if (rc) return rc;
             first = false;
         }
     }
-    return SOFIA_SC_OK;
+    return launch(h, s, F_MASK_OUT, 0.125 * N + (r.keep ? 2.0 : 1.0) * N, N, [&] {
+        return launch_write_mask(w.det[0], r.mask, r.keep ? 1 : 0, d.ncol, d.nz, wpp, s);
+    });
 }
 
 // Noise values of a finished run in cube units, and its sigma_0 output.
@@ -1847,13 +1850,12 @@ size_t carve_work(Work &w, uint8_t *base, const RunSpec &r) {
     const size_t N = (size_t)r.d.N;
     w.st = c.take<DevState>(1);
     w.hist = c.take<unsigned long long>(kHistWords);
-    w.wm[0] = c.take<uint8_t>(N);
-    w.wm[1] = c.take<uint8_t>(N);
-    w.wm_cap = N;
+    w.bits_cap = (size_t)bit_words(r.d);
+    w.blank = c.take<uint64_t>(w.bits_cap);
+    w.det[0] = c.take<uint64_t>(w.bits_cap);
+    w.det[1] = c.take<uint64_t>(w.bits_cap);
     w.p = sp ? c.take<float>(N) : nullptr;
     w.p_cap = sp ? N : 0;
-    w.det_cap = sp ? (size_t)(r.d.nz * det_words_per_plane(r.d.ncol)) : 0;
-    w.det = sp ? c.take<uint64_t>(w.det_cap) : nullptr;
     w.amb_cap = amb_capacity(r.d.N);
     w.amb = c.take<AmbEntry>(w.amb_cap);
     w.cap_cap = capture_capacity(r.d.N);
@@ -2121,25 +2123,20 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     h->w.sh = shapes_of(h->tune);
     const ColGrid g = col_grid(d.ncol, d.nz, h->w.sh);
     if ((rc = ensure_state(h))) return rc;
-    if ((rc = ensure_work(h, h->w, d.N, pl.spatial(), (size_t)g.blocks(),
-                          pl.spatial() ? d.nz * det_words_per_plane(d.ncol) : 0, q16)))
+    if ((rc = ensure_work(h, h->w, d.N, bit_words(d), pl.spatial(), (size_t)g.blocks(), q16)))
         return rc;
     const Work &w = h->w;
+    const int64_t wpp = det_words_per_plane(d.ncol);
     rc = launch(h, s, F_FINALIZE, 0, 0, [&] {
         return launch_set_sigma0(w.st, (repl || q16) ? sigma0 : NAN, s);
     });
     if (rc) return rc;
-    rc = launch(h, s, F_INIT, (mask_in ? 6.0 : 5.0) * d.N, (double)d.N, [&] {
-        return launch_init_mask(cube, mask_in, w.wm[0], d.N, s);
+    // blank bits, and the caller's mask as the detections so far
+    rc = launch(h, s, F_INIT, (mask_in ? 5.25 : 4.125) * d.N, (double)d.N, [&] {
+        return launch_init_bits(cube, mask_in, w.blank, mask_in ? w.det[0] : nullptr, d.ncol,
+                                d.nz, wpp, s);
     });
     if (rc) return rc;
-    if (pl.spatial() && repl) {
-        rc = launch(h, s, F_INIT, 1.125 * d.N, (double)d.N, [&] {
-            return launch_pack_det(w.wm[0], w.det, d.ncol, d.nz,
-                                   det_words_per_plane(d.ncol), s);
-        });
-        if (rc) return rc;
-    }
     int xtype = ST_F32;
     if (q16) {
         xtype = storage == SOFIA_SC_STORE_F16 ? ST_F16 : ST_BF16;
@@ -2150,12 +2147,30 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
         rc = launch(h, s, F_FINALIZE, 0, 0, [&] { return launch_enter_scaled(w.st, s); });
         if (rc) return rc;
     }
-    PairJob j{cube, q16 ? w.xq : nullptr, xtype, d, pl, 0, repl, replacement,
-              write_out ? 0 : mode, write_out ? 0 : range, write_out ? 1.0 : threshold,
-              w.wm[0], write_out ? nullptr : mask_out, true, false, write_out,
-              pl.spatial()};
+    PairJob j;
+    j.x = cube;
+    j.xq = q16 ? w.xq : nullptr;
+    j.xtype = xtype;
+    j.d = d;
+    j.pl = pl;
+    j.k = 0;
+    j.repl_active = repl && mask_in;
+    j.repl_n = replacement;
+    j.mode = write_out ? 0 : mode;
+    j.range = write_out ? 0 : range;
+    j.t = write_out ? 1.0 : threshold;
+    j.det_in = mask_in ? w.det[0] : nullptr;
+    j.blank_in = w.blank;
+    j.det_out = write_out ? nullptr : w.det[1];
+    j.write_out = write_out;
     j.zstride = zstride;
     if ((rc = run_pair(h, s, w, j))) return rc;
+    if (!write_out) {
+        rc = launch(h, s, F_MASK_OUT, 1.125 * d.N, (double)d.N, [&] {
+            return launch_write_mask(w.det[1], mask_out, 0, d.ncol, d.nz, wpp, s);
+        });
+        if (rc) return rc;
+    }
     if ((rc = finish(h, s, h->st_host, w.st))) return rc;
     if (write_out) return SOFIA_SC_OK;
     *noise = h->st_host->sigma[0] * (q16 ? h->st_host->scale : 1.0);

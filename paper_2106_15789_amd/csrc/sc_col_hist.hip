@@ -3,9 +3,9 @@
 
 namespace sc {
 
-template hipError_t launch_column_op<OP_HIST1>(int src, bool spec, bool has_wm,
+template hipError_t launch_column_op<OP_HIST1>(int src, bool spec,
                                                const ColArgs &a, int nb, hipStream_t s);
-template hipError_t launch_column_op<OP_HIST2>(int src, bool spec, bool has_wm,
+template hipError_t launch_column_op<OP_HIST2>(int src, bool spec,
                                                const ColArgs &a, int nb, hipStream_t s);
 
 }  // namespace sc

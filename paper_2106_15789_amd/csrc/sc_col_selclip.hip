@@ -4,7 +4,7 @@
 
 namespace sc {
 
-template hipError_t launch_column_op<OP_SELCLIP>(int src, bool spec, bool has_wm,
+template hipError_t launch_column_op<OP_SELCLIP>(int src, bool spec,
                                                 const ColArgs &a, int nb, hipStream_t s);
 
 }  // namespace sc

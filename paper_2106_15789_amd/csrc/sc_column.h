@@ -33,7 +33,7 @@ struct ColGroup {
     static constexpr int G = W >= 3 ? W * ((8 + W - 1) / W) : 8;
 };
 
-template <int SRC, int OP, bool HASWM, int W, int XT>
+template <int SRC, int OP, int W, int XT>
 __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     extern __shared__ float dyn_lds[];
     constexpr int B = kColThreads;
@@ -51,11 +51,19 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // evenly over x and y; the other passes take B adjacent columns per block.
     // Either way thread tid owns column col0 + tid.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
     const int64_t col0 =
         a.cb_stride > 1
             ? (((int64_t)cb * (B / 64) + wave) * a.cb_stride - wave) * 64
             : (int64_t)cb * B;
     const bool active = col0 + tid < ncol;
+    // The wave's 64 columns start at a multiple of 64: they are word wcol of
+    // every plane of the packed bits. A wave with no column in the plane
+    // idles; in a partly filled wave the lanes past the plane's end run
+    // along as blanked voxels and load nothing.
+    const int64_t wcol = (col0 >> 6) + wave;
+    const bool live = col0 + 64 * wave < ncol;
+    const uint64_t live_m = wave_mask(active);   // the wave's columns inside the plane
     const int nz = (int)a.nz;
     const int z0 = zc * a.zchunk;
     const int z1 = min(nz, z0 + a.zchunk);
@@ -78,19 +86,19 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     }
     if (kHistWords) __syncthreads();
 
-    const bool repl = SRC == SRC_X && HASWM && a.repl_on;
+    const bool repl = SRC == SRC_X && a.det_in && a.repl_on;
     const float rv = repl ? (float)(a.repl_n * a.st->sigma0) : 0.f;
     constexpr bool SELCLIP = OP == OP_SELCLIP;
     const double T = (OP == OP_CLIP) ? a.st->thr : 0.0;
     const double Tlo = SELCLIP ? a.st->thr_lo : 0.0, Thi = SELCLIP ? a.st->thr_hi : 0.0;
     uint32_t b0 = 0xffffffffu, b1 = 0xffffffffu;
     if (OP == OP_HIST2) { b0 = a.st->bin[0]; b1 = a.st->bin[1]; }
-    // Flux range as a sign test without branches: all voxels, or those with
-    // s * range > 0 (s < 0 for range -1, s > 0 for range +1).
-    const bool all_range = a.range == 0;
+    // Flux range as a lane mask: all voxels, or those with s * range > 0
+    // (s < 0 for range -1, s > 0 for range +1).
+    const uint64_t all_m = a.range == 0 ? ~0ull : 0ull;
     const double rsgn = (double)a.range;
-    auto in_range = [&](double s) { return all_range | (s * rsgn > 0.0); };
-    ColAcc acc{0.0, 0ull};
+    auto range_mask = [&](double s) { return all_m | wave_mask(s * rsgn > 0.0); };
+    ColAcc acc{0.0, 0ull};   // sum: this lane's; cnt: the wave's (same in every lane)
     const float *src = SRC == SRC_X ? a.x : a.p;
 
     // Selection pass: count the selected voxels and the keys below the
@@ -100,6 +108,8 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     constexpr bool capture = OP == OP_SELECT || OP == OP_SELCLIP;
     uint32_t klo = 1, khi = 0;
     if (capture) { klo = a.st->klo; khi = a.st->khi; }
+    // selected voxels and keys below the window: wave totals (same in every
+    // lane), counted from lane masks
     unsigned n_sel = 0, n_below = 0;
     uint32_t *capw = (uint32_t *)(hist + kHistWords) + (tid >> 6) * kCapStride(G);
     int fill = 0;   // entries in this wave's buffer (same in every lane)
@@ -154,68 +164,61 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         afill = 0;
     };
 
-    // Clip output byte of a voxel and, when kept, its packed detection bit.
-    auto clip_out = [&](int64_t po, int64_t zw, bool blank, uint8_t wb, uint8_t det) {
-        uint8_t out;
-        if (a.out_user) out = (uint8_t)((wb & kDet) | det);
-        else out = (uint8_t)(wb | det | (blank ? kBlank : 0));
-        buf_st_u8(out, plane_rsrc(a.mask_out + po), (uint32_t)tid, 0u);
-        if (a.det_bits) {
-            // the wave's 64 columns start at a multiple of 64: one word
-            const uint64_t bits = __ballot((out & kDet) != 0);
-            if ((tid & 63) == 0) a.det_bits[zw + ((col0 + tid) >> 6)] = bits;
-        }
+    // Clip output: the wave's words of the group's planes, lane j holding
+    // plane j's (its earlier detections ORed with this kernel's; for a pass
+    // over the raw cube also its blank bits), stored once per group.
+    uint64_t oacc = 0, bacc = 0;
+    auto put_word = [&](int j, uint64_t det_word, uint64_t blank_m) {
+        oacc = with_lane_word(oacc, j, det_word);
+        if (SRC == SRC_X) bacc = with_lane_word(bacc, j, blank_m & live_m);
     };
 
-    // Per-voxel operation on the smoothed value s of output plane zo; po =
-    // zo * ncol + col0 and zw = zo * wpp are kept as running sums by the
-    // caller (no 64-bit multiply per plane).
-    // zs: the output plane is one the noise is measured on (every plane
-    // unless the noise is subsampled); the clip takes every plane.
-    auto consume = [&](int64_t po, int64_t zw, double s, bool blank, uint8_t wb, bool zs) {
+    // Per-voxel operation on the smoothed value s of plane j of the group
+    // (output plane zo). Predicates are lane masks: blank_m marks blanked
+    // voxels and lanes past the plane's end, dprev the plane's detections so
+    // far; zsel: the plane is one the noise is measured on (every plane
+    // unless the noise is subsampled; the clip takes every plane).
+    auto consume = [&](int j, int zo, double s, uint64_t blank_m, uint64_t dprev, bool zsel) {
+        const uint64_t ok_m = ~blank_m;
         if (OP == OP_STD) {
-            const bool sel = !blank & in_range(s) & zs;
-            acc.sum += sel ? s * s : 0.0;
-            acc.cnt += sel ? 1ull : 0ull;
+            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            acc.sum += lane_bit(sel_m) ? s * s : 0.0;
+            acc.cnt += (unsigned long long)__popcll(sel_m);
         } else if (OP == OP_HIST1) {
-            if (!blank & in_range(s) & zs) {
+            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            if (lane_bit(sel_m)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
             }
         } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
-            // predicates combine bitwise: no branch per voxel
-            const bool sel = !blank & in_range(s) & zs;
+            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
             const uint32_t key = __float_as_uint(fabsf((float)s));
-            n_sel += sel ? 1u : 0u;
-            n_below += (sel & (key < klo)) ? 1u : 0u;
-            const bool want = sel & (key >= klo) & (key <= khi);
-            const unsigned long long bal = __ballot(want);
+            n_sel += (unsigned)__popcll(sel_m);
+            n_below += (unsigned)__popcll(sel_m & wave_mask(key < klo));
+            const uint64_t want_m = sel_m & wave_mask(key >= klo) & wave_mask(key <= khi);
             // every lane writes: a capturing lane to its place in the list,
             // the others to a slot of their own past the list's end
-            const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            capw[want ? fill + below : kCapPerWave(G) + (tid & 63)] = key;
-            fill += __popcll(bal);
+            capw[lane_bit(want_m) ? fill + lanes_below(want_m) : kCapPerWave(G) + lane] = key;
+            fill += __popcll(want_m);
             if (SELCLIP) {
                 // clip now unless |s| lies in (thr_lo, thr_hi], where the
                 // decision waits for the exact threshold
                 const double as = fabs(s);
-                const bool det = !blank & (as > Thi);
-                const bool amb = !blank & (as > Tlo) & !det;
-                clip_out(po, zw, blank, wb, det ? kDet : 0);
-                const unsigned long long ab = __ballot(amb);
-                if (ab) {
-                    if (amb) {
-                        const int at = afill + (int)__builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(ab >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ab, 0u));
+                const uint64_t det_m = ok_m & wave_mask(as > Thi);
+                const uint64_t amb_m = ok_m & wave_mask(as > Tlo) & ~det_m;
+                put_word(j, det_m | dprev, blank_m);
+                if (amb_m) {
+                    if (lane_bit(amb_m)) {
+                        const int at = afill + lanes_below(amb_m);
                         if (at < kAmbPerWave)
-                            ambw[at] = AmbEntry{(uint64_t)(po + tid), s};
+                            ambw[at] = AmbEntry{(uint64_t)((int64_t)zo * ncol + col0 + tid), s};
                     }
-                    afill += __popcll(ab);
+                    afill += __popcll(amb_m);
                 }
             }
         } else if (OP == OP_HIST2) {
-            if (!blank & in_range(s) & zs) {
+            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            if (lane_bit(sel_m)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 const uint32_t k1 = key >> kL1Shift;
                 const uint32_t lo = key & (kL2Bins - 1);
@@ -229,16 +232,18 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_CLIP) {
-            clip_out(po, zw, blank, wb, (!blank & (fabs(s) > T)) ? kDet : 0);
+            put_word(j, (ok_m & wave_mask(fabs(s) > T)) | dprev, blank_m);
         } else {  // OP_WRITE
-            buf_st_f32(blank ? NAN : (float)s, plane_rsrc(a.s_out + po), 4u * (uint32_t)tid, 0u);
+            if (active)
+                buf_st_f32(lane_bit(blank_m) ? NAN : (float)s,
+                           plane_rsrc(a.s_out + (int64_t)zo * ncol + col0), 4u * (uint32_t)tid, 0u);
         }
     };
 
     // Spectral input of a raw voxel: blanked -> 0, detected -> +-n sigma_0.
-    auto raw_value = [&](float xv, uint8_t wb) -> float {
+    auto raw_value = [&](float xv, bool det) -> float {
         if (!isfinite(xv)) return 0.f;
-        if (repl & ((wb & kDet) != 0)) return copysignf(rv, xv);
+        if (repl & det) return copysignf(rv, xv);
         return xv;
     };
 
@@ -248,8 +253,12 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     struct Group {
         float v[G];
         uint16_t q[G];
-        uint8_t b[G];    // working-mask byte of the input plane (SRC_X) or of
-                         // the output plane (SRC_P)
+        // Packed bits of the group's planes: lane j holds the wave's word of
+        // plane j (the input plane for SRC_X, the output plane for SRC_P),
+        // detection bits in dw and blank bits in bw (SRC_P), so that one load
+        // per group fetches them and each plane's word is read back from its
+        // lane.
+        uint64_t dw, bw;
     };
     auto in_value = [&](const Group &g, int j) -> float {
         if (!Q16) return g.v[j];
@@ -257,7 +266,6 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     };
     const int zs = SPEC ? z0 - h : z0;
     const int ze = SPEC ? z1 + h : z1;   // exclusive
-    const int64_t hoff = (int64_t)h * ncol;
     auto load_group = [&](int zb, Group &g) {
         int64_t off = (int64_t)zb * ncol + col0;   // running: plane zb + j
 #pragma unroll
@@ -265,23 +273,38 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             const int zi = zb + j;
             g.v[j] = 0.f;
             g.q[j] = 0;
-            g.b[j] = 0;
-            if (zi < ze && zi >= 0 && zi < nz) {
+            if (active && zi < ze && zi >= 0 && zi < nz) {
                 if (Q16) g.q[j] = buf_u16(plane_rsrc(a.xq + off), 2u * (uint32_t)tid, 0u);
                 else g.v[j] = buf_f32(plane_rsrc(src + off), 4u * (uint32_t)tid, 0u);
-                if (SRC == SRC_X && HASWM)
-                    g.b[j] = buf_u8(plane_rsrc(a.wm_in + off), (uint32_t)tid, 0u);
             }
-            if (SRC == SRC_P) {
-                const int zo = zi - h;
-                if (zi < ze && zo >= z0)
-                    g.b[j] = buf_u8(plane_rsrc(a.wm_in + (off - hoff)), (uint32_t)tid, 0u);
+        }
+        g.dw = 0;
+        g.bw = 0;
+        if (lane < G) {
+            const int zi = zb + lane;
+            const int zp = SRC == SRC_P ? zi - h : zi;
+            const bool ok = zi < ze && (SRC == SRC_P ? zp >= z0 : (zi >= 0 && zi < nz));
+            if (ok) {
+                const int64_t wi = (int64_t)zp * a.wpp + wcol;
+                if (a.det_in) g.dw = a.det_in[wi];
+                if (SRC == SRC_P) g.bw = a.blank_in[wi];
             }
+        }
+    };
+    // After the group zb: its clip words to the bit planes (lane j: plane j,
+    // where that plane was an output plane of this block).
+    auto store_words = [&](int zb) {
+        const int zi = zb + lane;
+        const int zo = SPEC ? zi - h : zi;
+        if (lane < G && zi < ze && zo >= z0) {
+            const int64_t wi = (int64_t)zo * a.wpp + wcol;
+            a.det_out[wi] = oacc;
+            if (SRC == SRC_X && a.blank_out) a.blank_out[wi] = bacc;
         }
     };
 
     float ring[W >= 3 ? W : 1];
-    uint8_t bring[W >= 3 ? W : 1];
+    uint8_t bring[W >= 3 ? W : 1];   // SRC_X: working bytes of the window's planes
 #pragma unroll
     for (int j = 0; j < (W >= 3 ? W : 1); ++j) { ring[j] = 0.f; bring[j] = 0; }
     int lslot = 0;           // W = 0: LDS ring slot of the next input
@@ -292,30 +315,49 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     auto process_group = [&](int zb, const Group &g) {
         // output plane of step j: zb + j (no spectral smoothing) or zb + j - h
         const int zo0 = SPEC ? zb - h : zb;
-        int64_t po = (int64_t)zo0 * ncol + col0, zw = (int64_t)zo0 * a.wpp;
+        // bit j: output plane zo0 + j is one the noise is measured on
+        uint32_t zbits = 0xffffffffu;
+        if (a.zstride > 1) {
+            zbits = 0u;
+            for (int j = 0; j < G; ++j)
+                if ((zo0 + j) % a.zstride == 0) zbits |= 1u << j;
+        }
 #pragma unroll
-        for (int j = 0; j < G; ++j, po += ncol, zw += a.wpp) {
+        for (int j = 0; j < G; ++j) {
             const int zi = zb + j;
             if (zi >= ze) break;
+            const int zo = zo0 + j;
+            const bool zsel = (zbits >> j) & 1u;
             if (!SPEC) {
                 const float xv = in_value(g, j);
-                const bool zs = a.zstride <= 1 || zi % a.zstride == 0;
-                if (SRC == SRC_X) {
-                    const bool blank = !isfinite(xv);
-                    consume(po, zw, (double)raw_value(xv, g.b[j]), blank, g.b[j], zs);
-                } else {
-                    consume(po, zw, (double)xv, (g.b[j] & kBlank) != 0, g.b[j], zs);
-                }
+                const uint64_t dprev = lane_word(g.dw, j);
+                if (SRC == SRC_X)
+                    consume(j, zo, (double)raw_value(xv, lane_bit(dprev)),
+                            ~live_m | wave_mask(!isfinite(xv)), dprev, zsel);
+                else
+                    consume(j, zo, (double)xv, ~live_m | lane_word(g.bw, j), dprev, zsel);
                 continue;
             }
-            const float vn = SRC == SRC_X ? raw_value(in_value(g, j), g.b[j]) : g.v[j];
+            // SRC_X keeps the working byte (kDet, kBlank) of every plane of
+            // the window in a ring next to the values
+            float vn;
+            uint8_t wb_in = 0;
+            if (SRC == SRC_X) {
+                const float xv = in_value(g, j);
+                const bool det = lane_bit(lane_word(g.dw, j));
+                const bool blank = !active | !isfinite(xv);
+                wb_in = (uint8_t)((det ? kDet : 0) | (blank ? kBlank : 0));
+                vn = raw_value(xv, det);
+            } else {
+                vn = g.v[j];
+            }
             float vo;
-            uint8_t wb_out = g.b[j];
+            uint8_t wb_out = 0;
             if (LDSRING) {
                 vo = lring[lslot * B + tid];
                 lring[lslot * B + tid] = vn;
                 if (SRC == SRC_X) {
-                    lbring[lslot * B + tid] = g.b[j];
+                    lbring[lslot * B + tid] = wb_in;
                     int os = lslot + h + 1;
                     if (os >= w) os -= w;
                     wb_out = lbring[os * B + tid];
@@ -327,16 +369,25 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 vo = ring[sl];
                 ring[sl] = vn;
                 if (SRC == SRC_X) {
-                    bring[sl] = g.b[j];
+                    bring[sl] = wb_in;
                     wb_out = bring[(j + kW - (kW - 1) / 2) % kW];
                 }
             }
             S += (double)vn - (double)vo;
-            const int zo = zi - h;
-            if (zo >= z0)
-                consume(po, zw, S * inv_w, (wb_out & kBlank) != 0, wb_out,
-                        a.zstride <= 1 || zo % a.zstride == 0);
+            if (zo >= z0) {
+                // output plane zo: its blank bits and earlier detections
+                uint64_t blank_m, dprev;
+                if (SRC == SRC_P) {
+                    blank_m = ~live_m | lane_word(g.bw, j);
+                    dprev = lane_word(g.dw, j);
+                } else {
+                    blank_m = wave_mask(wb_out >= kBlank);
+                    dprev = wave_mask((wb_out & kDet) != 0);
+                }
+                consume(j, zo, S * inv_w, blank_m, dprev, zsel);
+            }
         }
+        if (OP == OP_CLIP || OP == OP_SELCLIP) store_words(zb);
         // The buffer holds one more group on top of kCapFlushAt entries.
         if (capture && fill > kCapFlushAt) flush();
         if (SELCLIP && afill > kAmbFlushAt) flush_amb();
@@ -351,7 +402,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         }
     };
 
-    if (active) {
+    if (live) {
         Group ga, gb;
         load_group(zs, ga);
         for (int zb = zs; zb < ze; zb += 2 * G) {
@@ -368,7 +419,6 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         // the whole grid serialises its atomics, so they are kept few).
         __shared__ unsigned wfill[2][B / 64];
         __shared__ unsigned long long wbase[2];
-        const int lane = tid & 63;
         if (lane == 0) {
             wfill[0][wave] = (unsigned)fill;
             wfill[1][wave] = (unsigned)afill;
@@ -408,7 +458,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         __shared__ double rs[B];
         __shared__ unsigned long long rc[B];
         rs[tid] = acc.sum;
-        rc[tid] = acc.cnt;
+        rc[tid] = lane == 0 ? acc.cnt : 0ull;   // the count is a wave total
         __syncthreads();
         for (int off = B / 2; off > 0; off >>= 1) {
             if (tid < off) { rs[tid] += rs[tid + off]; rc[tid] += rc[tid + off]; }
@@ -421,8 +471,8 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
     } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
         __shared__ unsigned long long rc[2][B];
-        rc[0][tid] = n_sel;
-        rc[1][tid] = n_below;
+        rc[0][tid] = lane == 0 ? n_sel : 0u;   // wave totals
+        rc[1][tid] = lane == 0 ? n_below : 0u;
         __syncthreads();
         for (int off = B / 2; off > 0; off >>= 1) {
             if (tid < off) { rc[0][tid] += rc[0][tid + off]; rc[1][tid] += rc[1][tid + off]; }
@@ -464,51 +514,41 @@ inline size_t column_lds_bytes(int src, int op, bool spectral, int w) {
     return b;
 }
 
-template <int SRC, int OP, bool HASWM, int W, int XT>
+template <int SRC, int OP, int W, int XT>
 hipError_t column_inst(const ColArgs &a, int nblocks, hipStream_t s) {
     const size_t lds = column_lds_bytes(SRC, OP, W != 1, a.w);
-    hipLaunchKernelGGL((k_column<SRC, OP, HASWM, W, XT>), dim3(nblocks), dim3(kColThreads),
-                       lds, s, a);
+    hipLaunchKernelGGL((k_column<SRC, OP, W, XT>), dim3(nblocks), dim3(kColThreads), lds, s, a);
     return hipGetLastError();
 }
 
-template <int SRC, int OP, bool HASWM, int XT>
+template <int SRC, int OP, int XT>
 hipError_t column_width(int w, const ColArgs &a, int nb, hipStream_t s) {
     switch (ring_template_width(w)) {
-        case 1: return column_inst<SRC, OP, HASWM, 1, XT>(a, nb, s);
-        case 3: return column_inst<SRC, OP, HASWM, 3, XT>(a, nb, s);
-        case 5: return column_inst<SRC, OP, HASWM, 5, XT>(a, nb, s);
-        case 7: return column_inst<SRC, OP, HASWM, 7, XT>(a, nb, s);
-        case 9: return column_inst<SRC, OP, HASWM, 9, XT>(a, nb, s);
-        case 11: return column_inst<SRC, OP, HASWM, 11, XT>(a, nb, s);
-        case 15: return column_inst<SRC, OP, HASWM, 15, XT>(a, nb, s);
-        case 21: return column_inst<SRC, OP, HASWM, 21, XT>(a, nb, s);
-        case 31: return column_inst<SRC, OP, HASWM, 31, XT>(a, nb, s);
-        default: return column_inst<SRC, OP, HASWM, 0, XT>(a, nb, s);
+        case 1: return column_inst<SRC, OP, 1, XT>(a, nb, s);
+        case 3: return column_inst<SRC, OP, 3, XT>(a, nb, s);
+        case 5: return column_inst<SRC, OP, 5, XT>(a, nb, s);
+        case 7: return column_inst<SRC, OP, 7, XT>(a, nb, s);
+        case 9: return column_inst<SRC, OP, 9, XT>(a, nb, s);
+        case 11: return column_inst<SRC, OP, 11, XT>(a, nb, s);
+        case 15: return column_inst<SRC, OP, 15, XT>(a, nb, s);
+        case 21: return column_inst<SRC, OP, 21, XT>(a, nb, s);
+        case 31: return column_inst<SRC, OP, 31, XT>(a, nb, s);
+        default: return column_inst<SRC, OP, 0, XT>(a, nb, s);
     }
-}
-
-template <int SRC, int OP, int XT>
-hipError_t column_op_xt(bool spec, bool has_wm, const ColArgs &a, int nb, hipStream_t s) {
-    const int w = spec ? a.w : 1;
-    if (SRC == SRC_P || spec) {
-        if (!has_wm) return hipErrorInvalidValue;
-        return column_width<SRC, OP, true, XT>(w, a, nb, s);
-    }
-    return has_wm ? column_inst<SRC, OP, true, 1, XT>(a, nb, s)
-                  : column_inst<SRC, OP, false, 1, XT>(a, nb, s);
 }
 
 // Launch one operation of the column kernel; the raw cube's storage only
 // matters for SRC_X (SRC_P is always the FP32 smoothed buffer).
 template <int OP>
-hipError_t launch_column_op(int src, bool spec, bool has_wm, const ColArgs &a, int nb,
-                            hipStream_t s) {
-    if (src == SRC_P) return column_op_xt<SRC_P, OP, ST_F32>(spec, has_wm, a, nb, s);
+hipError_t launch_column_op(int src, bool spec, const ColArgs &a, int nb, hipStream_t s) {
+    if (src == SRC_P && !a.blank_in) return hipErrorInvalidValue;
+    if ((OP == OP_CLIP || OP == OP_SELCLIP) && !a.det_out) return hipErrorInvalidValue;
+    const int w = spec ? a.w : 1;
+    if (src == SRC_P) return column_width<SRC_P, OP, ST_F32>(w, a, nb, s);
     switch (a.xtype) {
-        case ST_F32: return column_op_xt<SRC_X, OP, ST_F32>(spec, has_wm, a, nb, s);
-        case ST_F16: return column_op_xt<SRC_X, OP, ST_F16>(spec, has_wm, a, nb, s);
-        case ST_BF16: return column_op_xt<SRC_X, OP, ST_BF16>(spec, has_wm, a, nb, s);
+        case ST_F32: return column_width<SRC_X, OP, ST_F32>(w, a, nb, s);
+        case ST_F16: return column_width<SRC_X, OP, ST_F16>(w, a, nb, s);
+        case ST_BF16: return column_width<SRC_X, OP, ST_BF16>(w, a, nb, s);
     }
     return hipErrorInvalidValue;
 }

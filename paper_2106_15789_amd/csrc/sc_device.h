@@ -47,6 +47,29 @@ __device__ __forceinline__ void buf_st_u8(uint8_t v, __amdgpu_buffer_rsrc_t r, u
     __builtin_amdgcn_raw_buffer_store_b8(v, r, (int)voff, (int)soff, 0);
 }
 
+// Lane masks of a wave: bit l of wave_mask(b) is lane l's b; lane_bit(m) is
+// this lane's bit of a wave-uniform mask (the mask itself serves as the
+// predicate, no per-lane arithmetic).
+__device__ __forceinline__ uint64_t wave_mask(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+__device__ __forceinline__ bool lane_bit(uint64_t m) {
+    return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+// The 64-bit value that lane j (a wave-uniform index) holds, in every lane.
+__device__ __forceinline__ uint64_t lane_word(uint64_t v, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+// v with lane j (a compile-time index) replaced by the wave-uniform w.
+__device__ __forceinline__ uint64_t with_lane_word(uint64_t v, int j, uint64_t w) {
+    return lane_bit(1ull << j) ? w : v;
+}
+// Number of lanes below this one whose bit is set in the mask m.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
 // b % 8). Remap so that each XCD works through one contiguous range of
 // workgroups: neighbouring row chunks then share their halo rows through the

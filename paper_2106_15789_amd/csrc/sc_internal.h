@@ -9,12 +9,13 @@
 
 namespace sc {
 
-// Working-mask bits. The library keeps its own per-voxel byte: bit 0 = in the
-// detection mask so far, bit 1 = blanked (non-finite input). The caller's
-// mask only ever receives 0/1. Next to it, the detection bits alone are kept
-// packed, 64 voxels of a row-major plane per word, for the spatial kernel:
-// its waves need them across 64 unaligned columns per row, which a byte per
-// lane would fetch several times over.
+// Working state of a run, packed one bit per voxel: word w of plane z holds
+// columns 64w .. 64w+63 of that row-major plane (bit b = column 64w + b), so
+// that a wave of 64 adjacent columns reads or writes one word per plane.
+// Blank bits mark non-finite inputs (fixed for a run); detection bits mark
+// the mask so far. The caller's byte mask only receives 0/1 at the end. In a
+// kernel a voxel's working byte combines the two: kDet = detected so far,
+// kBlank = blanked.
 constexpr uint8_t kDet = 1;
 constexpr uint8_t kBlank = 2;
 
@@ -94,8 +95,11 @@ struct ColArgs {
     int32_t xtype;               // Storage of the raw cube
     int32_t pad0;
     const float *p;              // spatially smoothed cube (SRC_P)
-    const uint8_t *wm_in;        // working mask (may be null when has_wm is false)
-    uint8_t *mask_out;           // OP_CLIP output
+    const uint64_t *det_in;      // detection bits so far (null: none yet)
+    const uint64_t *blank_in;    // blank bits (SRC_P; SRC_X tests its input)
+    uint64_t *det_out;           // OP_CLIP / OP_SELCLIP: detection bits after this kernel
+    uint64_t *blank_out;         // OP_CLIP / OP_SELCLIP on SRC_X: blank bits out (may be null)
+    int64_t wpp;                 // 64-bit words per plane of the bit planes
     float *s_out;                // OP_WRITE output
     int64_t ncol;                // nx * ny
     int64_t nz;
@@ -105,8 +109,6 @@ struct ColArgs {
     int32_t range;               // -1 negative, 0 all, +1 positive
     int32_t repl_on;             // replace detected voxels (SRC_X only)
     double repl_n;               // n of +-n sigma0
-    int32_t out_user;            // OP_CLIP: write 0/1 instead of working bits
-    int32_t pad;
     DevState *st;
     double *part_sum;            // OP_STD per-block partials
     unsigned long long *part_cnt;
@@ -120,8 +122,6 @@ struct ColArgs {
     unsigned long long cap_capacity;
     unsigned long long *sel_part;    // OP_SELECT / OP_SELCLIP: per block [selected voxels,
                                      // keys below klo], 2 per block
-    uint64_t *det_bits;          // OP_CLIP / OP_SELCLIP: packed detection bits out (may be null)
-    int64_t wpp;                 // 64-bit words per plane of det_bits
     AmbEntry *amb;               // OP_SELCLIP: undecided voxels
     unsigned long long *amb_count;
     unsigned long long amb_capacity;
@@ -158,14 +158,16 @@ constexpr int kMultiStage = 256;     // captured keys staged per wave and width 
 enum MultiOp { MOP_STATS = 0, MOP_CLIP = 1, MOP_SELECT = 2 };
 struct MultiArgs {
     const float *src;
-    const uint8_t *wm;               // working mask (blank bits), SRC_P
-    uint8_t *mask;                   // caller's 0/1 mask (CLIP)
+    const uint64_t *blank;           // blank bits (SRC_P)
+    const uint64_t *det_in;          // CLIP: detection bits so far (null: none; may equal det_out)
+    uint64_t *det_out;               // CLIP: detection bits out
+    int64_t wpp;                     // 64-bit words per plane of the bit planes
     DevState *st;
     double *part_sum;                // [nw][nparts]
     unsigned long long *part_cnt;    // [nw][nparts]
     int64_t ncol, nz;
     int32_t ncb, zchunk, nparts;
-    int32_t nw, hmax, range, zstride, or_mask;
+    int32_t nw, hmax, range, zstride;
     double t;
     int32_t w[kMultiMax], h[kMultiMax], k[kMultiMax];
     // MOP_SELECT (MAD): every width's own state (its predicted key window),
@@ -291,23 +293,23 @@ hipError_t launch_parameterise(const ParamArgs &a, hipStream_t s);
 hipError_t launch_reliability(const ParamArgs &a, hipStream_t s);
 
 // ---- launchers (sc_kernels.hip). Each returns the launch's hipError_t.
-hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
-                            int64_t n, hipStream_t s);
+// Blank bits of the cube x (non-finite voxels) and, when mask_in is given,
+// its nonzero voxels as detection bits (det may be null otherwise).
+hipError_t launch_init_bits(const float *x, const uint8_t *mask_in, uint64_t *blank,
+                            uint64_t *det, int64_t ncol, int64_t nz, int64_t wpp,
+                            hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
-// mask[i] |= 1 where wm[i] holds a detection.
-hipError_t launch_or_mask(const uint8_t *wm, uint8_t *mask, int64_t n, hipStream_t s);
-// Packed detection bits of a working mask (detected and not blanked); word
-// w of plane z holds columns 64w .. 64w+63 of that plane, bit b = column
-// 64w + b.
-hipError_t launch_pack_det(const uint8_t *wm, uint64_t *det, int64_t ncol, int64_t nz,
-                           int64_t wpp, hipStream_t s);
+// The caller's mask from detection bits: mask = bit (keep = 0), or
+// mask |= bit (keep = 1).
+hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, int64_t ncol,
+                             int64_t nz, int64_t wpp, hipStream_t s);
 // Spatial cascade of n_iter boxcars of radius r per axis into a.p.
 hipError_t launch_spatial(int n_iter, int radius, int xtype, bool repl,
                           const StripArgs &a, hipStream_t s);
 template <int R, int NIT>
 hipError_t launch_strip(const StripArgs &a, int xtype, bool repl, hipStream_t s);
-hipError_t launch_column(int src, int op, bool spectral, bool has_wm,
-                         const ColArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_column(int src, int op, bool spectral, const ColArgs &a, int nblocks,
+                         hipStream_t s);
 hipError_t launch_finalize_std(DevState *st, const double *part_sum,
                                const unsigned long long *part_cnt, int nparts,
                                int k, double t, int also_sigma0, hipStream_t s);
@@ -326,11 +328,11 @@ hipError_t launch_capture_l1(const DevState *st, const uint32_t *cap_buf,
 hipError_t launch_finalize_predict(DevState *st, const unsigned long long *hist_s,
                                    double t, hipStream_t s);
 // After sigma_k is exact: decide the voxels the fused selection pass left
-// undecided (when st->fused_ok), into the mask and the packed bits.
+// undecided (when st->fused_ok), into the detection bits.
 hipError_t launch_clip_fixup(const DevState *st, const AmbEntry *amb,
                              const unsigned long long *amb_count,
-                             unsigned long long amb_capacity, uint8_t *mask_out, int out_user,
-                             uint64_t *det_bits, int64_t ncol, int64_t wpp, hipStream_t s);
+                             unsigned long long amb_capacity, uint64_t *det_out, int64_t ncol,
+                             int64_t wpp, hipStream_t s);
 hipError_t launch_capture_coarse(const DevState *st, const uint32_t *cap_buf,
                                  const unsigned long long *cap_count,
                                  unsigned long long *hist2c, int blocks,

@@ -40,33 +40,63 @@ __device__ void put_sigma(DevState *st, int k, int also_sigma0, double sig,
 
 // ---------------------------------------------------------- mask / fill
 
-__global__ void k_init_mask(const float *__restrict__ x,
-                            const uint8_t *__restrict__ mask_in,
-                            uint8_t *__restrict__ wm, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += stride) {
-        uint8_t b = isfinite(x[i]) ? 0 : kBlank;
-        if (mask_in && mask_in[i]) b |= kDet;
-        wm[i] = b;
-    }
-}
-
-// One wave per (plane, word): lane l reads column 64w + l of the working
-// mask. A bit is set for detected voxels that are not blanked (a caller's
-// mask may mark blanked voxels; they are never replaced).
-__global__ void k_pack_det(const uint8_t *__restrict__ wm, uint64_t *__restrict__ det,
-                           int64_t ncol, int64_t nz, int64_t wpp) {
+// One wave per (plane, word): lane l tests column 64w + l of the plane. A
+// blank bit marks a non-finite voxel; with a caller's mask a detection bit
+// marks each nonzero byte (blanked voxels included: they stay in the mask
+// and are never replaced, since every loader tests finiteness first).
+__global__ void k_init_bits(const float *__restrict__ x, const uint8_t *__restrict__ mask_in,
+                            uint64_t *__restrict__ blank, uint64_t *__restrict__ det,
+                            int64_t ncol, int64_t nz, int64_t wpp) {
     const int lane = threadIdx.x & 63;
     const int64_t nw = nz * wpp;
     const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nw;
          w += wstride) {
         const int64_t z = w / wpp, col = (w - z * wpp) * 64 + lane;
-        const uint8_t b = col < ncol ? wm[z * ncol + col] : (uint8_t)0;
-        const bool d = (b & kDet) && !(b & kBlank);
-        const uint64_t bits = __ballot(d);
-        if (lane == 0) det[w] = bits;
+        const bool in = col < ncol;
+        const int64_t i = z * ncol + col;
+        const uint64_t bb = __ballot(in && !isfinite(x[in ? i : 0]));
+        if (lane == 0) blank[w] = bb;
+        if (mask_in) {
+            const uint64_t db = __ballot(in && mask_in[in ? i : 0] != 0);
+            if (lane == 0) det[w] = db;
+        }
+    }
+}
+
+// Four threads per word of detection bits, 16 columns each: one 16-byte
+// store (and load, keep = 1) where the 16 bytes are whole and aligned.
+__global__ __launch_bounds__(256) void k_write_mask(const uint64_t *__restrict__ det,
+                                                    uint8_t *__restrict__ mask, int keep,
+                                                    int64_t ncol, int64_t nz, int64_t wpp) {
+    const int64_t nq = nz * wpp * 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += stride) {
+        const int64_t w = t >> 2;
+        const int64_t z = w / wpp;
+        const int64_t c0 = (w - z * wpp) * 64 + 16 * (t & 3);
+        if (c0 >= ncol) continue;
+        const uint32_t bits = (uint32_t)(det[w] >> (16 * (t & 3))) & 0xffffu;
+        uint8_t *m = mask + z * ncol + c0;
+        const int64_t n = ncol - c0 < 16 ? ncol - c0 : 16;
+        if (n == 16 && ((uintptr_t)m & 15) == 0) {
+            // nibble -> four 0/1 bytes
+            auto expand = [](uint32_t q) {
+                return (q & 1u) | ((q & 2u) << 7) | ((q & 4u) << 14) | ((q & 8u) << 21);
+            };
+            uint4 v = make_uint4(expand(bits & 15u), expand((bits >> 4) & 15u),
+                                 expand((bits >> 8) & 15u), expand((bits >> 12) & 15u));
+            if (keep) {
+                const uint4 o = *reinterpret_cast<const uint4 *>(m);
+                v.x |= o.x; v.y |= o.y; v.z |= o.z; v.w |= o.w;
+            }
+            *reinterpret_cast<uint4 *>(m) = v;
+        } else {
+            for (int e = 0; e < (int)n; ++e) {
+                const uint8_t b = (uint8_t)((bits >> e) & 1u);
+                m[e] = keep ? (uint8_t)(m[e] | b) : b;
+            }
+        }
     }
 }
 
@@ -263,8 +293,8 @@ __global__ __launch_bounds__(256) void k_finalize_select(
 // Voxels with thr_lo < |s| <= thr_hi, decided with the exact threshold.
 __global__ void k_clip_fixup(const DevState *st, const AmbEntry *amb,
                              const unsigned long long *amb_count,
-                             unsigned long long amb_capacity, uint8_t *mask_out, int out_user,
-                             uint64_t *det_bits, int64_t ncol, int64_t wpp) {
+                             unsigned long long amb_capacity, uint64_t *det_out, int64_t ncol,
+                             int64_t wpp) {
     if (!st->fused_ok) return;
     const unsigned long long n = *amb_count < amb_capacity ? *amb_count : amb_capacity;
     const double T = st->thr;
@@ -273,12 +303,9 @@ __global__ void k_clip_fixup(const DevState *st, const AmbEntry *amb,
          i < n; i += stride) {
         const AmbEntry e = amb[i];
         if (!(fabs(e.s) > T)) continue;
-        mask_out[e.idx] |= out_user ? (uint8_t)1 : kDet;
-        if (det_bits) {
-            const int64_t z = (int64_t)(e.idx / (uint64_t)ncol);
-            const int64_t col = (int64_t)e.idx - z * ncol;
-            atomicOr((unsigned long long *)&det_bits[z * wpp + (col >> 6)], 1ull << (col & 63));
-        }
+        const int64_t z = (int64_t)(e.idx / (uint64_t)ncol);
+        const int64_t col = (int64_t)e.idx - z * ncol;
+        atomicOr((unsigned long long *)&det_out[z * wpp + (col >> 6)], 1ull << (col & 63));
     }
 }
 
@@ -482,31 +509,21 @@ static int grid_for(int64_t n, int threads, int cap) {
     return (int)g;
 }
 
-// mask[i] |= 1 wherever the working mask holds a detection (keep_input_mask).
-__global__ __launch_bounds__(256) void k_or_mask(const uint8_t *__restrict__ wm,
-                                                 uint8_t *__restrict__ mask, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        if (wm[i] & kDet) mask[i] = (uint8_t)(mask[i] | 1u);
-}
-
-hipError_t launch_or_mask(const uint8_t *wm, uint8_t *mask, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_or_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, wm, mask, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_init_mask(const float *x, const uint8_t *mask_in, uint8_t *wm,
-                            int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
-                       x, mask_in, wm, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack_det(const uint8_t *wm, uint64_t *det, int64_t ncol, int64_t nz,
-                           int64_t wpp, hipStream_t s) {
+hipError_t launch_init_bits(const float *x, const uint8_t *mask_in, uint64_t *blank,
+                            uint64_t *det, int64_t ncol, int64_t nz, int64_t wpp,
+                            hipStream_t s) {
     const int64_t waves = nz * wpp;
     const int blocks = (int)(waves / 4 + 1 < 65536 ? waves / 4 + 1 : 65536);
-    hipLaunchKernelGGL(k_pack_det, dim3(blocks), dim3(256), 0, s, wm, det, ncol, nz, wpp);
+    hipLaunchKernelGGL(k_init_bits, dim3(blocks), dim3(256), 0, s, x, mask_in, blank, det,
+                       ncol, nz, wpp);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, int64_t ncol,
+                             int64_t nz, int64_t wpp, hipStream_t s) {
+    const int64_t n = nz * wpp * 4;
+    hipLaunchKernelGGL(k_write_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, det, mask,
+                       keep, ncol, nz, wpp);
     return hipGetLastError();
 }
 
@@ -588,19 +605,18 @@ hipError_t launch_gauss(int radius, int xtype, bool repl, const GaussArgs &a, hi
 }
 
 template <int OP>
-hipError_t launch_column_op(int src, bool spec, bool has_wm, const ColArgs &a, int nb,
-                            hipStream_t s);
+hipError_t launch_column_op(int src, bool spec, const ColArgs &a, int nb, hipStream_t s);
 
-hipError_t launch_column(int src, int op, bool spectral, bool has_wm,
-                         const ColArgs &a, int nblocks, hipStream_t s) {
+hipError_t launch_column(int src, int op, bool spectral, const ColArgs &a, int nblocks,
+                         hipStream_t s) {
     switch (op) {
-        case OP_STD: return launch_column_op<OP_STD>(src, spectral, has_wm, a, nblocks, s);
-        case OP_HIST1: return launch_column_op<OP_HIST1>(src, spectral, has_wm, a, nblocks, s);
-        case OP_HIST2: return launch_column_op<OP_HIST2>(src, spectral, has_wm, a, nblocks, s);
-        case OP_CLIP: return launch_column_op<OP_CLIP>(src, spectral, has_wm, a, nblocks, s);
-        case OP_WRITE: return launch_column_op<OP_WRITE>(src, spectral, has_wm, a, nblocks, s);
-        case OP_SELECT: return launch_column_op<OP_SELECT>(src, spectral, has_wm, a, nblocks, s);
-        case OP_SELCLIP: return launch_column_op<OP_SELCLIP>(src, spectral, has_wm, a, nblocks, s);
+        case OP_STD: return launch_column_op<OP_STD>(src, spectral, a, nblocks, s);
+        case OP_HIST1: return launch_column_op<OP_HIST1>(src, spectral, a, nblocks, s);
+        case OP_HIST2: return launch_column_op<OP_HIST2>(src, spectral, a, nblocks, s);
+        case OP_CLIP: return launch_column_op<OP_CLIP>(src, spectral, a, nblocks, s);
+        case OP_WRITE: return launch_column_op<OP_WRITE>(src, spectral, a, nblocks, s);
+        case OP_SELECT: return launch_column_op<OP_SELECT>(src, spectral, a, nblocks, s);
+        case OP_SELCLIP: return launch_column_op<OP_SELCLIP>(src, spectral, a, nblocks, s);
     }
     return hipErrorInvalidValue;
 }
@@ -631,10 +647,10 @@ hipError_t launch_finalize_select(DevState *st, const unsigned long long *sel_pa
 
 hipError_t launch_clip_fixup(const DevState *st, const AmbEntry *amb,
                              const unsigned long long *amb_count,
-                             unsigned long long amb_capacity, uint8_t *mask_out, int out_user,
-                             uint64_t *det_bits, int64_t ncol, int64_t wpp, hipStream_t s) {
+                             unsigned long long amb_capacity, uint64_t *det_out, int64_t ncol,
+                             int64_t wpp, hipStream_t s) {
     hipLaunchKernelGGL(k_clip_fixup, dim3(512), dim3(256), 0, s, st, amb, amb_count,
-                       amb_capacity, mask_out, out_user, det_bits, ncol, wpp);
+                       amb_capacity, det_out, ncol, wpp);
     return hipGetLastError();
 }
 

@@ -9,8 +9,9 @@
 //  * k_multi_finalize: sigma of every width from the per-block partials in a
 //    fixed order;
 //  * k_multi<SRC, CLIP>: the same stream, every voxel detected when any
-//    width's |s| exceeds t sigma of that width, written (or ORed) into the
-//    caller's mask.
+//    width's |s| exceeds t sigma of that width, ORed into the run's packed
+//    detection bits (one word per wave and plane, read and written by the
+//    same wave, so the bits may be updated in place).
 // Every width's running sum is an FP64 sum of the same float inputs as the
 // per-pair column pass, re-anchored from the ring every 32 planes; the
 // windows of all widths are centred on the same output plane.
@@ -30,6 +31,10 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
     const int64_t ncol = a.ncol;
     const int64_t col0 = (int64_t)cb * B;
     const bool active = col0 + tid < ncol;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int64_t wcol = (col0 >> 6) + wave;      // the wave's word of each bit plane
+    const bool live = col0 + 64 * wave < ncol;    // the wave has a column in the plane
     const int nz = (int)a.nz;
     const int z0 = zc * a.zchunk;
     const int z1 = min(nz, z0 + a.zchunk);
@@ -89,26 +94,30 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
     const int zs = z0 - hm, ze = z1 + hm;
     constexpr int G = 8;
     float cur[G], nxt[G];
-    uint8_t bcur[G], bnxt[G];   // SRC_P: working-mask byte of the output plane
-    auto load_group = [&](int zb, float *v, uint8_t *bb) {
+    // packed bits of the group's output planes: lane j holds the wave's word
+    // of output plane j (blank bits for SRC_P; detection bits so far, CLIP)
+    uint64_t bcur = 0, bnxt = 0, dcur = 0, dnxt = 0;
+    auto load_group = [&](int zb, float *v, uint64_t &bw, uint64_t &dw) {
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const int zi = zb + j;
             v[j] = 0.f;
-            bb[j] = 0;
             if (active && zi < ze && zi >= 0 && zi < nz)
                 v[j] = buf_f32(plane_rsrc(a.src + (int64_t)zi * ncol + col0), 4u * (uint32_t)tid, 0u);
-            if (SRC == SRC_P) {
-                const int zo = zi - hm;
-                if (active && zi < ze && zo >= z0)
-                    bb[j] = buf_u8(plane_rsrc(a.wm + (int64_t)zo * ncol + col0), (uint32_t)tid, 0u);
-            }
+        }
+        bw = 0;
+        dw = 0;
+        const int zo = zb + lane - hm;
+        if (lane < G && zb + lane < ze && zo >= z0) {
+            const int64_t wi = (int64_t)zo * a.wpp + wcol;
+            if (SRC == SRC_P) bw = a.blank[wi];
+            if (MOP == MOP_CLIP && a.det_in) dw = a.det_in[wi];
         }
     };
     int steps = 0;
-    load_group(zs, cur, bcur);
-    for (int zb = zs; zb < ze; zb += G) {
-        if (zb + G < ze) load_group(zb + G, nxt, bnxt);
+    if (live) load_group(zs, cur, bcur, dcur);
+    for (int zb = zs; live && zb < ze; zb += G) {
+        if (zb + G < ze) load_group(zb + G, nxt, bnxt, dnxt);
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const int zi = zb + j;
@@ -132,8 +141,8 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
                     S[i] += (double)fin(back(hm - hw[i])) - (double)fin(back(hm + hw[i] + 1));
             }
             // columns past the plane's end take no part
-            const bool blank = !active || (SRC == SRC_X ? !isfinite(back(hm))
-                                                      : (bcur[j] & kBlank) != 0);
+            const bool blank = !active | (SRC == SRC_X ? !isfinite(back(hm))
+                                                     : lane_bit(lane_word(bcur, j)));
             const bool zsel = a.zstride <= 1 || zo % a.zstride == 0;
             if (MOP == MOP_STATS) {
 #pragma unroll
@@ -152,7 +161,7 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
                     cnt[i] += sel ? 1u : 0u;
                     nbelow[i] += (sel & (key < klo[i])) ? 1u : 0u;
                     const bool want = sel & (key >= klo[i]) & (key <= khi[i]);
-                    const unsigned long long bal = __ballot(want);
+                    const uint64_t bal = wave_mask(want);
                     if (bal) {
                         if (want) {
                             const int below = (int)__builtin_amdgcn_mbcnt_hi(
@@ -169,16 +178,14 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
 #pragma unroll
                 for (int i = 0; i < NW; ++i)
                     det |= !blank & (fabs(S[i] * inv_w[i]) > T[i]);
-                if (active) {
-                    const __amdgpu_buffer_rsrc_t mr = plane_rsrc(a.mask + (int64_t)zo * ncol + col0);
-                    uint8_t out = det ? 1 : 0;
-                    if (a.or_mask) out |= buf_u8(mr, (uint32_t)tid, 0u);
-                    buf_st_u8(out, mr, (uint32_t)tid, 0u);
-                }
+                const uint64_t bits = wave_mask(det) | lane_word(dcur, j);
+                if (lane == 0) a.det_out[(int64_t)zo * a.wpp + wcol] = bits;
             }
         }
 #pragma unroll
-        for (int j = 0; j < G; ++j) { cur[j] = nxt[j]; bcur[j] = bnxt[j]; }
+        for (int j = 0; j < G; ++j) cur[j] = nxt[j];
+        bcur = bnxt;
+        dcur = dnxt;
     }
 
     if (MOP == MOP_SELECT) {
@@ -272,6 +279,7 @@ hipError_t launch_multi_t(const MultiArgs &a, int nblocks, size_t lds, hipStream
 }
 
 hipError_t launch_multi(int src, int mop, const MultiArgs &a, int nblocks, hipStream_t s) {
+    if ((src == SRC_P && !a.blank) || (mop == MOP_CLIP && !a.det_out)) return hipErrorInvalidValue;
     size_t lds = (size_t)(2 * a.hmax + 2) * kColThreads * sizeof(float);
     if (mop == MOP_SELECT)
         lds += (size_t)(kColThreads / 64) * a.nw * kMultiStage * sizeof(uint32_t);

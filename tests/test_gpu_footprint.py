@@ -1,7 +1,7 @@
 """Device memory a handle takes for a run, against the workspace the design
-budgets: working masks 2N, P 4N (spatial kernels only), packed detection bits
-N/8 (spatial kernels only), MAD capture list N/8 keys x 4 B, undecided list
-N/256 x 16 B, plus a few MB of histograms, partials and state."""
+budgets: three packed bit planes (blank bits and two sets of detection bits)
+3N/8, P 4N (spatial kernels only), MAD capture list N/8 keys x 4 B, undecided
+list N/256 x 16 B, plus a few MB of histograms, partials and state."""
 import numpy as np
 import pytest
 
@@ -21,8 +21,8 @@ def _free():
 
 
 @pytest.mark.parametrize("kernels,per_voxel", [
-    ([(0.0, 0), (3.0, 7), (6.0, 15)], 2 + 4 + 1 / 8 + 4 / 8 + 16 / 256),
-    ([(0.0, 0), (0.0, 7), (0.0, 15)], 2 + 4 / 8 + 16 / 256),
+    ([(0.0, 0), (3.0, 7), (6.0, 15)], 3 / 8 + 4 + 4 / 8 + 16 / 256),
+    ([(0.0, 0), (0.0, 7), (0.0, 15)], 3 / 8 + 4 / 8 + 16 / 256),
 ])
 def test_run_workspace_within_budget(kernels, per_voxel):
     spec = synth.CubeSpec(256, 256, 128, seed=81, n_gal=3)
