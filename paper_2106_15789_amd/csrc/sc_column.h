@@ -266,16 +266,37 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     };
     const int zs = SPEC ? z0 - h : z0;
     const int ze = SPEC ? z1 + h : z1;   // exclusive
+    // Lanes past the plane's end load their block's first column (in bounds;
+    // they count as blanked).
+    constexpr uint32_t XB = Q16 ? 2u : 4u;
+    const uint32_t vo = (uint32_t)(active ? tid : 0) * XB;
+    // A group whose planes are all inside the stream and the cube loads them
+    // through one buffer descriptor with per-plane scalar offsets, when the
+    // group's span fits the 32-bit offsets.
+    const int zhi = min(ze, nz);
+    const bool one_rsrc = (int64_t)(G - 1) * ncol * XB + (int64_t)B * XB < (1ll << 32);
+    const uint32_t pbytes = (uint32_t)(ncol * XB);
     auto load_group = [&](int zb, Group &g) {
-        int64_t off = (int64_t)zb * ncol + col0;   // running: plane zb + j
+        const int64_t off0 = (int64_t)zb * ncol + col0;
+        if (one_rsrc && zb >= 0 && zb + G <= zhi) {
+            const __amdgpu_buffer_rsrc_t r =
+                plane_rsrc(Q16 ? (const void *)(a.xq + off0) : (const void *)(src + off0));
 #pragma unroll
-        for (int j = 0; j < G; ++j, off += ncol) {
-            const int zi = zb + j;
-            g.v[j] = 0.f;
-            g.q[j] = 0;
-            if (active && zi < ze && zi >= 0 && zi < nz) {
-                if (Q16) g.q[j] = buf_u16(plane_rsrc(a.xq + off), 2u * (uint32_t)tid, 0u);
-                else g.v[j] = buf_f32(plane_rsrc(src + off), 4u * (uint32_t)tid, 0u);
+            for (int j = 0; j < G; ++j) {
+                if (Q16) g.q[j] = buf_u16(r, vo, (uint32_t)j * pbytes);
+                else g.v[j] = buf_f32(r, vo, (uint32_t)j * pbytes);
+            }
+        } else {
+            int64_t off = off0;   // running: plane zb + j
+#pragma unroll
+            for (int j = 0; j < G; ++j, off += ncol) {
+                const int zi = zb + j;
+                g.v[j] = 0.f;
+                g.q[j] = 0;
+                if (zi < ze && zi >= 0 && zi < nz) {
+                    if (Q16) g.q[j] = buf_u16(plane_rsrc(a.xq + off), vo, 0u);
+                    else g.v[j] = buf_f32(plane_rsrc(src + off), vo, 0u);
+                }
             }
         }
         g.dw = 0;

@@ -97,13 +97,26 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
     // packed bits of the group's output planes: lane j holds the wave's word
     // of output plane j (blank bits for SRC_P; detection bits so far, CLIP)
     uint64_t bcur = 0, bnxt = 0, dcur = 0, dnxt = 0;
+    // lanes past the plane's end load their block's first column (in bounds;
+    // they count as blanked); a group inside the stream and the cube loads
+    // its planes through one buffer descriptor with per-plane scalar offsets
+    const uint32_t vo = (uint32_t)(active ? tid : 0) * 4u;
+    const int zhi = min(ze, nz);
+    const bool one_rsrc = (int64_t)(G - 1) * ncol * 4 + (int64_t)B * 4 < (1ll << 32);
+    const uint32_t pbytes = (uint32_t)(ncol * 4);
     auto load_group = [&](int zb, float *v, uint64_t &bw, uint64_t &dw) {
+        if (one_rsrc && zb >= 0 && zb + G <= zhi) {
+            const __amdgpu_buffer_rsrc_t r = plane_rsrc(a.src + (int64_t)zb * ncol + col0);
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            const int zi = zb + j;
-            v[j] = 0.f;
-            if (active && zi < ze && zi >= 0 && zi < nz)
-                v[j] = buf_f32(plane_rsrc(a.src + (int64_t)zi * ncol + col0), 4u * (uint32_t)tid, 0u);
+            for (int j = 0; j < G; ++j) v[j] = buf_f32(r, vo, (uint32_t)j * pbytes);
+        } else {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int zi = zb + j;
+                v[j] = 0.f;
+                if (zi < ze && zi >= 0 && zi < nz)
+                    v[j] = buf_f32(plane_rsrc(a.src + (int64_t)zi * ncol + col0), vo, 0u);
+            }
         }
         bw = 0;
         dw = 0;
