@@ -954,8 +954,8 @@ int enqueue_run(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
     // the caller's 0/1 mask from the final detection bits (ORed into it when
     // the caller's mask is kept)
     return launch(h, s, F_MASK_OUT, 0.125 * d.N + (r.keep ? 2.0 : 1.0) * d.N, (double)d.N,
-                  [&] { return launch_write_mask(din, r.mask, r.keep ? 1 : 0, d.ncol, d.nz,
-                                                 wpp, s); });
+                  [&] { return launch_write_mask(din, r.mask, r.keep ? 1 : 0, nullptr, d.ncol,
+                                                 d.nz, wpp, s); });
 }
 
 // MAD noise of the widths of one fused chunk: per width its own state,
@@ -1187,7 +1187,8 @@ int enqueue_fused(sofia_sc *h, hipStream_t s, const Work &w, const RunSpec &r) {
         }
     }
     return launch(h, s, F_MASK_OUT, 0.125 * N + (r.keep ? 2.0 : 1.0) * N, N, [&] {
-        return launch_write_mask(w.det[0], r.mask, r.keep ? 1 : 0, d.ncol, d.nz, wpp, s);
+        return launch_write_mask(w.det[0], r.mask, r.keep ? 1 : 0, nullptr, d.ncol, d.nz, wpp,
+                                 s);
     });
 }
 
@@ -2166,8 +2167,10 @@ static int single_kernel(sofia_sc *h, const float *cube, int64_t nx, int64_t ny,
     j.zstride = zstride;
     if ((rc = run_pair(h, s, w, j))) return rc;
     if (!write_out) {
-        rc = launch(h, s, F_MASK_OUT, 1.125 * d.N, (double)d.N, [&] {
-            return launch_write_mask(w.det[1], mask_out, 0, d.ncol, d.nz, wpp, s);
+        // the caller's marks on blanked voxels (never detection bits) stay in
+        // the output mask
+        rc = launch(h, s, F_MASK_OUT, (mask_in ? 2.125 : 1.125) * d.N, (double)d.N, [&] {
+            return launch_write_mask(w.det[1], mask_out, 0, mask_in, d.ncol, d.nz, wpp, s);
         });
         if (rc) return rc;
     }

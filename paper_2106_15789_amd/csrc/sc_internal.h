@@ -294,15 +294,16 @@ hipError_t launch_reliability(const ParamArgs &a, hipStream_t s);
 
 // ---- launchers (sc_kernels.hip). Each returns the launch's hipError_t.
 // Blank bits of the cube x (non-finite voxels) and, when mask_in is given,
-// its nonzero voxels as detection bits (det may be null otherwise).
+// its nonzero finite voxels as detection bits (det may be null otherwise).
 hipError_t launch_init_bits(const float *x, const uint8_t *mask_in, uint64_t *blank,
                             uint64_t *det, int64_t ncol, int64_t nz, int64_t wpp,
                             hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, hipStream_t s);
-// The caller's mask from detection bits: mask = bit (keep = 0), or
-// mask |= bit (keep = 1).
-hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, int64_t ncol,
-                             int64_t nz, int64_t wpp, hipStream_t s);
+// The caller's mask from detection bits: mask = bit (keep = 0), mask |= bit
+// (keep = 1), or, with a source mask src (not aliasing mask), mask = bit |
+// (src != 0).
+hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, const uint8_t *src,
+                             int64_t ncol, int64_t nz, int64_t wpp, hipStream_t s);
 // Spatial cascade of n_iter boxcars of radius r per axis into a.p.
 hipError_t launch_spatial(int n_iter, int radius, int xtype, bool repl,
                           const StripArgs &a, hipStream_t s);

@@ -42,8 +42,9 @@ __device__ void put_sigma(DevState *st, int k, int also_sigma0, double sig,
 
 // One wave per (plane, word): lane l tests column 64w + l of the plane. A
 // blank bit marks a non-finite voxel; with a caller's mask a detection bit
-// marks each nonzero byte (blanked voxels included: they stay in the mask
-// and are never replaced, since every loader tests finiteness first).
+// marks each nonzero byte of a finite voxel (the loaders replace every
+// detected voxel; a caller's marks on blanked voxels reach the output mask
+// through k_write_mask's source mask instead).
 __global__ void k_init_bits(const float *__restrict__ x, const uint8_t *__restrict__ mask_in,
                             uint64_t *__restrict__ blank, uint64_t *__restrict__ det,
                             int64_t ncol, int64_t nz, int64_t wpp) {
@@ -58,16 +59,20 @@ __global__ void k_init_bits(const float *__restrict__ x, const uint8_t *__restri
         const uint64_t bb = __ballot(in && !isfinite(x[in ? i : 0]));
         if (lane == 0) blank[w] = bb;
         if (mask_in) {
-            const uint64_t db = __ballot(in && mask_in[in ? i : 0] != 0);
+            const uint64_t db =
+                __ballot(in && mask_in[in ? i : 0] != 0 && isfinite(x[in ? i : 0]));
             if (lane == 0) det[w] = db;
         }
     }
 }
 
 // Four threads per word of detection bits, 16 columns each: one 16-byte
-// store (and load, keep = 1) where the 16 bytes are whole and aligned.
+// store (and load, keep = 1 or a source mask) where the 16 bytes are whole
+// and aligned. mask = bit (keep = 0), mask |= bit (keep = 1), or, with a
+// source mask src, mask = bit | (src != 0).
 __global__ __launch_bounds__(256) void k_write_mask(const uint64_t *__restrict__ det,
                                                     uint8_t *__restrict__ mask, int keep,
+                                                    const uint8_t *__restrict__ src,
                                                     int64_t ncol, int64_t nz, int64_t wpp) {
     const int64_t nq = nz * wpp * 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -90,10 +95,17 @@ __global__ __launch_bounds__(256) void k_write_mask(const uint64_t *__restrict__
                 const uint4 o = *reinterpret_cast<const uint4 *>(m);
                 v.x |= o.x; v.y |= o.y; v.z |= o.z; v.w |= o.w;
             }
+            if (src) {
+                const uint8_t *sm = src + z * ncol + c0;
+                for (int e = 0; e < 16; ++e)
+                    if (sm[e]) reinterpret_cast<uint8_t *>(&v)[e] = 1;
+            }
             *reinterpret_cast<uint4 *>(m) = v;
         } else {
+            const uint8_t *sm = src ? src + z * ncol + c0 : nullptr;
             for (int e = 0; e < (int)n; ++e) {
-                const uint8_t b = (uint8_t)((bits >> e) & 1u);
+                uint8_t b = (uint8_t)((bits >> e) & 1u);
+                if (sm && sm[e]) b = 1;
                 m[e] = keep ? (uint8_t)(m[e] | b) : b;
             }
         }
@@ -519,11 +531,11 @@ hipError_t launch_init_bits(const float *x, const uint8_t *mask_in, uint64_t *bl
     return hipGetLastError();
 }
 
-hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, int64_t ncol,
-                             int64_t nz, int64_t wpp, hipStream_t s) {
+hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, const uint8_t *src,
+                             int64_t ncol, int64_t nz, int64_t wpp, hipStream_t s) {
     const int64_t n = nz * wpp * 4;
     hipLaunchKernelGGL(k_write_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, det, mask,
-                       keep, ncol, nz, wpp);
+                       keep, src, ncol, nz, wpp);
     return hipGetLastError();
 }
 

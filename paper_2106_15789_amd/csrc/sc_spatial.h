@@ -228,17 +228,16 @@ __global__ __launch_bounds__(64 * kStripWaves) void k_strip(StripArgs a) {
             const int yi = y_first + base + j;      // input row of this step
             const float vx = xs[buf][j][lx], vy = xs[buf][j][lx + 1];
 
-            // pass-0 values: zero at blanked voxels (even where a caller's
-            // mask marks them), +-n sigma_0 (sign of the datum) at detected
-            // finite ones, zero outside the cube
-            const bool f0 = isfinite(vx), f1 = isfinite(vy);
-            float c0 = f0 ? vx : 0.f, c1 = f1 ? vy : 0.f;
+            // pass-0 values: zero at blanked voxels, +-n sigma_0 (sign of the
+            // datum) at detected ones (the packed bits mark only finite
+            // voxels), zero outside the cube
+            float c0 = isfinite(vx) ? vx : 0.f, c1 = isfinite(vy) ? vy : 0.f;
             if (RP) {
                 const uint32_t t0 = (uint32_t)(row_bit0(clamp_row(yi)) & 31) + (uint32_t)lx;
                 const uint32_t *wr = &dws[buf][j][t0 >> 5];
                 const uint32_t bits = __builtin_amdgcn_alignbit(wr[1], wr[0], t0 & 31);
-                if ((bits & 1u) && f0) c0 = copysignf(rv, vx);
-                if ((bits & 2u) && f1) c1 = copysignf(rv, vy);
+                if (bits & 1u) c0 = copysignf(rv, vx);
+                if (bits & 2u) c1 = copysignf(rv, vy);
             }
             if (EDGE) {
                 const bool yin = yi >= 0 && yi < ny;   // uniform
