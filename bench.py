@@ -14,8 +14,9 @@ slab straight into HBM.
 
 Other workloads: plain_1024cube (1024^3, 12 kernels), batch96 (96 uneven
 cubes in one graph launch, --batch-mode loop for one run call per cube),
-paper_360x360x1464; --storage f16/bf16 stores the cube noise-scaled in 16
-bits inside each run.
+paper_360x360x1464 and paper_1501cube (the shapes of the paper's two speed
+tests); --storage f16/bf16 stores the cube noise-scaled in 16 bits inside
+each run.
 
 Unless --no-extras is given, the line also carries, measured in the same
 process after the headline: the large cube with FP16 storage as a one-cube

@@ -66,25 +66,32 @@ __global__ void k_init_bits(const float *__restrict__ x, const uint8_t *__restri
     }
 }
 
-// Four threads per word of detection bits, 16 columns each: one 16-byte
-// store (and load, keep = 1 or a source mask) where the 16 bytes are whole
-// and aligned. mask = bit (keep = 0), mask |= bit (keep = 1), or, with a
+// Thread t writes bytes 16t .. 16t+15 of the caller's mask (16-byte stores
+// whenever the mask itself is 16-byte aligned, whatever the plane size):
+// their 16 bits come from one or two words of the plane's detection bits;
+// only the few runs that cross a plane boundary (or the cube's end) go
+// byte by byte. mask = bit (keep = 0), mask |= bit (keep = 1), or, with a
 // source mask src, mask = bit | (src != 0).
 __global__ __launch_bounds__(256) void k_write_mask(const uint64_t *__restrict__ det,
                                                     uint8_t *__restrict__ mask, int keep,
                                                     const uint8_t *__restrict__ src,
                                                     int64_t ncol, int64_t nz, int64_t wpp) {
-    const int64_t nq = nz * wpp * 4;
+    const int64_t n = nz * ncol;
+    const int64_t nt = (n + 15) / 16;
+    const bool aligned = ((uintptr_t)mask & 15) == 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += stride) {
-        const int64_t w = t >> 2;
-        const int64_t z = w / wpp;
-        const int64_t c0 = (w - z * wpp) * 64 + 16 * (t & 3);
-        if (c0 >= ncol) continue;
-        const uint32_t bits = (uint32_t)(det[w] >> (16 * (t & 3))) & 0xffffu;
-        uint8_t *m = mask + z * ncol + c0;
-        const int64_t n = ncol - c0 < 16 ? ncol - c0 : 16;
-        if (n == 16 && ((uintptr_t)m & 15) == 0) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
+        const int64_t i0 = 16 * t;
+        int64_t z = i0 / ncol, c = i0 - z * ncol;
+        uint8_t *m = mask + i0;
+        const uint8_t *sm = src ? src + i0 : nullptr;
+        if (aligned && c + 16 <= ncol) {
+            const uint64_t *dz = det + z * wpp;
+            const int64_t w = c >> 6;
+            const uint32_t sh = (uint32_t)(c & 63);
+            uint64_t b = dz[w] >> sh;
+            if (sh > 48) b |= dz[w + 1] << (64 - sh);
+            const uint32_t bits = (uint32_t)b & 0xffffu;
             // nibble -> four 0/1 bytes
             auto expand = [](uint32_t q) {
                 return (q & 1u) | ((q & 2u) << 7) | ((q & 4u) << 14) | ((q & 8u) << 21);
@@ -95,18 +102,18 @@ __global__ __launch_bounds__(256) void k_write_mask(const uint64_t *__restrict__
                 const uint4 o = *reinterpret_cast<const uint4 *>(m);
                 v.x |= o.x; v.y |= o.y; v.z |= o.z; v.w |= o.w;
             }
-            if (src) {
-                const uint8_t *sm = src + z * ncol + c0;
+            if (sm) {
                 for (int e = 0; e < 16; ++e)
                     if (sm[e]) reinterpret_cast<uint8_t *>(&v)[e] = 1;
             }
             *reinterpret_cast<uint4 *>(m) = v;
         } else {
-            const uint8_t *sm = src ? src + z * ncol + c0 : nullptr;
-            for (int e = 0; e < (int)n; ++e) {
-                uint8_t b = (uint8_t)((bits >> e) & 1u);
+            const int ne = (int)(n - i0 < 16 ? n - i0 : 16);
+            for (int e = 0; e < ne; ++e) {
+                uint8_t b = (uint8_t)((det[z * wpp + (c >> 6)] >> (c & 63)) & 1u);
                 if (sm && sm[e]) b = 1;
                 m[e] = keep ? (uint8_t)(m[e] | b) : b;
+                if (++c == ncol) { c = 0; ++z; }
             }
         }
     }
@@ -533,7 +540,7 @@ hipError_t launch_init_bits(const float *x, const uint8_t *mask_in, uint64_t *bl
 
 hipError_t launch_write_mask(const uint64_t *det, uint8_t *mask, int keep, const uint8_t *src,
                              int64_t ncol, int64_t nz, int64_t wpp, hipStream_t s) {
-    const int64_t n = nz * wpp * 4;
+    const int64_t n = (nz * ncol + 15) / 16;
     hipLaunchKernelGGL(k_write_mask, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, det, mask,
                        keep, src, ncol, nz, wpp);
     return hipGetLastError();

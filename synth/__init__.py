@@ -217,6 +217,13 @@ def workload(name: str) -> Workload:
             name, [CubeSpec(360, 360, 1464, seed=7, n_gal=40)],
             _pairs([0, 5, 10], [0, 3, 7, 15]), 3.5, "mad", "negative",
             notes="shape and kernels of the paper's laptop speed test (Sect. 5)")
+    if name == "paper_1501cube":
+        # 1501^3 float32 (12.6 GiB), i.i.d. noise of sigma 1 (the paper scales
+        # its mock cube's noise to 1) and mock galaxies at the 1024^3 density.
+        return Workload(
+            name, [CubeSpec(1501, 1501, 1501, seed=8, n_gal=6300)],
+            _pairs([0, 5, 10], [0, 3, 7, 15]), 3.5, "mad", "negative",
+            notes="shape of the paper's 12.6 GB cube (Sects. 5 and 6)")
     raise KeyError(name)
 
 
