@@ -20,8 +20,9 @@ each run.
 
 Unless --no-extras is given, the line also carries, measured in the same
 process after the headline: the large cube with FP16 storage as a one-cube
-graph launch, the 1024^3 workload in FP32, the local noise normalisation of
-that cube (31 px / 31 ch window) and the linker on its S+C mask.
+graph launch, the 1024^3 workload in FP32 (also as a one-cube graph launch),
+the local noise normalisation of that cube (31 px / 31 ch window) and the
+linker on its S+C mask.
 
 Prints one JSON line. `value` is voxels per second of whole runs; `roofline`
 describes the kernel family with the largest share of device time, timed with
@@ -258,6 +259,12 @@ def extras(sc, torch, synth, stream, large_x=None, large_wl=None):
             "whole_step_hbm_frac": alg / (dt / 10) / 1e9 / HBM_PEAK_GBS,
             "kernel_gbs": family_gbs(stats), "mask_voxels": count_set(m, torch)}
         say(f"1024^3 f32: {dt * 100:.1f} ms/step")
+        # the same run as a one-cube graph launch (no launch gaps)
+        dt, noise, s0, stats = time_runs(h, wl, [x], [m], 10, 2, "f32", True, stream, torch)
+        out["plain_1024cube_graph"] = {
+            "ms_per_step": dt * 100, "value": x.numel() * 10 / dt, "unit": "voxels/s",
+            "batch_mode": "graph"}
+        say(f"1024^3 f32, one-cube graph: {dt * 100:.1f} ms/step")
         # the same run with the sampled-Gaussian spatial kernel (variant G1)
         wlg = dataclasses.replace(wl, name=wl.name + "_gauss", kernels=[
             (f, w, "gauss") if f > 0 else (f, w) for f, w in wl.kernels])
