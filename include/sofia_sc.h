@@ -369,9 +369,11 @@ int sofia_sc_normalise_grid(int64_t nx, int64_t ny, int64_t nz, int32_t window_x
  *  boxes       host, int64 [box_capacity][7] or NULL: per kept detection in
  *              label order x_min, x_max, y_min, y_max, z_min, z_max, voxel
  *              count (the first box_capacity of them).
- * Returns after the work has completed. EINVAL for NULL pointers, bad
- * dimensions, nx*ny*nz >= 2^31, radii outside 0..SOFIA_SC_LINK_MAX_RADIUS or
- * negative sizes. */
+ * The handle's workspace holds the list of the detected voxels (4 bytes
+ * each) and per detection 36 bytes. Returns after the work has completed.
+ * EINVAL for NULL pointers, bad dimensions, nx*ny*nz >= 2^31, radii outside
+ * 0..SOFIA_SC_LINK_MAX_RADIUS or negative sizes; ENOMEM when the workspace
+ * cannot grow. */
 #define SOFIA_SC_LINK_MAX_RADIUS 4
 int sofia_sc_link(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t nz,
                   int32_t radius_xy, int32_t radius_z, int32_t min_size_xy, int32_t min_size_z,

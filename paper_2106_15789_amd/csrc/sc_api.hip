@@ -158,6 +158,8 @@ struct sofia_sc {
     // linker workspace: block counts, per-detection boxes and labels, output boxes
     int *lk_counts = nullptr;
     size_t lk_counts_cap = 0;
+    int *lk_list = nullptr;          // the detected voxels of a linked mask
+    size_t lk_list_cap = 0;
     int *lk_box = nullptr;
     size_t lk_box_cap = 0;
     int *lk_label = nullptr;
@@ -1662,17 +1664,37 @@ int link_impl(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t 
     const int64_t nb = link_scan_blocks(N);
     if ((rc = grow(h, h->lk_counts, h->lk_counts_cap, (size_t)nb + 1, "link counts", nullptr)))
         return rc;
-    rc = launch(h, s, F_LINK_UNION, 5.0 * Nd, Nd, [&] { return launch_link_init(mask, labels, N, s); });
-    if (!rc) rc = launch(h, s, F_LINK_UNION, Nd, Nd, [&] { return launch_link_union(a, s); });
-    if (!rc) rc = launch(h, s, F_LINK_UNION, 4.0 * Nd, Nd, [&] { return launch_link_flatten(labels, N, s); });
-    if (!rc) rc = launch(h, s, F_LINK_NUMBER, 4.0 * Nd, Nd, [&] {
-        return launch_link_number(true, a, N, h->lk_counts, s);
+    // the list of the detected voxels in raster order, and the forest
+    rc = launch(h, s, F_LINK_NUMBER, Nd, Nd, [&] {
+        return launch_link_number(LK_VOXELS, a, N, h->lk_counts, s);
     });
     if (rc) return rc;
-    int nc = 0;
-    hipError_t e = hipMemcpyAsync(&nc, h->lk_counts + nb, sizeof(int), hipMemcpyDeviceToHost, s);
+    int m = 0;
+    hipError_t e = hipMemcpyAsync(&m, h->lk_counts + nb, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "count of detections");
+    if (e != hipSuccess) return hip_fail(h, e, "count of detected voxels");
+    int nc = 0;
+    if (m > 0) {
+        if ((rc = grow(h, h->lk_list, h->lk_list_cap, (size_t)m, "link list", nullptr)))
+            return rc;
+        a.list = h->lk_list;
+        a.m = m;
+        const double Md = (double)m;
+        const int64_t nbm = link_scan_blocks(m);   // <= nb: lk_counts holds its counts
+        rc = launch(h, s, F_LINK_NUMBER, Nd + 4.0 * Md, Nd, [&] {
+            return launch_link_assign(LK_VOXELS, a, N, h->lk_counts, s);
+        });
+        if (!rc) rc = launch(h, s, F_LINK_UNION, 8.0 * Md, Md, [&] { return launch_link_init(a, s); });
+        if (!rc) rc = launch(h, s, F_LINK_UNION, 12.0 * Md, Md, [&] { return launch_link_union(a, s); });
+        if (!rc) rc = launch(h, s, F_LINK_UNION, 12.0 * Md, Md, [&] { return launch_link_flatten(a, s); });
+        if (!rc) rc = launch(h, s, F_LINK_NUMBER, 8.0 * Md, Md, [&] {
+            return launch_link_number(LK_ROOTS, a, m, h->lk_counts, s);
+        });
+        if (rc) return rc;
+        e = hipMemcpyAsync(&nc, h->lk_counts + nbm, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "count of detections");
+    }
     int n_kept = 0;
     if (nc > 0) {
         const int64_t nbc = link_scan_blocks(nc);
@@ -1683,24 +1705,25 @@ int link_impl(sofia_sc *h, const uint8_t *mask, int64_t nx, int64_t ny, int64_t 
             return rc;
         a.box = h->lk_box;
         a.label_of = h->lk_label;
-        rc = launch(h, s, F_LINK_NUMBER, 4.0 * Nd, Nd, [&] {
-            return launch_link_assign(true, a, N, h->lk_counts, s);
+        const double Md = (double)m;
+        rc = launch(h, s, F_LINK_NUMBER, 12.0 * Md, Md, [&] {
+            return launch_link_assign(LK_ROOTS, a, m, h->lk_counts, s);
         });
-        if (!rc) rc = launch(h, s, F_LINK_NUMBER, 4.0 * Nd, Nd, [&] {
+        if (!rc) rc = launch(h, s, F_LINK_NUMBER, 16.0 * Md, Md, [&] {
             return launch_link_resolve(a, nc, s);
         });
         if (!rc) rc = launch(h, s, F_LINK_NUMBER, 32.0 * nc, nc, [&] {
-            return launch_link_number(false, a, nc, h->lk_kcounts, s);
+            return launch_link_number(LK_KEPT, a, nc, h->lk_kcounts, s);
         });
         if (!rc) rc = launch(h, s, F_LINK_NUMBER, 32.0 * nc, nc, [&] {
-            return launch_link_assign(false, a, nc, h->lk_kcounts, s);
+            return launch_link_assign(LK_KEPT, a, nc, h->lk_kcounts, s);
         });
         if (rc) return rc;
         e = hipMemcpyAsync(&n_kept, h->lk_kcounts + nbc, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(h, e, "count of kept detections");
     }
-    rc = launch(h, s, F_LINK_LABEL, 8.0 * Nd, Nd, [&] { return launch_link_label(a, s); });
+    rc = launch(h, s, F_LINK_LABEL, 5.0 * Nd + 4.0 * m, Nd, [&] { return launch_link_label(a, s); });
     if (rc) return rc;
     if (boxes && cap > 0 && n_kept > 0) {
         if ((rc = grow(h, h->lk_out, h->lk_out_cap, (size_t)n_kept * 7, "link output boxes",
@@ -1995,7 +2018,7 @@ void sofia_sc_destroy(sofia_sc *h) {
         if (h->bst) (void)hipFree(h->bst);
         if (h->bst_host) (void)hipHostFree(h->bst_host);
         if (h->nn_sigma) (void)hipFree(h->nn_sigma);
-        void *lk[] = {h->lk_counts, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out,
+        void *lk[] = {h->lk_counts, h->lk_list, h->lk_box, h->lk_label, h->lk_kcounts, h->lk_out,
                       h->pm_acc, h->pm_sign, h->pm_vec, h->pm_state, h->mu_sum, h->mu_cnt,
                       h->mu_st, h->mu_hist, h->mu_cap, h->mu_sel};
         for (void *p : lk)

@@ -240,6 +240,8 @@ constexpr int kLinkMaxOffsets = 160;
 struct LinkArgs {
     const uint8_t *mask;
     int *L;
+    int *list;                   // [m]: the detected voxels' indices, in raster order
+    int64_t m;                   // detected voxels
     int *box;                    // [nc][8]: x0, x1, y0, y1, z0, z1, count, pad
     int *label_of;               // [nc]: label of each detection, 0 = dropped
     int64_t nx, ny, nz;
@@ -249,16 +251,21 @@ struct LinkArgs {
     int32_t delta[kLinkMaxOffsets];   // index difference of each offset
 };
 
-hipError_t launch_link_init(const uint8_t *mask, int *L, int64_t n, hipStream_t s);
+// Over the list of detected voxels (a.list, a.m entries).
+hipError_t launch_link_init(const LinkArgs &a, hipStream_t s);
 hipError_t launch_link_union(const LinkArgs &a, hipStream_t s);
-hipError_t launch_link_flatten(int *L, int64_t n, hipStream_t s);
+hipError_t launch_link_flatten(const LinkArgs &a, hipStream_t s);
 // Blocks of the count / assign steps over n items.
 int64_t link_scan_blocks(int64_t n);
-// Count flagged items per block (roots, or kept detections) and scan the
-// counts in place; counts[blocks] receives the total.
-hipError_t launch_link_number(bool roots, const LinkArgs &a, int64_t n, int *counts,
+// Items of the count / assign steps: the cube's voxels (detected ones go to
+// the list), the listed voxels (roots get their detection's number), or the
+// detections (kept ones get their label).
+enum LinkItems { LK_VOXELS = 0, LK_ROOTS = 1, LK_KEPT = 2 };
+// Count flagged items per block and scan the counts in place; counts[blocks]
+// receives the total.
+hipError_t launch_link_number(int items, const LinkArgs &a, int64_t n, int *counts,
                               hipStream_t s);
-hipError_t launch_link_assign(bool roots, const LinkArgs &a, int64_t n, const int *counts,
+hipError_t launch_link_assign(int items, const LinkArgs &a, int64_t n, const int *counts,
                               hipStream_t s);
 hipError_t launch_link_resolve(const LinkArgs &a, int64_t nc, hipStream_t s);
 hipError_t launch_link_label(const LinkArgs &a, hipStream_t s);

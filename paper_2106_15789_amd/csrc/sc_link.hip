@@ -8,20 +8,23 @@
 // detections are numbered 1, 2, ... in the raster order of their first voxel.
 //
 // Work split (the label cube itself is the union-find forest, int32 voxel
-// indices):
-//  * k_link_init: every detected voxel its own root, -1 elsewhere;
-//  * k_link_union: one thread per voxel unites a detected voxel with its
-//    detected friends at the forward half of the offsets (the other half is
-//    the friends' own forward half). Unions hook the larger root under the
+// indices). The mask is sparse, so after one pass over the cube the work
+// runs over a list of the detected voxels, in raster order, one per lane:
+//  * per-block counts, a scan and a block-local scan write the detected
+//    voxels' indices to the list; k_link_init makes every listed voxel its
+//    own root (the other voxels' links are never read);
+//  * k_link_union: one thread per listed voxel unites it with its detected
+//    friends at the forward half of the offsets (the other half is the
+//    friends' own forward half). Unions hook the larger root under the
 //    smaller one with a compare-and-swap, so every tree's root ends as the
 //    smallest index of its detection: the canonical label, independent of
 //    the order in which the threads ran;
-//  * k_link_flatten: every detected voxel points straight at its root;
-//  * per-block counts, one scan and a block-local scan number the roots in
-//    raster order; k_link_resolve then gives every voxel its detection's
-//    number and accumulates the bounding boxes with atomics;
-//  * the same count/scan/assign steps number the kept detections, and
-//    k_link_label writes the final labels.
+//  * k_link_flatten: every listed voxel points straight at its root;
+//  * the same count/scan/assign steps over the list number the roots in
+//    raster order; k_link_resolve then gives every listed voxel its
+//    detection's number and accumulates the bounding boxes with atomics;
+//  * the same steps number the kept detections, and k_link_label writes the
+//    final labels of the whole cube (reading links only where detected).
 // Forest links are read with agent-scope atomic loads: a CU's vector cache is
 // not coherent with the other CUs' writes.
 #include <limits.h>
@@ -103,11 +106,13 @@ __device__ int block_excl_scan(int v, int *buf, int *total) {
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_link_init(const uint8_t *__restrict__ mask,
-                                                   int *__restrict__ L, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        L[i] = mask[i] ? (int)i : -1;
+__global__ __launch_bounds__(256) void k_link_init(LinkArgs a) {
+    const int m = (int)a.m;
+    const int stride = (int)(gridDim.x * blockDim.x);
+    for (int t = (int)(blockIdx.x * blockDim.x + threadIdx.x); t < m; t += stride) {
+        const int i = a.list[t];
+        a.L[i] = i;
+    }
 }
 
 // Position of voxel i (the linker's cubes hold fewer than 2^31 voxels, so
@@ -121,10 +126,10 @@ __device__ __forceinline__ void pos_of(const LinkArgs &a, uint32_t i, int &x, in
 }
 
 __global__ __launch_bounds__(256) void k_link_union(LinkArgs a) {
-    const int n = (int)(a.nx * a.ny * a.nz);
+    const int m = (int)a.m;
     const int stride = (int)(gridDim.x * blockDim.x);
-    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
-        if (!a.mask[i]) continue;
+    for (int t = (int)(blockIdx.x * blockDim.x + threadIdx.x); t < m; t += stride) {
+        const int i = a.list[t];
         int x, y, z;
         pos_of(a, (uint32_t)i, x, y, z);
         for (int k = 0; k < a.n_off; ++k) {
@@ -141,22 +146,27 @@ __global__ __launch_bounds__(256) void k_link_union(LinkArgs a) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_link_flatten(int *L, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (ld_link(L, (int)i) < 0) continue;
-        const int r = find_root(L, (int)i);
+__global__ __launch_bounds__(256) void k_link_flatten(LinkArgs a) {
+    const int m = (int)a.m;
+    const int stride = (int)(gridDim.x * blockDim.x);
+    for (int t = (int)(blockIdx.x * blockDim.x + threadIdx.x); t < m; t += stride) {
+        const int i = a.list[t];
+        const int r = find_root(a.L, i);
         // the root is the smallest index on the path: after every thread's
         // minimum, each detected voxel links straight to its root
-        atomicMin(L + i, r);
+        atomicMin(a.L + i, r);
     }
 }
 
-// Flags of the count / assign steps: item i is a root (ROOTS) or a kept
-// detection (otherwise).
-template <bool ROOTS>
+// Flags of the count / assign steps: voxel i is detected (LK_VOXELS), listed
+// voxel i is a root (LK_ROOTS), detection i is kept (LK_KEPT).
+template <int ITEMS>
 __device__ __forceinline__ bool link_flag(const LinkArgs &a, int64_t i) {
-    if (ROOTS) return a.L[i] == (int)i;
+    if (ITEMS == LK_VOXELS) return a.mask[i] != 0;
+    if (ITEMS == LK_ROOTS) {
+        const int v = a.list[i];
+        return a.L[v] == v;
+    }
     const int *b = a.box + 8 * i;
     const int ex = b[1] - b[0] + 1, ey = b[3] - b[2] + 1, ez = b[5] - b[4] + 1;
     bool keep = ex >= a.min_xy && ey >= a.min_xy && ez >= a.min_z;
@@ -165,7 +175,7 @@ __device__ __forceinline__ bool link_flag(const LinkArgs &a, int64_t i) {
     return keep;
 }
 
-template <bool ROOTS>
+template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_link_count(LinkArgs a, int64_t n,
                                                              int *counts) {
     __shared__ int buf[kScanThreads / 64 + 1];
@@ -173,7 +183,7 @@ __global__ __launch_bounds__(kScanThreads) void k_link_count(LinkArgs a, int64_t
     int c = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (i0 + k < n && link_flag<ROOTS>(a, i0 + k)) ++c;
+        if (i0 + k < n && link_flag<ITEMS>(a, i0 + k)) ++c;
     int total;
     block_excl_scan(c, buf, &total);
     if (threadIdx.x == 0) counts[blockIdx.x] = total;
@@ -197,9 +207,10 @@ __global__ __launch_bounds__(kScanThreads) void k_link_scan(int *counts, int64_t
     if (threadIdx.x == 0) counts[nb] = total;
 }
 
-// Roots: the detection number (raster order) into the root's own link,
-// encoded as -2 - number. Kept detections: label_of[c] = 1 + rank or 0.
-template <bool ROOTS>
+// Detected voxels: list[rank] = index. Roots: the detection number (raster
+// order) into the root's own link, encoded as -2 - number. Kept detections:
+// label_of[c] = 1 + rank or 0.
+template <int ITEMS>
 __global__ __launch_bounds__(kScanThreads) void k_link_assign(LinkArgs a, int64_t n,
                                                               const int *offsets) {
     __shared__ int buf[kScanThreads / 64 + 1];
@@ -208,7 +219,7 @@ __global__ __launch_bounds__(kScanThreads) void k_link_assign(LinkArgs a, int64_
     int c = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        f[k] = i0 + k < n && link_flag<ROOTS>(a, i0 + k);
+        f[k] = i0 + k < n && link_flag<ITEMS>(a, i0 + k);
         c += f[k] ? 1 : 0;
     }
     int total;
@@ -216,8 +227,10 @@ __global__ __launch_bounds__(kScanThreads) void k_link_assign(LinkArgs a, int64_
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (i0 + k >= n) break;
-        if (ROOTS) {
-            if (f[k]) a.L[i0 + k] = -2 - rank++;
+        if (ITEMS == LK_VOXELS) {
+            if (f[k]) a.list[rank++] = (int)(i0 + k);
+        } else if (ITEMS == LK_ROOTS) {
+            if (f[k]) a.L[a.list[i0 + k]] = -2 - rank++;
         } else {
             a.label_of[i0 + k] = f[k] ? 1 + rank++ : 0;
         }
@@ -244,27 +257,26 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
-// Every detected voxel: its detection's number (from its root) and its share
+// Every listed voxel: its detection's number (from its root) and its share
 // of the detection's bounding box and voxel count. The lanes of a wave that
 // belong to one detection are reduced first, and one of them updates the
-// box: neighbouring voxels mostly share a detection. Waves step through the
-// cube together, so every lane takes part in the reductions.
+// box: consecutive listed voxels mostly share a detection. Waves step
+// through the list together, so every lane takes part in the reductions.
 __global__ __launch_bounds__(256) void k_link_resolve(LinkArgs a) {
-    const int n = (int)(a.nx * a.ny * a.nz);
+    const int m = (int)a.m;
     const int stride = (int)(gridDim.x * blockDim.x);
     const int lane = threadIdx.x & 63;
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    for (int ib = t - lane; ib < n; ib += stride) {
-        const int i = ib + lane;
+    for (int tb = t - lane; tb < m; tb += stride) {
+        const int tt = tb + lane;
         int c = -1, x = 0, y = 0, z = 0;
-        if (i < n) {
+        if (tt < m) {
+            const int i = a.list[tt];
             const int p = a.L[i];
-            if (p != -1) {
-                const int code = p >= 0 ? a.L[p] : p;   // a non-root points at its root
-                c = -2 - code;
-                if (p >= 0) a.L[i] = code;
-                pos_of(a, (uint32_t)i, x, y, z);
-            }
+            const int code = p >= 0 ? a.L[p] : p;   // a non-root points at its root
+            c = -2 - code;
+            if (p >= 0) a.L[i] = code;
+            pos_of(a, (uint32_t)i, x, y, z);
         }
         unsigned long long pending = __ballot(c >= 0);
         while (pending) {
@@ -291,7 +303,8 @@ __global__ __launch_bounds__(256) void k_link_label(LinkArgs a) {
     const int64_t n = a.nx * a.ny * a.nz;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int p = a.L[i];
+        // a detected voxel's link holds its detection's code (-2 - number)
+        const int p = a.mask[i] ? a.L[i] : 0;
         a.L[i] = p <= -2 ? a.label_of[-2 - p] : 0;
     }
 }
@@ -316,48 +329,50 @@ unsigned grid_of(int64_t n, int per) {
 }
 }  // namespace
 
-hipError_t launch_link_init(const uint8_t *mask, int *L, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_link_init, dim3(grid_of(n, 256)), dim3(256), 0, s, mask, L, n);
+hipError_t launch_link_init(const LinkArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_init, dim3(grid_of(a.m, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_link_union(const LinkArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_link_union, dim3(grid_of(a.nx * a.ny * a.nz, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_link_union, dim3(grid_of(a.m, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_link_flatten(int *L, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_link_flatten, dim3(grid_of(n, 256)), dim3(256), 0, s, L, n);
+hipError_t launch_link_flatten(const LinkArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_link_flatten, dim3(grid_of(a.m, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 int64_t link_scan_blocks(int64_t n) { return (n + kScanItems - 1) / kScanItems; }
 
-hipError_t launch_link_number(bool roots, const LinkArgs &a, int64_t n, int *counts,
+hipError_t launch_link_number(int items, const LinkArgs &a, int64_t n, int *counts,
                               hipStream_t s) {
     const int64_t nb = link_scan_blocks(n);
     if (nb < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (roots)
-        hipLaunchKernelGGL(k_link_count<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n,
-                           counts);
+    const dim3 g((unsigned)nb), b(kScanThreads);
+    if (items == LK_VOXELS)
+        hipLaunchKernelGGL(k_link_count<LK_VOXELS>, g, b, 0, s, a, n, counts);
+    else if (items == LK_ROOTS)
+        hipLaunchKernelGGL(k_link_count<LK_ROOTS>, g, b, 0, s, a, n, counts);
     else
-        hipLaunchKernelGGL(k_link_count<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a,
-                           n, counts);
+        hipLaunchKernelGGL(k_link_count<LK_KEPT>, g, b, 0, s, a, n, counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_link_scan, dim3(1), dim3(kScanThreads), 0, s, counts, nb);
     return hipGetLastError();
 }
 
-hipError_t launch_link_assign(bool roots, const LinkArgs &a, int64_t n, const int *counts,
+hipError_t launch_link_assign(int items, const LinkArgs &a, int64_t n, const int *counts,
                               hipStream_t s) {
     const int64_t nb = link_scan_blocks(n);
-    if (roots)
-        hipLaunchKernelGGL(k_link_assign<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a,
-                           n, counts);
+    const dim3 g((unsigned)nb), b(kScanThreads);
+    if (items == LK_VOXELS)
+        hipLaunchKernelGGL(k_link_assign<LK_VOXELS>, g, b, 0, s, a, n, counts);
+    else if (items == LK_ROOTS)
+        hipLaunchKernelGGL(k_link_assign<LK_ROOTS>, g, b, 0, s, a, n, counts);
     else
-        hipLaunchKernelGGL(k_link_assign<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a,
-                           n, counts);
+        hipLaunchKernelGGL(k_link_assign<LK_KEPT>, g, b, 0, s, a, n, counts);
     return hipGetLastError();
 }
 
@@ -365,8 +380,7 @@ hipError_t launch_link_resolve(const LinkArgs &a, int64_t nc, hipStream_t s) {
     hipLaunchKernelGGL(k_link_box_init, dim3(grid_of(nc, 256)), dim3(256), 0, s, a.box, nc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_link_resolve, dim3(grid_of(a.nx * a.ny * a.nz, 256)), dim3(256), 0, s,
-                       a);
+    hipLaunchKernelGGL(k_link_resolve, dim3(grid_of(a.m, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
