@@ -176,29 +176,33 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     // Per-voxel operation on the smoothed value s of plane j of the group
     // (output plane zo). Predicates are lane masks: blank_m marks blanked
     // voxels and lanes past the plane's end, dprev the plane's detections so
-    // far; zsel: the plane is one the noise is measured on (every plane
+    // far; zsel: all ones if the plane is one the noise is measured on (every plane
     // unless the noise is subsampled; the clip takes every plane).
-    auto consume = [&](int j, int zo, double s, uint64_t blank_m, uint64_t dprev, bool zsel) {
+    auto consume = [&](int j, int zo, double s, uint64_t blank_m, uint64_t dprev, uint64_t zsel) {
         const uint64_t ok_m = ~blank_m;
         if (OP == OP_STD) {
-            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            const uint64_t sel_m = zsel & ok_m & range_mask(s);
             acc.sum += lane_bit(sel_m) ? s * s : 0.0;
             acc.cnt += (unsigned long long)__popcll(sel_m);
         } else if (OP == OP_HIST1) {
-            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            const uint64_t sel_m = zsel & ok_m & range_mask(s);
             if (lane_bit(sel_m)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 atomicAdd(&hist[key >> kL1Shift], 1u);
             }
         } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
-            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            const uint64_t sel_m = zsel & ok_m & range_mask(s);
             const uint32_t key = __float_as_uint(fabsf((float)s));
+            const uint64_t below_m = wave_mask(key < klo);
             n_sel += (unsigned)__popcll(sel_m);
-            n_below += (unsigned)__popcll(sel_m & wave_mask(key < klo));
-            const uint64_t want_m = sel_m & wave_mask(key >= klo) & wave_mask(key <= khi);
+            n_below += (unsigned)__popcll(sel_m & below_m);
+            const uint64_t want_m = sel_m & ~below_m & wave_mask(key <= khi);
             // every lane writes: a capturing lane to its place in the list,
-            // the others to a slot of their own past the list's end
-            capw[lane_bit(want_m) ? fill + lanes_below(want_m) : kCapPerWave(G) + lane] = key;
+            // the others to a slot of their own past the list's end (the
+            // rank is taken in every lane, so no lane mask is switched)
+            int at = fill + lanes_below(want_m);
+            __asm__ volatile("" : "+v"(at));
+            capw[lane_bit(want_m) ? at : kCapPerWave(G) + lane] = key;
             fill += __popcll(want_m);
             if (SELCLIP) {
                 // clip now unless |s| lies in (thr_lo, thr_hi], where the
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
                 }
             }
         } else if (OP == OP_HIST2) {
-            const uint64_t sel_m = zsel ? ok_m & range_mask(s) : 0ull;
+            const uint64_t sel_m = zsel & ok_m & range_mask(s);
             if (lane_bit(sel_m)) {
                 const uint32_t key = __float_as_uint(fabsf((float)s));
                 const uint32_t k1 = key >> kL1Shift;
@@ -348,7 +352,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             const int zi = zb + j;
             if (zi >= ze) break;
             const int zo = zo0 + j;
-            const bool zsel = (zbits >> j) & 1u;
+            const uint64_t zsel = (zbits >> j) & 1u ? ~0ull : 0ull;
             if (!SPEC) {
                 const float xv = in_value(g, j);
                 const uint64_t dprev = lane_word(g.dw, j);
@@ -491,17 +495,17 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         for (int i = tid; i < kL1Bins; i += B)
             if (hist[i]) atomicAdd(&a.hist1[i], (unsigned long long)hist[i]);
     } else if (OP == OP_SELECT || OP == OP_SELCLIP) {
-        __shared__ unsigned long long rc[2][B];
-        rc[0][tid] = lane == 0 ? n_sel : 0u;   // wave totals
-        rc[1][tid] = lane == 0 ? n_below : 0u;
-        __syncthreads();
-        for (int off = B / 2; off > 0; off >>= 1) {
-            if (tid < off) { rc[0][tid] += rc[0][tid + off]; rc[1][tid] += rc[1][tid + off]; }
-            __syncthreads();
+        __shared__ unsigned long long rc[2][B / 64];
+        if (lane == 0) {   // wave totals
+            rc[0][wave] = n_sel;
+            rc[1][wave] = n_below;
         }
+        __syncthreads();
         if (tid == 0) {   // per-block partials, summed by the finalize kernel
-            a.sel_part[2 * blockIdx.x] = rc[0][0];
-            a.sel_part[2 * blockIdx.x + 1] = rc[1][0];
+            unsigned long long ns = 0, nb = 0;
+            for (int v = 0; v < B / 64; ++v) { ns += rc[0][v]; nb += rc[1][v]; }
+            a.sel_part[2 * blockIdx.x] = ns;
+            a.sel_part[2 * blockIdx.x + 1] = nb;
         }
     } else if (OP == OP_HIST2) {
         __syncthreads();

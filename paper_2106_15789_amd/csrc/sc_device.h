@@ -60,9 +60,17 @@ __device__ __forceinline__ uint64_t lane_word(uint64_t v, int j) {
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
     return ((uint64_t)hi << 32) | lo;
 }
-// v with lane j (a compile-time index) replaced by the wave-uniform w.
+// The hardware's lane write (v_writelane_b32): lane `lane` of `old` set to
+// the wave-uniform `val`, every other lane unchanged. HIP has no builtin for
+// it, so the LLVM intrinsic is named directly.
+extern "C" __device__ int sc_writelane_i32(int val, int lane, int old)
+    __asm("llvm.amdgcn.writelane.i32");
+// v with lane j (a wave-uniform index) replaced by the wave-uniform w.
 __device__ __forceinline__ uint64_t with_lane_word(uint64_t v, int j, uint64_t w) {
-    return lane_bit(1ull << j) ? w : v;
+    const uint32_t lo = (uint32_t)sc_writelane_i32((int)(uint32_t)w, j, (int)(uint32_t)v);
+    const uint32_t hi =
+        (uint32_t)sc_writelane_i32((int)(uint32_t)(w >> 32), j, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 // Number of lanes below this one whose bit is set in the mask m.
 __device__ __forceinline__ int lanes_below(uint64_t m) {

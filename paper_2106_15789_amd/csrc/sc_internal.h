@@ -78,7 +78,7 @@ constexpr int kCapStride(int group) { return kCapPerWave(group) + 64; }
 // adds well under one; a group that overflows the buffer sends the pass to
 // the full clip.
 constexpr int kAmbFlushAt = 64;
-constexpr int kAmbPerWave = 192;
+constexpr int kAmbPerWave = 160;
 
 enum Src { SRC_X = 0, SRC_P = 1 };
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
