@@ -43,8 +43,11 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
     const int tid = threadIdx.x;
     if ((OP == OP_HIST1 || OP == OP_HIST2) && a.skip_if_captured && a.st->use_capture) return;
     if (OP == OP_CLIP && a.skip_if_fused && a.st->fused_ok) return;
-    const int cb = (int)(blockIdx.x % (unsigned)a.ncb);
-    const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
+    // Tile of this block, XCD-aware: neighbouring column blocks share the
+    // cache lines of the bit planes, so they run on the same XCD (one L2).
+    const int tile = (int)xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+    const int cb = tile % a.ncb;
+    const int zc = tile / a.ncb;
     const int64_t ncol = a.ncol;
     // A sampling pass (cb_stride > 1) gives each wave its own 64-column
     // segment, every cb_stride-th of the plane, so that the sample spreads
@@ -489,7 +492,7 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
             if (tid < off) { rs[tid] += rs[tid + off]; rc[tid] += rc[tid + off]; }
             __syncthreads();
         }
-        if (tid == 0) { a.part_sum[blockIdx.x] = rs[0]; a.part_cnt[blockIdx.x] = rc[0]; }
+        if (tid == 0) { a.part_sum[tile] = rs[0]; a.part_cnt[tile] = rc[0]; }
     } else if (OP == OP_HIST1) {
         __syncthreads();
         for (int i = tid; i < kL1Bins; i += B)
@@ -504,8 +507,8 @@ __global__ __launch_bounds__(kColThreads) void k_column(ColArgs a) {
         if (tid == 0) {   // per-block partials, summed by the finalize kernel
             unsigned long long ns = 0, nb = 0;
             for (int v = 0; v < B / 64; ++v) { ns += rc[0][v]; nb += rc[1][v]; }
-            a.sel_part[2 * blockIdx.x] = ns;
-            a.sel_part[2 * blockIdx.x + 1] = nb;
+            a.sel_part[2 * tile] = ns;
+            a.sel_part[2 * tile + 1] = nb;
         }
     } else if (OP == OP_HIST2) {
         __syncthreads();

@@ -26,8 +26,10 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
     extern __shared__ float mring[];
     constexpr int B = kColThreads;
     const int tid = threadIdx.x;
-    const int cb = (int)(blockIdx.x % (unsigned)a.ncb);
-    const int zc = (int)(blockIdx.x / (unsigned)a.ncb);
+    // XCD-aware tile order, as in the column kernel
+    const int tile = (int)xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+    const int cb = tile % a.ncb;
+    const int zc = tile / a.ncb;
     const int64_t ncol = a.ncol;
     const int64_t col0 = (int64_t)cb * B;
     const bool active = col0 + tid < ncol;
@@ -220,8 +222,8 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
                 __syncthreads();
             }
             if (tid == 0) {
-                a.sel_part[i][2 * blockIdx.x] = rc2[0][0];
-                a.sel_part[i][2 * blockIdx.x + 1] = rc2[1][0];
+                a.sel_part[i][2 * tile] = rc2[0][0];
+                a.sel_part[i][2 * tile + 1] = rc2[1][0];
             }
             __syncthreads();
         }
@@ -241,8 +243,8 @@ __global__ __launch_bounds__(kColThreads) void k_multi(MultiArgs a) {
                 __syncthreads();
             }
             if (tid == 0) {
-                a.part_sum[(int64_t)i * a.nparts + blockIdx.x] = rs[0];
-                a.part_cnt[(int64_t)i * a.nparts + blockIdx.x] = rc[0];
+                a.part_sum[(int64_t)i * a.nparts + tile] = rs[0];
+                a.part_cnt[(int64_t)i * a.nparts + tile] = rc[0];
             }
             __syncthreads();
         }
