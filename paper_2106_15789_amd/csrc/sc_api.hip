@@ -349,8 +349,13 @@ int check_modes(sofia_sc *h, double t, int32_t mode, int32_t range) {
     return SOFIA_SC_OK;
 }
 
-// Column-kernel grid: 256 columns per block; z is split only as far as
-// needed to give the chip several waves of blocks.
+// Column-kernel grid: 256 columns per block; z is split as far as needed to
+// give the chip several waves of blocks, and so that no block streams more
+// than kColMaxZChunk planes: the four blocks that share a cache line of the
+// bit planes start together but drift apart in z as they stream, and over
+// thousands of planes the line leaves their L2 before the last of them reads
+// it.
+constexpr int64_t kColMaxZChunk = 1024;
 struct ColGrid {
     int ncb, nzc, zchunk;
     int blocks() const { return ncb * nzc; }
@@ -362,6 +367,7 @@ ColGrid col_grid(int64_t ncol, int64_t nz, const Shapes &sh) {
     int64_t nzc = (sh.col_blocks + g.ncb - 1) / g.ncb;
     const int64_t max_nzc = std::max<int64_t>(1, nz / std::max(1, sh.col_min_planes));
     nzc = std::max<int64_t>(1, std::min(nzc, max_nzc));
+    nzc = std::max<int64_t>(nzc, (nz + kColMaxZChunk - 1) / kColMaxZChunk);
     g.zchunk = (int)((nz + nzc - 1) / nzc);
     g.nzc = (int)((nz + g.zchunk - 1) / g.zchunk);
     return g;
