@@ -220,7 +220,8 @@ typedef struct {
                                by side: 4, 8 or 16 (default 8) */
     int32_t col_blocks;     /* column passes: blocks a launch aims at, by
                                splitting z into chunks: 3072, 6144 or 12288
-                               (default 6144) */
+                               (default 6144); whatever it is, no chunk is
+                               longer than 1024 planes */
     int32_t strip_rows;     /* spatial pass: most rows per chunk of a strip:
                                64, 128 or 256 (default 256) */
     int32_t strip_waves;    /* spatial pass: most adjacent 128-column strips
